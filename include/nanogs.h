@@ -1,0 +1,235 @@
+/*
+ * nanogs.h -- C ABI of the MI355X (gfx950) splat-simplification library.
+ *
+ * The library implements the data-parallel hot path of NanoGS (Xiong et al.,
+ * "NanoGS: Training-Free Gaussian Splat Simplification", arXiv 2603.16103):
+ * rounds of  kNN merge graph (Sec. 3.1)  ->  merge cost per edge (Sec. 3.2,
+ * Eq. cost, Appendix A)  ->  greedy disjoint low-cost pairs (Sec. 3.4,
+ * Algorithm 1)  ->  mass-preserved moment-matching merge and compaction
+ * (Sec. 3.3), repeated until a target splat count (Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller unless a
+ *    comment says "host".  The library never frees caller memory and never
+ *    keeps a pointer after a call returns.
+ *  - Arrays are row-major per splat: pos[n][3], sh[n][48], ...; float arrays
+ *    must be 4-byte aligned, and ws / sh / rot / quat must be 16-byte aligned.
+ *  - Every call returns a nanogs_status; on failure nanogs_last_error()
+ *    (thread-local) describes it.  Argument checks happen before any launch,
+ *    so a failed check leaves every output untouched.
+ *  - Stage calls are asynchronous on `stream` (0 = the null stream).
+ *    nanogs_simplify synchronises `stream` and returns a host count.
+ *  - Workspace: each call that needs scratch takes (ws, ws_bytes); the size
+ *    comes from the matching *_workspace_bytes query.  A smaller workspace
+ *    gives NANOGS_EWORKSPACE.  Workspace contents are not preserved.
+ *  - Index limits: n * k < 2^31.
+ */
+#ifndef NANOGS_H
+#define NANOGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NANOGS_OK = 0,
+  NANOGS_EINVAL = 1,      /* bad argument (null pointer, size or alignment) */
+  NANOGS_EWORKSPACE = 2,  /* workspace smaller than the size query asked for */
+  NANOGS_ENONFINITE = 3,  /* an input value is NaN or infinite */
+  NANOGS_EHIP = 4,        /* a HIP runtime call failed */
+  NANOGS_ENOTREADY = 5    /* the library found no usable HIP device */
+} nanogs_status;
+
+#define NANOGS_SH_COEFFS 48   /* degree-3 spherical harmonics per splat */
+#define NANOGS_MAX_K 32       /* largest supported kNN size */
+#define NANOGS_MAX_S 16       /* largest supported Monte Carlo draw count */
+#define NANOGS_MAX_ROUNDS 64  /* per-round statistics kept in nanogs_stats */
+
+/* Stored 3DGS form: what a trained splat PLY holds (Sec. 1, Algorithm 1
+ * input/output).  pos[n][3] centre; log_scale[n][3] per-axis log standard
+ * deviation; rot[n][4] quaternion (w,x,y,z), not necessarily unit; opacity[n]
+ * logit; sh[n][48] f_dc_0..2 then f_rest_0..44. */
+typedef struct {
+  float* pos;
+  float* log_scale;
+  float* rot;
+  float* opacity;
+  float* sh;
+} nanogs_gaussians;
+
+/* Activated form used by the stage calls: mu[n][3] centre; scale[n][3]
+ * standard deviations (> 0); quat[n][4] unit quaternion (w,x,y,z);
+ * alpha[n] opacity in [0,1]; sh[n][48] appearance feature f (Sec. 3.2);
+ * origin[n] provenance (nullable). */
+typedef struct {
+  float* mu;
+  float* scale;
+  float* quat;
+  float* alpha;
+  float* sh;
+  int32_t* origin;
+} nanogs_splats;
+
+#define NANOGS_PREC_FP32 0  /* FP32 costs, FP64 for ill-conditioned pairs */
+#define NANOGS_PREC_FP64 1  /* every edge cost in FP64 */
+
+typedef struct {
+  int32_t S;          /* Monte Carlo draws per edge, 1..NANOGS_MAX_S (1) */
+  int32_t app_dims;   /* SH coefficients in the appearance term, 1..48 (48) */
+  int32_t precision;  /* NANOGS_PREC_FP32 (default) or NANOGS_PREC_FP64 */
+  float fb_ratio;     /* FP64 fallback when a Cholesky factor's smallest
+                         diagonal is below fb_ratio times its largest
+                         (1/256) */
+  uint64_t seed;      /* key of the shared Monte Carlo draws (0) */
+  int32_t max_rounds; /* stop after this many passes; 0 = no limit */
+  int32_t* d_trace;   /* nullable device [n][2]: provenance pairs merged, in
+                         pass order, each row (smaller origin, larger) */
+  int32_t* d_origin;  /* nullable device [n]: provenance of each output
+                         splat (smallest input index it absorbed) */
+} nanogs_options;
+
+typedef struct {
+  int32_t rounds;                          /* passes that merged >= 1 pair */
+  int32_t early_exit;                      /* 1 if a pass found no pair */
+  int64_t n_out;
+  int64_t n_per_round[NANOGS_MAX_ROUNDS];  /* N at the start of pass r */
+  int64_t edges_per_round[NANOGS_MAX_ROUNDS];
+  int64_t pairs_per_round[NANOGS_MAX_ROUNDS];
+  int64_t fallback_per_round[NANOGS_MAX_ROUNDS]; /* edges costed in FP64 */
+  int32_t ld_iters_per_round[NANOGS_MAX_ROUNDS]; /* matching iterations */
+} nanogs_stats;
+
+/* Fills *opt with the defaults listed above. */
+void nanogs_default_options(nanogs_options* opt);
+
+/* Thread-local description of the last failure ("" after success). */
+const char* nanogs_last_error(void);
+
+/* The shared Monte Carlo draws of pass `round` (Appendix A: common random
+ * numbers across candidate pairs; the paper names no generator): S rows of
+ * (u, z0, z1, z2), u ~ U[0,1) and z ~ N(0, I3), written to HOST out[S][4].
+ * Definition: h = SplitMix64 output for a given state;
+ * U(s,c) = (h(h(h(seed) ^ round) ^ (8s+c)) >> 11) * 2^-53;
+ * u = U(s,0); (z0, z1) = Box-Muller on (U(s,1), U(s,2));
+ * z2 = cosine branch of Box-Muller on (U(s,3), U(s,4)), with ln(1-U);
+ * computed in double and rounded to float.  Host-only, no device work. */
+void nanogs_crn(uint64_t seed, int32_t round, int32_t S, float* out);
+
+/* ---- whole loop (Algorithm 1, without the opacity pre-filter) ---------- */
+
+size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k,
+                                       const nanogs_options* opt);
+
+/* Simplify n splats to target_n (Algorithm 1: while N > N_tgt: kNN graph
+ * with k_eff = min(max(1,k), N-1), union edges, edge costs, at most
+ * P = N - N_tgt greedy disjoint pairs, stop if none, merge).  in and out are
+ * stored-form arrays of capacity n (they may not alias); on success
+ * out[0, *n_out) holds the result in the standard 3DGS form with alpha
+ * clipped to [0,1].  Output order: splats keep the relative order of the
+ * lowest input index they absorbed.  target_n >= n (or n <= 1) copies the
+ * input through activation and back.  opt and stats are nullable (host).
+ * Errors: EINVAL (n < 1, target_n < 1, k < 1 or > NANOGS_MAX_K, n*k too
+ * large, bad options), EWORKSPACE, ENONFINITE (checked before any merge),
+ * EHIP.  Synchronises `stream`. */
+nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n,
+                              int64_t target_n, int32_t k,
+                              const nanogs_options* opt, nanogs_gaussians* out,
+                              int64_t* n_out, nanogs_stats* stats, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* ---- boundary conversions ---------------------------------------------- */
+
+/* Stored -> activated: scale = exp(log_scale), alpha = sigmoid(opacity),
+ * quat = rot/|rot| (zero -> identity); mu and sh copied.  Computed in double,
+ * rounded to float.  If d_nonfinite (device int32, nullable) is non-null, a
+ * non-finite input value sets it to 1 (it is never cleared). */
+nanogs_status nanogs_activate(const nanogs_gaussians* g, int64_t n,
+                              nanogs_splats* s, int32_t* d_nonfinite,
+                              hipStream_t stream);
+
+/* Activated -> stored: log_scale = log(scale), opacity =
+ * logit(clamp(alpha, 2^-24, 1-2^-24)) (alpha clipped to [0,1] first, the
+ * final step of Algorithm 1), rot = quat with w >= 0; mu and sh copied. */
+nanogs_status nanogs_deactivate(const nanogs_splats* s, int64_t n,
+                                nanogs_gaussians* g, hipStream_t stream);
+
+/* ---- stage 1: kNN merge graph (Sec. 3.1) -------------------------------- */
+
+size_t nanogs_knn_workspace_bytes(int64_t n, int32_t k);
+
+/* Directed k nearest neighbours of every centre: nbr[i][t] for
+ * t < k_eff = min(k, n-1) is the t-th element of {j != i} ordered by the key
+ * (d2, j), d2 = ((dx*dx + dy*dy) + dz*dz) in double from the float centres,
+ * no fused multiply-add; entries t >= k_eff are -1.  Exact (not
+ * approximate).  mu[n][3] float, nbr[n][k] int32. */
+nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Undirected union of the lists (Algorithm 1 UndirectedUnionEdges): every
+ * unordered pair {i,j} with j in nbr(i) or i in nbr(j) exactly once, as
+ * ei[e] < ej[e].  Order: by emitting row i, then by slot t, where row i emits
+ * j = nbr[i][t] unless i > j and i is also in nbr(j).  ei/ej capacity n*k;
+ * the edge count goes to the device int64 *d_m.  Entries < 0 are skipped. */
+size_t nanogs_edges_workspace_bytes(int64_t n, int32_t k);
+nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k,
+                           int32_t* ei, int32_t* ej, int64_t* d_m, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* ---- stage 2: merge cost (Eq. cost = D_geo + D_app) --------------------- */
+
+/* cost[e] = D_geo + D_app of edge (ei[e], ej[e]) over the activated splats:
+ * D_geo is the Monte Carlo KL estimate of Appendix A with the S shared draws
+ * crn (HOST [S][4], see nanogs_crn): the draw picks splat ei[e] when
+ * u < pi = w_i / (w_i + w_j), the weight taken in float as
+ * ((alpha*s0)*s1)*s2, and samples x = mu_c + chol(Sigma_c) z; D_app =
+ * ||f_i - f_j||^2 over the first opt->app_dims SH coefficients.  dgeo
+ * (nullable) receives D_geo alone.  Accuracy (FP32 mode): |dC| <= 1e-4|C|
+ * + 1e-5 against a float64 evaluation except where u is within float
+ * rounding of pi.  opt nullable (defaults). */
+size_t nanogs_edge_cost_workspace_bytes(int64_t n, int64_t m);
+nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n,
+                               const int32_t* ei, const int32_t* ej, int64_t m,
+                               const float* crn, const nanogs_options* opt,
+                               float* cost, float* dgeo, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* ---- stage 3: greedy disjoint pairs (Algorithm 1 GreedyDisjointPairs) --- */
+
+/* partner[n] receives the result of scanning the edges in increasing
+ * (cost, min(i,j), max(i,j)) order and taking an edge whenever both ends are
+ * free, stopping after max_pairs: partner[i] = j and partner[j] = i for each
+ * taken pair, -1 elsewhere.  Edges with a non-finite cost are never taken;
+ * -0 equals +0.  Computed by iterated locally-dominant matching, which yields
+ * exactly that scan's result.  The pair count goes to device int64
+ * *d_npairs. */
+size_t nanogs_select_workspace_bytes(int64_t n, int64_t m);
+nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej,
+                            const float* cost, int64_t m, int64_t n,
+                            int64_t max_pairs, int32_t* partner,
+                            int64_t* d_npairs, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* ---- stage 4: merge + compaction (Sec. 3.3, Algorithm 1 MergePairs) ---- */
+
+/* Mass-preserved moment matching of every pair in partner (Eq. vm_weights,
+ * vm_cov, vm_alpha): the merged splat takes the lower index's place, the
+ * higher index is removed, survivors keep their relative order; (scale,
+ * quat) of the merged covariance from its eigen-decomposition (eigenvalues
+ * decreasing, signs fixed so the largest component of the first two axes is
+ * positive, w >= 0).  Computed in double.  out must hold n splats and must
+ * not alias in; the new count goes to device int64 *d_nout.  origin, when
+ * both in and out give one, becomes the smaller origin of a pair. */
+size_t nanogs_merge_workspace_bytes(int64_t n);
+nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,
+                           const int32_t* partner, nanogs_splats* out,
+                           int64_t* d_nout, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NANOGS_H */

@@ -1,0 +1,638 @@
+// C ABI entry points: argument checks, workspace layout, and the round driver
+// of Algorithm 1 (kNN graph -> union edges -> edge costs -> greedy disjoint
+// pairs -> merge, until the target count or a pass without pairs).
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "../../include/nanogs.h"
+#include "internal.h"
+
+namespace ng {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+namespace {
+
+struct Work {
+  float4* cen;
+  int* lg;
+  float4* shp;
+  float* sh;
+  int* org;
+};
+
+Work take_work(Carver& c, long long n) {
+  Work w;
+  w.cen = c.take<float4>(n);
+  w.lg = c.take<int>(n);
+  w.shp = c.take<float4>(2 * n);
+  w.sh = c.take<float>(n * NG_SH);
+  w.org = c.take<int>(n);
+  return w;
+}
+
+struct Opts {
+  int S = 1;
+  int app_dims = NG_SH;
+  int precision = NANOGS_PREC_FP32;
+  float fb_ratio = 1.0f / 256.0f;
+  uint64_t seed = 0;
+  int max_rounds = 0;
+  int* d_trace = nullptr;
+  int* d_origin = nullptr;
+};
+
+nanogs_status read_opts(const nanogs_options* o, Opts* out) {
+  Opts r;
+  if (o) {
+    r.S = o->S;
+    r.app_dims = o->app_dims;
+    r.precision = o->precision;
+    r.fb_ratio = o->fb_ratio;
+    r.seed = o->seed;
+    r.max_rounds = o->max_rounds;
+    r.d_trace = o->d_trace;
+    r.d_origin = o->d_origin;
+  }
+  if (r.S < 1 || r.S > NANOGS_MAX_S) {
+    set_error("options.S must be in [1, 16]");
+    return NANOGS_EINVAL;
+  }
+  if (r.app_dims < 0 || r.app_dims > NG_SH) {
+    set_error("options.app_dims must be in [0, 48]");
+    return NANOGS_EINVAL;
+  }
+  if (r.precision != NANOGS_PREC_FP32 && r.precision != NANOGS_PREC_FP64) {
+    set_error("options.precision must be NANOGS_PREC_FP32 or NANOGS_PREC_FP64");
+    return NANOGS_EINVAL;
+  }
+  if (!(r.fb_ratio >= 0.0f && r.fb_ratio <= 1.0f)) {
+    set_error("options.fb_ratio must be in [0, 1]");
+    return NANOGS_EINVAL;
+  }
+  if (r.max_rounds < 0) {
+    set_error("options.max_rounds must be >= 0");
+    return NANOGS_EINVAL;
+  }
+  *out = r;
+  return NANOGS_OK;
+}
+
+CrnArgs make_crn(uint64_t seed, int round, int S) {
+  CrnArgs c;
+  std::memset(&c, 0, sizeof(c));
+  c.S = S;
+  crn_host(seed, round, S, &c.v[0][0]);
+  return c;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+nanogs_status check_ptr(const void* p, size_t align, const char* name) {
+  if (!p) {
+    set_error(std::string(name) + " is null");
+    return NANOGS_EINVAL;
+  }
+  if (!aligned(p, align)) {
+    set_error(std::string(name) + " is not " + std::to_string(align) + "-byte aligned");
+    return NANOGS_EINVAL;
+  }
+  return NANOGS_OK;
+}
+
+#define NG_CHECK(expr)                     \
+  do {                                     \
+    nanogs_status _s = (expr);             \
+    if (_s != NANOGS_OK) return _s;        \
+  } while (0)
+
+nanogs_status check_gaussians(const nanogs_gaussians* g, const char* name) {
+  if (!g) {
+    set_error(std::string(name) + " is null");
+    return NANOGS_EINVAL;
+  }
+  NG_CHECK(check_ptr(g->pos, 4, "pos"));
+  NG_CHECK(check_ptr(g->log_scale, 4, "log_scale"));
+  NG_CHECK(check_ptr(g->rot, 4, "rot"));
+  NG_CHECK(check_ptr(g->opacity, 4, "opacity"));
+  NG_CHECK(check_ptr(g->sh, 16, "sh"));
+  return NANOGS_OK;
+}
+
+nanogs_status check_splats(const nanogs_splats* s, const char* name) {
+  if (!s) {
+    set_error(std::string(name) + " is null");
+    return NANOGS_EINVAL;
+  }
+  NG_CHECK(check_ptr(s->mu, 4, "mu"));
+  NG_CHECK(check_ptr(s->scale, 4, "scale"));
+  NG_CHECK(check_ptr(s->quat, 4, "quat"));
+  NG_CHECK(check_ptr(s->alpha, 4, "alpha"));
+  NG_CHECK(check_ptr(s->sh, 16, "sh"));
+  return NANOGS_OK;
+}
+
+nanogs_status check_n(long long n, long long k) {
+  if (n < 0) {
+    set_error("n must be >= 0");
+    return NANOGS_EINVAL;
+  }
+  if (k < 1 || k > NANOGS_MAX_K) {
+    set_error("k must be in [1, 32]");
+    return NANOGS_EINVAL;
+  }
+  if (n * k >= (1ll << 31) - 1) {
+    set_error("n * k must be below 2^31");
+    return NANOGS_EINVAL;
+  }
+  return NANOGS_OK;
+}
+
+nanogs_status check_ws(void* ws, size_t have, size_t need) {
+  if (need == 0) return NANOGS_OK;
+  if (!ws || have < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes, got " +
+              std::to_string(have));
+    return NANOGS_EWORKSPACE;
+  }
+  if (!aligned(ws, 256)) {
+    set_error("workspace must be 256-byte aligned");
+    return NANOGS_EINVAL;
+  }
+  return NANOGS_OK;
+}
+
+template <class F>
+nanogs_status guarded(F&& f) {
+  try {
+    g_error.clear();
+    return f();
+  } catch (const HipError& e) {
+    set_error(e.msg);
+    return NANOGS_EHIP;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return NANOGS_EHIP;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// simplify: workspace layout
+// ---------------------------------------------------------------------------
+struct SimplifyWs {
+  Work w[2];
+  float4* pre;
+  int* nbr;
+  int* ea;
+  int* eb;
+  float* cost;
+  int* fb_list;
+  int* partner;
+  unsigned* keys;
+  int* perm;
+  int* counters;
+  long long* d_m;
+  void* temp;
+};
+
+size_t big_temp_bytes(long long n, int k) {
+  size_t t = sort_temp_bytes(n);
+  t = std::max(t, knn_tree_bytes(n));
+  t = std::max(t, edges_temp_bytes(n, k));
+  t = std::max(t, select_temp_bytes(n, n * k));
+  t = std::max(t, merge_temp_bytes(n));
+  return t + 4096;
+}
+
+SimplifyWs carve_simplify(void* base, long long n, int k, size_t* bytes_out = nullptr) {
+  Carver c(base);
+  SimplifyWs s;
+  s.w[0] = take_work(c, n);
+  s.w[1] = take_work(c, n);
+  s.pre = c.take<float4>(2 * n);
+  s.nbr = c.take<int>(n * k);
+  s.ea = c.take<int>(n * k);
+  s.eb = c.take<int>(n * k);
+  s.cost = c.take<float>(n * k);
+  s.fb_list = c.take<int>(n * k);
+  s.partner = c.take<int>(n);
+  s.keys = c.take<unsigned>(n);
+  s.perm = c.take<int>(n);
+  s.counters = c.take<int>(64);
+  s.d_m = c.take<long long>(8);
+  s.temp = base ? (char*)base + c.bytes() : nullptr;
+  if (bytes_out) *bytes_out = c.bytes();
+  return s;
+}
+
+size_t simplify_bytes(long long n, int k) {
+  if (n < 1) n = 1;
+  size_t b = 0;
+  carve_simplify(nullptr, n, k, &b);
+  return b + big_temp_bytes(n, k);
+}
+
+__global__ void k_iota(int* v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long target_n, int k,
+                           const Opts& o, nanogs_gaussians* out, int64_t* n_out,
+                           nanogs_stats* stats, void* ws, hipStream_t st) {
+  SimplifyWs W = carve_simplify(ws, n, k);
+  long long* host = pinned_host();
+  nanogs_stats local;
+  std::memset(&local, 0, sizeof(local));
+
+  // 1. spatial order of the input (Morton order of the centres)
+  launch_morton_keys(in->pos, nullptr, (int)n, W.keys, W.counters + 8, st);
+  k_iota<<<blocks_for(n, 256), 256, 0, st>>>(W.perm, (int)n);
+  NG_LAUNCH_CHECK();
+  sort_pairs_u32(W.keys, W.perm, n, 30, W.temp, st);
+
+  // 2. activation into working set 0, in that order
+  fill_i32(W.counters, 0, 1, st);
+  launch_activate_stored(in->pos, in->log_scale, in->rot, in->opacity, W.perm, (int)n,
+                         W.w[0].cen, W.w[0].lg, W.w[0].shp, W.w[0].org, W.counters, st);
+  launch_check_finite(in->sh, n * NG_SH, W.counters, st);
+  launch_copy_sh_rows(in->sh, W.perm, W.w[0].sh, nullptr, (int)n, st);
+  NG_HIP(hipMemcpyAsync(host, W.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+  NG_HIP(hipStreamSynchronize(st));
+  if (*(int*)host != 0) {
+    set_error("input contains a non-finite value");
+    return NANOGS_ENONFINITE;
+  }
+
+  // 3. passes
+  int cur = 0;
+  long long N = n;
+  long long traced = 0;
+  int r = 0;
+  while (N > target_n && (o.max_rounds == 0 || r < o.max_rounds)) {
+    const Work& a = W.w[cur];
+    const Work& b = W.w[cur ^ 1];
+    const int keff = (int)std::min<long long>(std::max(1, k), N - 1);
+    launch_precompute(a.shp, (int)N, W.pre, st);
+    knn_working(a.cen, (int)N, k, keff, W.nbr, W.temp, st);
+    launch_union_edges(W.nbr, a.lg, (int)N, k, W.ea, W.eb, W.d_m, W.temp, st);
+    NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st));
+    NG_HIP(hipStreamSynchronize(st));
+    const long long m = host[0];
+    const CrnArgs crn = make_crn(o.seed, r, o.S);
+    int* fb_count = W.counters + 1;
+    fill_i32(fb_count, 0, 1, st);
+    if (o.precision == NANOGS_PREC_FP64) {
+      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, nullptr, nullptr,
+                            (int)m, crn, W.cost, nullptr, st);
+    } else {
+      launch_edge_cost(a.cen, W.pre, a.sh, o.app_dims, W.ea, W.eb, (int)m, (int)N, crn,
+                       o.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, st);
+      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, W.fb_list,
+                            fb_count, (int)m, crn, W.cost, nullptr, st);
+    }
+    const long long P = N - target_n;
+    SelectResult sel =
+        select_pairs(W.ea, W.eb, W.cost, m, (int)N, a.lg, P, W.partner, W.temp, st, nullptr);
+    long long fb = m;
+    if (o.precision != NANOGS_PREC_FP64) {
+      NG_HIP(hipMemcpyAsync(host, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
+      NG_HIP(hipStreamSynchronize(st));
+      fb = *(int*)host;
+    }
+    if (r < NANOGS_MAX_ROUNDS) {
+      local.n_per_round[r] = N;
+      local.edges_per_round[r] = m;
+      local.pairs_per_round[r] = sel.pairs;
+      local.fallback_per_round[r] = fb;
+      local.ld_iters_per_round[r] = sel.iters;
+    }
+    if (sel.pairs == 0) {
+      local.early_exit = 1;
+      break;
+    }
+    int* trace = o.d_trace ? o.d_trace + 2 * traced : nullptr;
+    const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
+                                       b.lg, b.shp, b.sh, b.org, trace, W.temp, st, nullptr);
+    traced += sel.pairs;
+    N = nn;
+    cur ^= 1;
+    ++r;
+  }
+  local.rounds = r;
+
+  // 4. output in the caller's (logical) order
+  const Work& f = W.w[cur];
+  launch_deactivate_work(f.cen, f.lg, f.shp, f.org, (int)N, out->pos, out->log_scale, out->rot,
+                         out->opacity, o.d_origin, st);
+  launch_copy_sh_rows(f.sh, nullptr, out->sh, f.lg, (int)N, st);
+  NG_HIP(hipStreamSynchronize(st));
+  local.n_out = N;
+  *n_out = N;
+  if (stats) *stats = local;
+  return NANOGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stage workspaces
+// ---------------------------------------------------------------------------
+struct Packed {
+  float4* cen;
+  int* lg;
+  float4* shp;
+  int* org;
+};
+
+Packed take_packed(Carver& c, long long n) {
+  Packed p;
+  p.cen = c.take<float4>(n);
+  p.lg = c.take<int>(n);
+  p.shp = c.take<float4>(2 * n);
+  p.org = c.take<int>(n);
+  return p;
+}
+
+size_t cost_bytes(long long n, long long m) {
+  Carver c(nullptr);
+  take_packed(c, n);
+  c.take<float4>(2 * n);
+  c.take<int>(m);
+  c.take<int>(64);
+  return c.bytes();
+}
+
+size_t merge_ws_bytes(long long n) {
+  Carver c(nullptr);
+  take_packed(c, n);
+  take_packed(c, n);
+  return c.bytes() + merge_temp_bytes(n);
+}
+
+}  // namespace
+}  // namespace ng
+
+using namespace ng;
+
+extern "C" {
+
+void nanogs_default_options(nanogs_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->S = 1;
+  opt->app_dims = NANOGS_SH_COEFFS;
+  opt->precision = NANOGS_PREC_FP32;
+  opt->fb_ratio = 1.0f / 256.0f;
+  opt->seed = 0;
+  opt->max_rounds = 0;
+}
+
+const char* nanogs_last_error(void) { return g_error.c_str(); }
+
+void nanogs_crn(uint64_t seed, int32_t round, int32_t S, float* out) {
+  if (!out || S <= 0) return;
+  crn_host(seed, round, S, out);
+}
+
+size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k, const nanogs_options* opt) {
+  (void)opt;
+  if (n < 1 || k < 1 || k > NANOGS_MAX_K) return 0;
+  return simplify_bytes(n, k);
+}
+
+nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n, int64_t target_n, int32_t k,
+                              const nanogs_options* opt, nanogs_gaussians* out, int64_t* n_out,
+                              nanogs_stats* stats, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    if (n < 1) {
+      set_error("n must be >= 1");
+      return NANOGS_EINVAL;
+    }
+    if (target_n < 1) {
+      set_error("target_n must be >= 1");
+      return NANOGS_EINVAL;
+    }
+    if (!n_out) {
+      set_error("n_out is null");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_n(n, k));
+    NG_CHECK(check_gaussians(in, "in"));
+    NG_CHECK(check_gaussians(out, "out"));
+    if (in->pos == out->pos || in->sh == out->sh) {
+      set_error("in and out may not alias");
+      return NANOGS_EINVAL;
+    }
+    Opts o;
+    NG_CHECK(read_opts(opt, &o));
+    NG_CHECK(check_ws(ws, ws_bytes, simplify_bytes(n, k)));
+    return run_simplify(in, n, target_n, k, o, out, n_out, stats, ws, stream);
+  });
+}
+
+nanogs_status nanogs_activate(const nanogs_gaussians* g, int64_t n, nanogs_splats* s,
+                              int32_t* d_nonfinite, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    if (n == 0) return NANOGS_OK;
+    NG_CHECK(check_gaussians(g, "g"));
+    NG_CHECK(check_splats(s, "s"));
+    launch_activate_plain(g->pos, g->log_scale, g->rot, g->opacity, (int)n, s->mu, s->scale,
+                          s->quat, s->alpha, d_nonfinite, stream);
+    if (d_nonfinite) launch_check_finite(g->sh, n * NG_SH, d_nonfinite, stream);
+    if (s->sh != g->sh)
+      NG_HIP(hipMemcpyAsync(s->sh, g->sh, n * NG_SH * sizeof(float), hipMemcpyDeviceToDevice,
+                            stream));
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_deactivate(const nanogs_splats* s, int64_t n, nanogs_gaussians* g,
+                                hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    if (n == 0) return NANOGS_OK;
+    NG_CHECK(check_splats(s, "s"));
+    NG_CHECK(check_gaussians(g, "g"));
+    launch_deactivate_plain(s->mu, s->scale, s->quat, s->alpha, (int)n, g->pos, g->log_scale,
+                            g->rot, g->opacity, stream);
+    if (s->sh != g->sh)
+      NG_HIP(hipMemcpyAsync(g->sh, s->sh, n * NG_SH * sizeof(float), hipMemcpyDeviceToDevice,
+                            stream));
+    return NANOGS_OK;
+  });
+}
+
+size_t nanogs_knn_workspace_bytes(int64_t n, int32_t k) {
+  (void)k;
+  return knn_plain_bytes(n < 1 ? 1 : n);
+}
+
+nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, k));
+    if (n == 0) return NANOGS_OK;
+    NG_CHECK(check_ptr(mu, 4, "mu"));
+    NG_CHECK(check_ptr(nbr, 4, "nbr"));
+    NG_CHECK(check_ws(ws, ws_bytes, knn_plain_bytes(n)));
+    if (n == 1) {
+      fill_i32(nbr, -1, k, stream);
+      return NANOGS_OK;
+    }
+    const int keff = (int)std::min<long long>(k, n - 1);
+    knn_plain(mu, (int)n, k, keff, nbr, ws, stream);
+    return NANOGS_OK;
+  });
+}
+
+size_t nanogs_edges_workspace_bytes(int64_t n, int32_t k) {
+  if (n < 1) n = 1;
+  if (k < 1) k = 1;
+  return edges_temp_bytes(n, k);
+}
+
+nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k, int32_t* ei, int32_t* ej,
+                           int64_t* d_m, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, k));
+    NG_CHECK(check_ptr(d_m, 8, "d_m"));
+    if (n == 0) {
+      set_i64((long long*)d_m, 0, stream);
+      return NANOGS_OK;
+    }
+    NG_CHECK(check_ptr(nbr, 4, "nbr"));
+    NG_CHECK(check_ptr(ei, 4, "ei"));
+    NG_CHECK(check_ptr(ej, 4, "ej"));
+    NG_CHECK(check_ws(ws, ws_bytes, edges_temp_bytes(n, k)));
+    launch_union_edges(nbr, nullptr, (int)n, k, ei, ej, (long long*)d_m, ws, stream);
+    return NANOGS_OK;
+  });
+}
+
+size_t nanogs_edge_cost_workspace_bytes(int64_t n, int64_t m) {
+  return cost_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
+}
+
+nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t* ei,
+                               const int32_t* ej, int64_t m, const float* crn,
+                               const nanogs_options* opt, float* cost, float* dgeo, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    if (m < 0 || m >= (1ll << 31)) {
+      set_error("m must be in [0, 2^31)");
+      return NANOGS_EINVAL;
+    }
+    Opts o;
+    NG_CHECK(read_opts(opt, &o));
+    if (m == 0) return NANOGS_OK;
+    NG_CHECK(check_splats(s, "s"));
+    NG_CHECK(check_ptr(ei, 4, "ei"));
+    NG_CHECK(check_ptr(ej, 4, "ej"));
+    NG_CHECK(check_ptr(crn, 4, "crn"));
+    NG_CHECK(check_ptr(cost, 4, "cost"));
+    NG_CHECK(check_ws(ws, ws_bytes, cost_bytes(n, m)));
+    Carver c(ws);
+    Packed p = take_packed(c, n);
+    float4* pre = c.take<float4>(2 * n);
+    int* fb_list = c.take<int>(m);
+    int* counters = c.take<int>(64);
+    CrnArgs args;
+    std::memset(&args, 0, sizeof(args));
+    args.S = o.S;
+    std::memcpy(&args.v[0][0], crn, sizeof(float) * 4 * o.S);
+    launch_pack_splats(s->mu, s->scale, s->quat, s->alpha, s->origin, (int)n, p.cen, p.lg, p.shp,
+                       p.org, stream);
+    if (o.precision == NANOGS_PREC_FP64) {
+      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, nullptr, nullptr,
+                            (int)m, args, cost, dgeo, stream);
+    } else {
+      launch_precompute(p.shp, (int)n, pre, stream);
+      fill_i32(counters, 0, 1, stream);
+      launch_edge_cost(p.cen, pre, s->sh, o.app_dims, ei, ej, (int)m, (int)n, args, o.fb_ratio,
+                       cost, dgeo, fb_list, counters, stream);
+      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, fb_list, counters,
+                            (int)m, args, cost, dgeo, stream);
+    }
+    return NANOGS_OK;
+  });
+}
+
+size_t nanogs_select_workspace_bytes(int64_t n, int64_t m) {
+  return select_temp_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
+}
+
+nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* cost, int64_t m,
+                            int64_t n, int64_t max_pairs, int32_t* partner, int64_t* d_npairs,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    if (m < 0 || m >= (1ll << 31)) {
+      set_error("m must be in [0, 2^31)");
+      return NANOGS_EINVAL;
+    }
+    if (max_pairs < 0) {
+      set_error("max_pairs must be >= 0");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_ptr(d_npairs, 8, "d_npairs"));
+    if (n == 0) {
+      set_i64((long long*)d_npairs, 0, stream);
+      return NANOGS_OK;
+    }
+    NG_CHECK(check_ptr(partner, 4, "partner"));
+    if (m > 0) {
+      NG_CHECK(check_ptr(ei, 4, "ei"));
+      NG_CHECK(check_ptr(ej, 4, "ej"));
+      NG_CHECK(check_ptr(cost, 4, "cost"));
+    }
+    NG_CHECK(check_ws(ws, ws_bytes, select_temp_bytes(n, m < 1 ? 1 : m)));
+    select_pairs(ei, ej, cost, m, (int)n, nullptr, max_pairs, partner, ws, stream,
+                 (long long*)d_npairs);
+    return NANOGS_OK;
+  });
+}
+
+size_t nanogs_merge_workspace_bytes(int64_t n) { return merge_ws_bytes(n < 1 ? 1 : n); }
+
+nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* partner,
+                           nanogs_splats* out, int64_t* d_nout, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    NG_CHECK(check_ptr(d_nout, 8, "d_nout"));
+    if (n == 0) {
+      set_i64((long long*)d_nout, 0, stream);
+      return NANOGS_OK;
+    }
+    NG_CHECK(check_splats(in, "in"));
+    NG_CHECK(check_splats(out, "out"));
+    NG_CHECK(check_ptr(partner, 4, "partner"));
+    if (in->sh == out->sh || in->mu == out->mu) {
+      set_error("in and out may not alias");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_ws(ws, ws_bytes, merge_ws_bytes(n)));
+    Carver c(ws);
+    Packed a = take_packed(c, n);
+    Packed b = take_packed(c, n);
+    void* temp = (char*)ws + c.bytes();
+    launch_pack_splats(in->mu, in->scale, in->quat, in->alpha, in->origin, (int)n, a.cen, a.lg,
+                       a.shp, a.org, stream);
+    const long long nout = merge_compact(a.cen, nullptr, a.shp, in->sh, a.org, (int)n, partner,
+                                         b.cen, b.lg, b.shp, out->sh, b.org, nullptr, temp,
+                                         stream, nullptr);
+    launch_unpack_splats(b.cen, b.shp, b.org, (int)nout, out->mu, out->scale, out->quat,
+                         out->alpha, (in->origin && out->origin) ? out->origin : nullptr, stream);
+    set_i64((long long*)d_nout, nout, stream);
+    return NANOGS_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,340 @@
+// Merge cost of every candidate edge (Sec. 3.2): C = D_geo + D_app
+// (Eq. cost), D_geo = KL(p~_ij || q_m) estimated with the S shared draws of
+// Appendix A, D_app = ||f_i - f_j||^2.
+//
+// Arithmetic, per edge (i = first endpoint, j = second):
+//   pi = w_i / (w_i + w_j) (Eq. norm_mixture), d = mu_i - mu_j,
+//   merged covariance (Eq. vm_cov) = A + pi (1-pi) d d^T with
+//   A = pi Sigma_i + (1-pi) Sigma_j.
+// A is never formed: with Sigma = L L^T for each splat, A = G G^T for
+// G = [sqrt(pi) L_i | sqrt(1-pi) L_j] (3x6), and six Givens rotations reduce
+// G to its 3x3 lower-triangular LQ factor L_A, the Cholesky factor of A.  The
+// rank-one dispersion term enters in closed form: with e = L_A^-1 d and
+// c = pi (1-pi),
+//   log det Sigma_m = 2 log det L_A + log(1 + c |e|^2),
+//   y^T Sigma_m^-1 y for y = beta d + t, v = L_A^-1 t:
+//     |v - (v.e^)e^|^2 + (beta |e| + v.e^)^2 / (1 + c |e|^2).
+// A draw (u, z) picks splat i when u < pi, x = mu_c + L_c z, so
+//   log N_c(x) = -|z|^2/2 - log det L_c exactly, and the other two log
+// densities are triangular solves.  The -(3/2) log 2 pi constant cancels.
+// Working with the factors keeps the float error near eps * sqrt(cond)
+// instead of eps * cond; edges whose factors still look ill-conditioned
+// (a diagonal ratio below fb_ratio) or give a non-finite value are recomputed
+// in double from (s, q) by a second kernel.
+#include "internal.h"
+
+namespace ng {
+namespace {
+
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+template <typename T>
+NG_DEV V3<T> v3(T x, T y, T z) {
+  return {x, y, z};
+}
+template <typename T>
+NG_DEV T dot(const V3<T>& a, const V3<T>& b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
+// lower-triangular [[a00,0,0],[a10,a11,0],[a20,a21,a22]]
+template <typename T>
+struct Tri {
+  T a00, a10, a11, a20, a21, a22;
+};
+
+template <typename T>
+NG_DEV V3<T> tri_mul(const Tri<T>& L, const V3<T>& z) {
+  return {L.a00 * z.x, L.a10 * z.x + L.a11 * z.y, L.a20 * z.x + L.a21 * z.y + L.a22 * z.z};
+}
+
+template <typename T>
+NG_DEV V3<T> tri_solve(const Tri<T>& L, const V3<T>& y) {
+  V3<T> v;
+  v.x = y.x / L.a00;
+  v.y = (y.y - L.a10 * v.x) / L.a11;
+  v.z = (y.z - L.a20 * v.x - L.a21 * v.y) / L.a22;
+  return v;
+}
+
+template <typename T>
+NG_DEV T tri_ratio(const Tri<T>& L) {
+  T mn = fmin(fmin(L.a00, L.a11), L.a22);
+  T mx = fmax(fmax(L.a00, L.a11), L.a22);
+  return mn / mx;
+}
+
+// Rotates columns (ci, cj) of the 3 x NC row-major matrix g so that
+// g[row][cj] becomes zero and g[row][ci] >= 0.
+template <typename T, int NC>
+NG_DEV void givens(T (&g)[3][NC], int row, int ci, int cj) {
+  const T x = g[row][ci], y = g[row][cj];
+  const T r = sqrt(x * x + y * y);
+  if (!(r > T(0))) return;
+  const T c = x / r, s = y / r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= row) {
+      const T gi = g[i][ci], gj = g[i][cj];
+      g[i][ci] = c * gi + s * gj;
+      g[i][cj] = c * gj - s * gi;
+    }
+  }
+}
+
+// Cholesky factor of pa * La La^T + pb * Lb Lb^T, by LQ of [ra La | rb Lb].
+template <typename T>
+NG_DEV Tri<T> chol_of_mix(const Tri<T>& La, const Tri<T>& Lb, T ra, T rb) {
+  T g[3][6] = {{ra * La.a00, T(0), T(0), rb * Lb.a00, T(0), T(0)},
+               {ra * La.a10, ra * La.a11, T(0), rb * Lb.a10, rb * Lb.a11, T(0)},
+               {ra * La.a20, ra * La.a21, ra * La.a22, rb * Lb.a20, rb * Lb.a21, rb * Lb.a22}};
+  givens<T, 6>(g, 0, 0, 3);
+  givens<T, 6>(g, 1, 1, 3);
+  givens<T, 6>(g, 1, 1, 4);
+  givens<T, 6>(g, 2, 2, 3);
+  givens<T, 6>(g, 2, 2, 4);
+  givens<T, 6>(g, 2, 2, 5);
+  return {g[0][0], g[1][0], g[1][1], g[2][0], g[2][1], g[2][2]};
+}
+
+// Cholesky factor of R(q) diag(s^2) R(q)^T by LQ of M = R(q) diag(s).
+template <typename T>
+NG_DEV Tri<T> chol_from_scale_rot(T s0, T s1, T s2, T w, T x, T y, T z) {
+  const T nr = sqrt(w * w + x * x + y * y + z * z);
+  w /= nr;
+  x /= nr;
+  y /= nr;
+  z /= nr;
+  const T R00 = T(1) - T(2) * (y * y + z * z), R01 = T(2) * (x * y - w * z),
+          R02 = T(2) * (x * z + w * y);
+  const T R10 = T(2) * (x * y + w * z), R11 = T(1) - T(2) * (x * x + z * z),
+          R12 = T(2) * (y * z - w * x);
+  const T R20 = T(2) * (x * z - w * y), R21 = T(2) * (y * z + w * x),
+          R22 = T(1) - T(2) * (x * x + y * y);
+  T g[3][3] = {{R00 * s0, R01 * s1, R02 * s2},
+               {R10 * s0, R11 * s1, R12 * s2},
+               {R20 * s0, R21 * s1, R22 * s2}};
+  givens<T, 3>(g, 0, 0, 1);
+  givens<T, 3>(g, 0, 0, 2);
+  givens<T, 3>(g, 1, 1, 2);
+  const T l22 = g[2][2] < T(0) ? -g[2][2] : g[2][2];
+  return {g[0][0], g[1][0], g[1][1], g[2][0], g[2][1], l22};
+}
+
+// D_geo of one pair.  ratio receives the smallest diagonal ratio seen.
+template <typename T>
+NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const Tri<T>& Lb,
+                   T ldLa, T ldLb, T pa, T pb, float pa32, const CrnArgs& crn, T& ratio) {
+  const V3<T> d = {mua.x - mub.x, mua.y - mub.y, mua.z - mub.z};
+  const Tri<T> LA = chol_of_mix(La, Lb, sqrt(pa), sqrt(pb));
+  ratio = fmin(fmin(tri_ratio(La), tri_ratio(Lb)), tri_ratio(LA));
+  const V3<T> e = tri_solve(LA, d);
+  const T ee = dot(e, e);
+  const T c = pa * pb;
+  const T den = T(1) + c * ee;
+  const T half_logdet_m = log(LA.a00 * LA.a11 * LA.a22) + T(0.5) * log1p(c * ee);
+  const T lpa = log(pa), lpb = log(pb);
+  const T ne = sqrt(ee);
+  const T inv_ne = ne > T(0) ? T(1) / ne : T(0);
+  const V3<T> eh = {e.x * inv_ne, e.y * inv_ne, e.z * inv_ne};
+  T acc = T(0);
+  for (int s = 0; s < crn.S; ++s) {
+    const float u = crn.v[s][0];
+    const V3<T> zz = {(T)crn.v[s][1], (T)crn.v[s][2], (T)crn.v[s][3]};
+    const bool ca = u < pa32;
+    const Tri<T>& Lc = ca ? La : Lb;
+    const Tri<T>& Lo = ca ? Lb : La;
+    const T ldc = ca ? ldLa : ldLb;
+    const T ldo = ca ? ldLb : ldLa;
+    const V3<T> t = tri_mul(Lc, zz);
+    const T lnc = T(-0.5) * dot(zz, zz) - ldc;
+    const T sg = ca ? T(1) : T(-1);
+    const V3<T> y = {sg * d.x + t.x, sg * d.y + t.y, sg * d.z + t.z};
+    const V3<T> v = tri_solve(Lo, y);
+    const T lno = T(-0.5) * dot(v, v) - ldo;
+    const V3<T> w = tri_solve(LA, t);
+    const T beta = ca ? pb : -pa;
+    const T ww = dot(w, w);
+    const T we = dot(w, eh);
+    const T perp = fmax(ww - we * we, T(0));
+    const T par = beta * ne + we;
+    const T maha = perp + par * par / den;
+    const T lnm = T(-0.5) * maha - half_logdet_m;
+    const T la = lpa + (ca ? lnc : lno);
+    const T lb = lpb + (ca ? lno : lnc);
+    const T mx = fmax(la, lb), mn = fmin(la, lb);
+    const T lse = mx + log1p(exp(mn - mx));
+    acc += lse - lnm;
+  }
+  return acc / (T)crn.S;
+}
+
+NG_DEV float dapp_f32(const float* __restrict__ sh, long long a, long long b, int app_dims) {
+  const float* fa = sh + a * NG_SH;
+  const float* fb = sh + b * NG_SH;
+  float acc = 0.f;
+  const int n4 = app_dims >> 2;
+  for (int c = 0; c < n4; ++c) {
+    const float4 x = ((const float4*)fa)[c];
+    const float4 y = ((const float4*)fb)[c];
+    const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
+    acc += dx * dx + dy * dy + dz * dz + dw * dw;
+  }
+  for (int c = n4 * 4; c < app_dims; ++c) {
+    const float dc = fa[c] - fb[c];
+    acc += dc * dc;
+  }
+  return acc;
+}
+
+NG_DEV double dapp_f64(const float* __restrict__ sh, long long a, long long b, int app_dims) {
+  const float* fa = sh + a * NG_SH;
+  const float* fb = sh + b * NG_SH;
+  double acc = 0.0;
+  for (int c = 0; c < app_dims; ++c) {
+    const double dc = (double)fa[c] - (double)fb[c];
+    acc += dc * dc;
+  }
+  return acc;
+}
+
+NG_DEV float decision_weight(float wa, float wb) {
+  const float W = wa + wb;
+  return W > 0.f ? wa / W : 0.5f;
+}
+
+// ---- kernels ---------------------------------------------------------------
+__global__ void k_precompute(const float4* __restrict__ shp, int n, float4* __restrict__ pre) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float4 a = shp[2 * (long long)p];
+  const float4 q = shp[2 * (long long)p + 1];
+  const Tri<double> L = chol_from_scale_rot<double>(a.x, a.y, a.z, q.x, q.y, q.z, q.w);
+  const double ld = log((double)a.x) + log((double)a.y) + log((double)a.z);
+  const float wt = ((a.w * a.x) * a.y) * a.z;
+  pre[2 * (long long)p] = make_float4((float)L.a00, (float)L.a10, (float)L.a11, (float)L.a20);
+  pre[2 * (long long)p + 1] = make_float4((float)L.a21, (float)L.a22, (float)ld, wt);
+}
+
+NG_DEV void append_wave(bool flag, int value, int* list, int* count) {
+  const unsigned long long m = __ballot(flag);
+  if (m == 0) return;
+  const int lane = lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (flag) {
+    const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+    list[base + __popcll(below)] = value;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
+            const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
+            const int* __restrict__ eb, int m, int n, CrnArgs crn, float fb_ratio,
+            float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
+            int* __restrict__ fb_count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  bool live = e < m;
+  bool fb = false;
+  if (live) {
+    const int a = ea[e], b = eb[e];
+    if (a < 0 || a >= n || b < 0 || b >= n) {
+      cost[e] = __int_as_float(0x7fc00000);
+      if (dgeo_out) dgeo_out[e] = __int_as_float(0x7fc00000);
+      live = false;
+    }
+  }
+  if (live) {
+    const int a = ea[e], b = eb[e];
+    const float4 ca = cen[a], cb = cen[b];
+    const float4 pa0 = pre[2 * (long long)a], pa1 = pre[2 * (long long)a + 1];
+    const float4 pb0 = pre[2 * (long long)b], pb1 = pre[2 * (long long)b + 1];
+    const Tri<float> La = {pa0.x, pa0.y, pa0.z, pa0.w, pa1.x, pa1.y};
+    const Tri<float> Lb = {pb0.x, pb0.y, pb0.z, pb0.w, pb1.x, pb1.y};
+    const float pa = decision_weight(pa1.w, pb1.w);
+    const float W = pa1.w + pb1.w;
+    const float pb = W > 0.f ? pb1.w / W : 0.5f;
+    float ratio;
+    const float dg = dgeo_pair<float>(v3(ca.x, ca.y, ca.z), v3(cb.x, cb.y, cb.z), La, Lb, pa1.z,
+                                      pb1.z, pa, pb, pa, crn, ratio);
+    const float c = dg + dapp_f32(sh, a, b, app_dims);
+    fb = !(ratio >= fb_ratio) || !isfinite(c);
+    cost[e] = c;
+    if (dgeo_out) dgeo_out[e] = dg;
+  }
+  if (fb_list) append_wave(fb, e, fb_list, fb_count);
+}
+
+__global__ void __launch_bounds__(256)
+k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
+                 const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
+                 const int* __restrict__ eb, int n, const int* __restrict__ list,
+                 const int* __restrict__ d_count, int count_cap, CrnArgs crn,
+                 float* __restrict__ cost, float* __restrict__ dgeo_out) {
+  const int count = d_count ? min(*d_count, count_cap) : count_cap;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int e = list ? list[i] : i;
+    const int a = ea[e], b = eb[e];
+    if (a < 0 || a >= n || b < 0 || b >= n) {
+      cost[e] = __int_as_float(0x7fc00000);
+      if (dgeo_out) dgeo_out[e] = __int_as_float(0x7fc00000);
+      continue;
+    }
+    const float4 ca = cen[a], cb = cen[b];
+    const float4 sa = shp[2 * (long long)a], qa = shp[2 * (long long)a + 1];
+    const float4 sb = shp[2 * (long long)b], qb = shp[2 * (long long)b + 1];
+    const Tri<double> La = chol_from_scale_rot<double>(sa.x, sa.y, sa.z, qa.x, qa.y, qa.z, qa.w);
+    const Tri<double> Lb = chol_from_scale_rot<double>(sb.x, sb.y, sb.z, qb.x, qb.y, qb.z, qb.w);
+    const double lda = log((double)sa.x) + log((double)sa.y) + log((double)sa.z);
+    const double ldb = log((double)sb.x) + log((double)sb.y) + log((double)sb.z);
+    const float pa32 =
+        decision_weight(((sa.w * sa.x) * sa.y) * sa.z, ((sb.w * sb.x) * sb.y) * sb.z);
+    const double wa = (double)sa.w * (double)sa.x * (double)sa.y * (double)sa.z;
+    const double wb = (double)sb.w * (double)sb.x * (double)sb.y * (double)sb.z;
+    const double W = wa + wb;
+    const double pa = W > 0.0 ? wa / W : 0.5;
+    const double pb = W > 0.0 ? wb / W : 0.5;
+    double ratio;
+    const double dg = dgeo_pair<double>(v3<double>(ca.x, ca.y, ca.z), v3<double>(cb.x, cb.y, cb.z),
+                                        La, Lb, lda, ldb, pa, pb, pa32, crn, ratio);
+    cost[e] = (float)(dg + dapp_f64(sh, a, b, app_dims));
+    if (dgeo_out) dgeo_out[e] = (float)dg;
+  }
+}
+
+}  // namespace
+
+void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st) {
+  if (n <= 0) return;
+  k_precompute<<<blocks_for(n, 256), 256, 0, st>>>(shp, n, pre);
+  NG_LAUNCH_CHECK();
+}
+
+void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
+                      const int* ea, const int* eb, int m, int n, const CrnArgs& crn,
+                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
+                      hipStream_t st) {
+  if (m <= 0) return;
+  k_edge_cost<<<blocks_for(m, 256), 256, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n, crn,
+                                                  fb_ratio, cost, dgeo, fb_list, fb_count);
+  NG_LAUNCH_CHECK();
+}
+
+void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
+                           const int* ea, const int* eb, int n, const int* list,
+                           const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
+                           float* dgeo, hipStream_t st) {
+  if (count_cap <= 0) return;
+  unsigned b = blocks_for(count_cap, 256);
+  if (b > 2048) b = 2048;
+  k_edge_cost_fp64<<<b, 256, 0, st>>>(cen, shp, sh, app_dims, ea, eb, n, list, d_count, count_cap,
+                                      crn, cost, dgeo);
+  NG_LAUNCH_CHECK();
+}
+
+}  // namespace ng

@@ -1,0 +1,192 @@
+// Internal declarations shared by the library's translation units.
+//
+// Working layout (the library keeps its own copy of the splats, in an order
+// chosen for locality; every result is still defined on the caller's order,
+// called the logical order here):
+//   cen[p]        float4 (x, y, z, logical index as int bits)
+//   lg[p]         int32 logical index (same value as cen[p].w)
+//   shp[2p]       float4 (s0, s1, s2, alpha)      activated scales, opacity
+//   shp[2p+1]     float4 (qw, qx, qy, qz)         unit quaternion
+//   sh[p*48 ..]   float[48]                        appearance feature f
+//   org[p]        int32 provenance (smallest input index absorbed)
+// Per pass, per splat (cost kernel input):
+//   pre[2p]       float4 (L00, L10, L11, L20)     Cholesky factor of Sigma
+//   pre[2p+1]     float4 (L21, L22, log det L, w~) with w~ = ((a*s0)*s1)*s2
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#define NG_DEV __device__ __forceinline__
+#define NG_SH 48
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace ng {
+
+void set_error(const std::string& msg);
+
+struct HipError {
+  std::string msg;
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{std::string(what) + ": " + hipGetErrorString(e)};
+}
+#define NG_HIP(x) ::ng::hip_check((x), #x)
+#define NG_LAUNCH_CHECK() ::ng::hip_check(hipGetLastError(), "kernel launch")
+
+inline unsigned blocks_for(long long n, int bs) {
+  long long b = (n + bs - 1) / bs;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------------------------------
+// workspace carving (256-byte aligned sub-buffers)
+// ---------------------------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t bytes() const { return (off + 255) & ~(size_t)255; }
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+// Order-preserving map of a float to uint32 (-0 and +0 map to one key).
+NG_DEV uint32_t f2ord(float f) {
+  uint32_t u = __float_as_uint(f);
+  if (u == 0x80000000u) u = 0u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+NG_DEV int lane_id() { return (int)(threadIdx.x & 63); }
+
+// ---------------------------------------------------------------------------
+// host-side launchers (each defined in the .hip file named in the comment)
+// ---------------------------------------------------------------------------
+
+// util.hip -- exclusive prefix sums, fills
+size_t scan_temp_bytes(long long n);
+// out[i] = sum_{j<i} in[j]; *total (device, nullable) = sum of all.
+void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* temp,
+                        hipStream_t st);
+void fill_i32(int* p, int v, long long n, hipStream_t st);
+void fill_u64(unsigned long long* p, unsigned long long v, long long n, hipStream_t st);
+void set_i64(long long* d, long long v, hipStream_t st);
+// Small page-locked host buffer (64 int64 slots) for counts read back by the
+// host; one per calling thread, kept for the life of the process.
+long long* pinned_host();
+
+// sort.hip -- stable LSD radix sort of (uint32 key, int32 value) pairs
+size_t sort_temp_bytes(long long n);
+// Sorts keys/vals in place (using temp for the second buffers and counts).
+void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* temp,
+                    hipStream_t st);
+
+// activate.hip -- boundary conversions and packing
+// Stored form -> working layout; row p takes input row perm[p] (perm
+// nullable: identity) and gets logical index perm[p].
+void launch_activate_stored(const float* pos, const float* log_scale, const float* rot,
+                            const float* opacity, const int* perm, int n, float4* cen, int* lg,
+                            float4* shp, int* org, int* nonfinite, hipStream_t st);
+// Checks the SH rows for non-finite values.
+void launch_check_finite(const float* x, long long count, int* nonfinite, hipStream_t st);
+// Row copy of [rows][48] float arrays: dst[dst_row(r)] = src[src_row(r)],
+// dst_row = dst_map ? dst_map[r] : r, src_row = src_map ? src_map[r] : r.
+void launch_copy_sh_rows(const float* src, const int* src_map, float* dst, const int* dst_map,
+                         int rows, hipStream_t st);
+// Working layout -> stored form at the logical positions.
+void launch_deactivate_work(const float4* cen, const int* lg, const float4* shp, const int* org,
+                            int n, float* pos, float* log_scale, float* rot, float* opacity,
+                            int* origin_out, hipStream_t st);
+// Activated plain arrays <-> working layout (stage entry points).
+void launch_pack_splats(const float* mu, const float* scale, const float* quat, const float* alpha,
+                        const int* origin, int n, float4* cen, int* lg, float4* shp, int* org,
+                        hipStream_t st);
+void launch_unpack_splats(const float4* cen, const float4* shp, const int* org, int n, float* mu,
+                          float* scale, float* quat, float* alpha, int* origin, hipStream_t st);
+void launch_activate_plain(const float* pos, const float* log_scale, const float* rot,
+                           const float* opacity, int n, float* mu, float* scale, float* quat,
+                           float* alpha, int* nonfinite, hipStream_t st);
+void launch_deactivate_plain(const float* mu, const float* scale, const float* quat,
+                             const float* alpha, int n, float* pos, float* log_scale, float* rot,
+                             float* opacity, hipStream_t st);
+
+// knn.hip -- spatial order and exact kNN
+size_t knn_tree_bytes(long long n);
+// Morton keys of the centres over their bounding cube (10 bits per axis).
+void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
+                        void* temp, hipStream_t st);
+// Exact kNN over the splats in working order.  Output nbr[p][k] holds the
+// PHYSICAL indices of the k_eff nearest (key (d2, logical)); -1 padded.
+void knn_working(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
+                 hipStream_t st);
+// Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
+size_t knn_plain_bytes(long long n);
+void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);
+
+// edges.hip -- union edges
+size_t edges_temp_bytes(long long n, int k);
+// ea/eb: edges with lg[ea] < lg[eb] (lg nullable: identity).  Count written
+// to *d_m (int64, device) and returned through temp for the host.
+void launch_union_edges(const int* nbr, const int* lg, int n, int k, int* ea, int* eb,
+                        long long* d_m, void* temp, hipStream_t st);
+
+// cost.hip -- per-splat precompute and the edge cost
+struct CrnArgs {
+  int S;
+  float v[16][4];
+};
+void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st);
+// FP32 cost of edges [0, m); edges needing FP64 are appended to fb_list.
+// Edges with an end outside [0, n) get a NaN cost.
+void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
+                      const int* ea, const int* eb, int m, int n, const CrnArgs& crn,
+                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
+                      hipStream_t st);
+// FP64 cost of the listed edges (list nullable: all edges [0, count_host)).
+void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
+                           const int* ea, const int* eb, int n, const int* list,
+                           const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
+                           float* dgeo, hipStream_t st);
+
+// select.hip -- greedy disjoint pairs by locally-dominant matching
+size_t select_temp_bytes(long long n, long long m);
+struct SelectResult {
+  long long pairs;
+  int iters;
+};
+// partner[n] (physical); key tie-break on lg (nullable: identity).  Edges
+// with an end outside [0, n) are ignored.  d_npairs (nullable, device int64)
+// receives the pair count.  Synchronises st.
+SelectResult select_pairs(const int* ea, const int* eb, const float* cost, long long m, int n,
+                          const int* lg, long long max_pairs, int* partner, void* temp,
+                          hipStream_t st, long long* d_npairs);
+
+// merge.hip -- MPMM merge + stable compaction in working layout
+size_t merge_temp_bytes(long long n);
+// Returns the new count.  lg nullable (identity).  Writes the provenance pairs
+// (min origin, max origin) of the merges to trace (nullable) in the order of
+// the lower logical index.
+// Synchronises st.
+long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
+                        const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
+                        float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
+                        hipStream_t st, int* d_nout_i32);
+
+// crn.cpp
+void crn_host(uint64_t seed, int round, int S, float* out);
+
+}  // namespace ng

@@ -1,0 +1,144 @@
+// Device-wide exclusive prefix sums and fills.
+#include "internal.h"
+
+namespace ng {
+namespace {
+
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_ITEMS;
+
+// Exclusive scan of the per-thread values v across the block (256 threads).
+__device__ int block_exclusive_scan(int v, int* total) {
+  __shared__ int wsum[SCAN_BS / 64];
+  const int lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_BS / 64; ++i) {
+    int s = wsum[i];
+    off += (i < w) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, long long n,
+             int* __restrict__ tile_sums, int* __restrict__ total) {
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    long long idx = base + i;
+    v[i] = idx < n ? in[idx] : 0;
+    s += v[i];
+  }
+  int tot;
+  int run = block_exclusive_scan(s, &tot);
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    long long idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) {
+    if (tile_sums) tile_sums[blockIdx.x] = tot;
+    if (total) *total = tot;
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_add(int* __restrict__ out, long long n, const int* __restrict__ tile_off) {
+  const int add = tile_off[blockIdx.x];
+  const long long base = (long long)blockIdx.x * SCAN_TILE;
+  for (int i = threadIdx.x; i < SCAN_TILE; i += SCAN_BS) {
+    long long idx = base + i;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+__global__ void k_fill_i32(int* p, int v, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_set_i64(long long* d, long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
+}
+
+}  // namespace
+
+void set_i64(long long* d, long long v, hipStream_t st) {
+  k_set_i64<<<1, 64, 0, st>>>(d, v);
+  NG_LAUNCH_CHECK();
+}
+
+long long* pinned_host() {
+  thread_local long long* buf = nullptr;
+  if (!buf) NG_HIP(hipHostMalloc((void**)&buf, 64 * sizeof(long long), hipHostMallocDefault));
+  return buf;
+}
+
+size_t scan_temp_bytes(long long n) {
+  size_t b = 0;
+  while (n > SCAN_TILE) {
+    long long nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    b += 2 * (size_t)nt * sizeof(int) + 512;
+    n = nt;
+  }
+  return b + 256;
+}
+
+void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* temp,
+                        hipStream_t st) {
+  if (n <= 0) {
+    if (total) fill_i32(total, 0, 1, st);
+    return;
+  }
+  if (n <= SCAN_TILE) {
+    k_scan_tiles<<<1, SCAN_BS, 0, st>>>(in, out, n, nullptr, total);
+    NG_LAUNCH_CHECK();
+    return;
+  }
+  long long nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  Carver c(temp);
+  int* sums = c.take<int>(nt);
+  int* offs = c.take<int>(nt);
+  void* rest = (char*)temp + c.bytes();
+  k_scan_tiles<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, out, n, sums, nullptr);
+  NG_LAUNCH_CHECK();
+  scan_exclusive_i32(sums, offs, nt, total, rest, st);
+  k_scan_add<<<(unsigned)nt, SCAN_BS, 0, st>>>(out, n, offs);
+  NG_LAUNCH_CHECK();
+}
+
+void fill_i32(int* p, int v, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_i32<<<blocks_for(n, 256), 256, 0, st>>>(p, v, n);
+  NG_LAUNCH_CHECK();
+}
+
+void fill_u64(unsigned long long* p, unsigned long long v, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_u64<<<blocks_for(n, 256), 256, 0, st>>>(p, v, n);
+  NG_LAUNCH_CHECK();
+}
+
+}  // namespace ng

@@ -1,0 +1,401 @@
+"""Python binding of libnanogs.so (argument marshalling only).
+
+Every function takes torch tensors that live on the GPU, passes their device
+pointers and the current HIP stream to the C ABI of ``include/nanogs.h``, and
+raises ``NanoGSError`` on a non-OK status.  All arithmetic runs in the
+library's HIP kernels; there is no fallback path: if the library is missing
+or no GPU is present these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnanogs.so")
+
+SH = 48
+MAX_K = 32
+MAX_S = 16
+MAX_ROUNDS = 64
+PREC_FP32 = 0
+PREC_FP64 = 1
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY"}
+
+
+class NanoGSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
+                ("rot", ctypes.c_void_p), ("opacity", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+class Splats(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p), ("origin", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("app_dims", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("fb_ratio", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
+                ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("early_exit", ctypes.c_int32),
+                ("n_out", ctypes.c_int64),
+                ("n_per_round", ctypes.c_int64 * MAX_ROUNDS),
+                ("edges_per_round", ctypes.c_int64 * MAX_ROUNDS),
+                ("pairs_per_round", ctypes.c_int64 * MAX_ROUNDS),
+                ("fallback_per_round", ctypes.c_int64 * MAX_ROUNDS),
+                ("ld_iters_per_round", ctypes.c_int32 * MAX_ROUNDS)]
+
+    def as_dict(self):
+        r = self.rounds + (1 if self.early_exit else 0)
+        r = min(r, MAX_ROUNDS)
+        return {"rounds": self.rounds, "early_exit": bool(self.early_exit),
+                "n_out": self.n_out,
+                "n_per_round": list(self.n_per_round[:r]),
+                "edges_per_round": list(self.edges_per_round[:r]),
+                "pairs_per_round": list(self.pairs_per_round[:r]),
+                "fallback_per_round": list(self.fallback_per_round[:r]),
+                "ld_iters_per_round": list(self.ld_iters_per_round[:r])}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+
+_SIGS = {
+    "nanogs_default_options": (None, [ctypes.POINTER(Options)]),
+    "nanogs_last_error": (ctypes.c_char_p, []),
+    "nanogs_crn": (None, [ctypes.c_uint64, _I32, _I32, _P]),
+    "nanogs_simplify_workspace_bytes": (_SZ, [_I64, _I32, ctypes.POINTER(Options)]),
+    "nanogs_simplify": (ctypes.c_int, [ctypes.POINTER(Gaussians), _I64, _I64, _I32,
+                                       ctypes.POINTER(Options), ctypes.POINTER(Gaussians),
+                                       ctypes.POINTER(_I64), ctypes.POINTER(Stats), _P, _SZ, _P]),
+    "nanogs_activate": (ctypes.c_int, [ctypes.POINTER(Gaussians), _I64, ctypes.POINTER(Splats),
+                                       _P, _P]),
+    "nanogs_deactivate": (ctypes.c_int, [ctypes.POINTER(Splats), _I64,
+                                         ctypes.POINTER(Gaussians), _P]),
+    "nanogs_knn_workspace_bytes": (_SZ, [_I64, _I32]),
+    "nanogs_knn": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _SZ, _P]),
+    "nanogs_edges_workspace_bytes": (_SZ, [_I64, _I32]),
+    "nanogs_edges": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "nanogs_edge_cost_workspace_bytes": (_SZ, [_I64, _I64]),
+    "nanogs_edge_cost": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, _P, _I64, _P,
+                                        ctypes.POINTER(Options), _P, _P, _P, _SZ, _P]),
+    "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
+    "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
+    "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
+    "nanogs_merge": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, ctypes.POINTER(Splats),
+                                    _P, _P, _SZ, _P]),
+}
+
+
+def load():
+    """Loads the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2603_16103_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != 0:
+        msg = load().nanogs_last_error().decode(errors="replace")
+        raise NanoGSError(status, msg)
+
+
+# ---------------------------------------------------------------------------
+# torch plumbing
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int):
+    torch = _torch()
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
+            d_trace=None, d_origin=None) -> Options:
+    o = Options()
+    load().nanogs_default_options(ctypes.byref(o))
+    o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
+    o.seed, o.max_rounds = seed, max_rounds
+    o.d_trace = _ptr(d_trace).value if d_trace is not None else None
+    o.d_origin = _ptr(d_origin).value if d_origin is not None else None
+    return o
+
+
+@dataclass
+class GaussianTensors:
+    """Stored-form tensors on the GPU (float32, contiguous)."""
+
+    pos: object        # [n, 3]
+    log_scale: object  # [n, 3]
+    rot: object        # [n, 4]
+    opacity: object    # [n]
+    sh: object         # [n, 48]
+
+    @property
+    def n(self):
+        return int(self.pos.shape[0])
+
+    def struct(self):
+        return Gaussians(_ptr(self.pos), _ptr(self.log_scale), _ptr(self.rot),
+                         _ptr(self.opacity), _ptr(self.sh))
+
+    @staticmethod
+    def empty(n, device="cuda"):
+        torch = _torch()
+        f = torch.float32
+        return GaussianTensors(torch.empty((n, 3), dtype=f, device=device),
+                               torch.empty((n, 3), dtype=f, device=device),
+                               torch.empty((n, 4), dtype=f, device=device),
+                               torch.empty((n,), dtype=f, device=device),
+                               torch.empty((n, SH), dtype=f, device=device))
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        torch = _torch()
+        return GaussianTensors(*(torch.from_numpy(x).to(device).contiguous()
+                                 for x in (scene.pos, scene.log_scale, scene.rot,
+                                           scene.opacity, scene.sh)))
+
+    def slice(self, n):
+        return GaussianTensors(self.pos[:n], self.log_scale[:n], self.rot[:n],
+                               self.opacity[:n], self.sh[:n])
+
+    def numpy(self):
+        return tuple(x.cpu().numpy() for x in (self.pos, self.log_scale, self.rot,
+                                               self.opacity, self.sh))
+
+
+@dataclass
+class SplatTensors:
+    """Activated tensors on the GPU (float32, contiguous)."""
+
+    mu: object     # [n, 3]
+    scale: object  # [n, 3]
+    quat: object   # [n, 4]
+    alpha: object  # [n]
+    sh: object     # [n, 48]
+    origin: object = None  # [n] int32
+
+    @property
+    def n(self):
+        return int(self.mu.shape[0])
+
+    def struct(self):
+        return Splats(_ptr(self.mu), _ptr(self.scale), _ptr(self.quat), _ptr(self.alpha),
+                      _ptr(self.sh), _ptr(self.origin) if self.origin is not None else None)
+
+    @staticmethod
+    def empty(n, with_origin=False, device="cuda"):
+        torch = _torch()
+        f = torch.float32
+        return SplatTensors(torch.empty((n, 3), dtype=f, device=device),
+                            torch.empty((n, 3), dtype=f, device=device),
+                            torch.empty((n, 4), dtype=f, device=device),
+                            torch.empty((n,), dtype=f, device=device),
+                            torch.empty((n, SH), dtype=f, device=device),
+                            torch.empty((n,), dtype=torch.int32, device=device)
+                            if with_origin else None)
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+def crn(seed: int, round_idx: int, S: int):
+    """Host-side shared draws [S, 4] float32 (numpy)."""
+    import numpy as np
+    out = np.zeros((S, 4), dtype=np.float32)
+    load().nanogs_crn(ctypes.c_uint64(seed & ((1 << 64) - 1)), round_idx, S,
+                      out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+class Simplifier:
+    """Reusable simplify call: keeps the workspace between calls."""
+
+    def __init__(self, n_max: int, k: int = 16, opts: Options | None = None):
+        lib = load()
+        self.k = k
+        self.opts = opts if opts is not None else options()
+        self.ws_bytes = lib.nanogs_simplify_workspace_bytes(n_max, k, ctypes.byref(self.opts))
+        self.ws = _workspace(self.ws_bytes)
+        self.n_max = n_max
+
+    def __call__(self, g: GaussianTensors, target_n: int, out: GaussianTensors,
+                 stats: Stats | None = None) -> int:
+        if g.n > self.n_max:
+            raise ValueError("scene larger than the workspace was sized for")
+        lib = load()
+        n_out = ctypes.c_int64(0)
+        gs, os_ = g.struct(), out.struct()
+        _check(lib.nanogs_simplify(ctypes.byref(gs), g.n, target_n, self.k,
+                                   ctypes.byref(self.opts), ctypes.byref(os_),
+                                   ctypes.byref(n_out),
+                                   ctypes.byref(stats) if stats is not None else None,
+                                   _ptr(self.ws), self.ws_bytes, _stream()))
+        return int(n_out.value)
+
+
+def simplify(g: GaussianTensors, target_n: int | None = None, k: int = 16,
+             ratio: float | None = None, opts: Options | None = None, out=None,
+             return_stats: bool = False):
+    """Simplifies g to target_n splats (or max(ceil(ratio*n), 1)); returns
+    (GaussianTensors of length n_out[, stats dict])."""
+    if target_n is None:
+        if ratio is None:
+            raise ValueError("give target_n or ratio")
+        target_n = max(int(math.ceil(ratio * g.n)), 1)
+    out = out if out is not None else GaussianTensors.empty(g.n)
+    st = Stats()
+    n_out = Simplifier(g.n, k, opts)(g, target_n, out, st)
+    res = out.slice(n_out)
+    return (res, st.as_dict()) if return_stats else res
+
+
+def activate(g: GaussianTensors, s: SplatTensors | None = None, check_finite: bool = True):
+    torch = _torch()
+    s = s if s is not None else SplatTensors.empty(g.n)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda") if check_finite else None
+    gs, ss = g.struct(), s.struct()
+    _check(load().nanogs_activate(ctypes.byref(gs), g.n, ctypes.byref(ss), _ptr(flag), _stream()))
+    if check_finite and int(flag.item()) != 0:
+        raise NanoGSError(3, "input contains a non-finite value")
+    return s
+
+
+def deactivate(s: SplatTensors, g: GaussianTensors | None = None):
+    g = g if g is not None else GaussianTensors.empty(s.n)
+    ss, gs = s.struct(), g.struct()
+    _check(load().nanogs_deactivate(ctypes.byref(ss), s.n, ctypes.byref(gs), _stream()))
+    return g
+
+
+def knn(mu, k: int):
+    """mu [n,3] float32 cuda -> nbr [n,k] int32."""
+    torch = _torch()
+    lib = load()
+    n = int(mu.shape[0])
+    nbr = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    nb = lib.nanogs_knn_workspace_bytes(n, k)
+    ws = _workspace(nb)
+    _check(lib.nanogs_knn(_ptr(mu), n, k, _ptr(nbr), _ptr(ws), nb, _stream()))
+    return nbr
+
+
+def edges(nbr):
+    """nbr [n,k] int32 -> (ei, ej) int32 of length m."""
+    torch = _torch()
+    lib = load()
+    n, k = int(nbr.shape[0]), int(nbr.shape[1])
+    ei = torch.empty(max(n * k, 1), dtype=torch.int32, device="cuda")
+    ej = torch.empty(max(n * k, 1), dtype=torch.int32, device="cuda")
+    dm = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_edges_workspace_bytes(n, k)
+    ws = _workspace(nb)
+    _check(lib.nanogs_edges(_ptr(nbr), n, k, _ptr(ei), _ptr(ej), _ptr(dm), _ptr(ws), nb,
+                            _stream()))
+    m = int(dm.item())
+    return ei[:m], ej[:m]
+
+
+def edge_cost(s: SplatTensors, ei, ej, crn_block, opts: Options | None = None,
+              with_dgeo: bool = False):
+    """Cost of edges (ei[e], ej[e]); crn_block is a host [S,4] float32 array."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    m = int(ei.shape[0])
+    opts = opts if opts is not None else options()
+    blk = np.ascontiguousarray(crn_block, dtype=np.float32)
+    opts.S = int(blk.shape[0])
+    cost = torch.empty(max(m, 1), dtype=torch.float32, device="cuda")
+    dgeo = torch.empty(max(m, 1), dtype=torch.float32, device="cuda") if with_dgeo else None
+    nb = lib.nanogs_edge_cost_workspace_bytes(s.n, m)
+    ws = _workspace(nb)
+    ss = s.struct()
+    _check(lib.nanogs_edge_cost(ctypes.byref(ss), s.n, _ptr(ei), _ptr(ej), m,
+                                blk.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                                _ptr(cost), _ptr(dgeo), _ptr(ws), nb, _stream()))
+    return (cost[:m], dgeo[:m]) if with_dgeo else cost[:m]
+
+
+def select(ei, ej, cost, n: int, max_pairs: int):
+    """Greedy disjoint pairs -> (partner [n] int32, npairs)."""
+    torch = _torch()
+    lib = load()
+    m = int(ei.shape[0])
+    partner = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    dn = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_select_workspace_bytes(n, m)
+    ws = _workspace(nb)
+    _check(lib.nanogs_select(_ptr(ei) if m else None, _ptr(ej) if m else None,
+                             _ptr(cost) if m else None, m, n, max_pairs, _ptr(partner), _ptr(dn),
+                             _ptr(ws), nb, _stream()))
+    return partner[:n], int(dn.item())
+
+
+def merge(s: SplatTensors, partner):
+    """MPMM merge + compaction -> SplatTensors of the new count."""
+    torch = _torch()
+    lib = load()
+    out = SplatTensors.empty(s.n, with_origin=s.origin is not None)
+    dn = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_merge_workspace_bytes(s.n)
+    ws = _workspace(nb)
+    si, so = s.struct(), out.struct()
+    _check(lib.nanogs_merge(ctypes.byref(si), s.n, _ptr(partner), ctypes.byref(so), _ptr(dn),
+                            _ptr(ws), nb, _stream()))
+    k = int(dn.item())
+    return SplatTensors(out.mu[:k], out.scale[:k], out.quat[:k], out.alpha[:k], out.sh[:k],
+                        out.origin[:k] if out.origin is not None else None)
