@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the splat-simplification hot path on one MI355X.
+
+A step is one full nanogs_simplify call: 1,000,000 synthetic 3DGS splats
+(8 planes + 4 spheres + 10% clutter, seed 2) simplified to 100,000 with a
+k = 16 kNN graph and S = 1 shared draw, every pass of Algorithm 1 included
+(kNN graph, union edges, edge costs, greedy disjoint pairs, merge and
+compaction).  Inputs are resident in HBM before the timed region; the output
+is written to preallocated device buffers.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel, the
+FP64 oracle's CPU throughput on a bounded sample).  Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1m.json")
+
+
+def eprint(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(name):
+    with open(os.path.join(ROOT, "paper_2603_16103_amd", "csrc", name), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+# Algorithmic bytes per launch of the single-kernel stages (each input and
+# output element counted once): n = splats in the pass, e = edges, k = kNN size.
+def algo_bytes(stage, n, e, k):
+    if stage == "cost":        # cen 16 + factors 32 + SH 192 per splat; ends 8 + cost 4 per edge
+        return 240 * n + 12 * e
+    if stage == "knn_query":   # centres 16 per splat in, k neighbour ids out
+        return 16 * n + 4 * k * n
+    if stage == "precompute":  # shape 32 in, factors 32 out
+        return 64 * n
+    if stage == "knn_tree":    # centres in, boxes out (16 per splat, 2 x 16 per leaf pair)
+        return 16 * n + 4 * n
+    return None
+
+
+KERNEL_OF = {"cost": "k_edge_cost", "knn_query": "k_knn_query", "precompute": "k_precompute",
+             "knn_tree": "k_tree_levels"}
+SOURCE_OF = {"cost": "cost.hip", "knn_query": "knn.hip", "precompute": "cost.hip",
+             "knn_tree": "knn.hip"}
+
+
+def traffic_for(stage, launches_bytes):
+    """HBM bytes per launch from the committed counter summary, scaled by the
+    copy-kernel calibration; None when absent or the kernel source changed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = t.get("kernels", {}).get(KERNEL_OF[stage])
+    if not ent or ent.get("source_sha") != src_hash(SOURCE_OF[stage]):
+        return None
+    scale = t.get("copy_calibration", 1.0)
+    return (ent["fetch_kib"] + ent["write_kib"]) * 1024.0 * scale
+
+
+def cpu_baseline(sample_n):
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    import oracle as O
+    from paper_2603_16103_amd.synth import gen_scene
+    sc = gen_scene(sample_n, 2)
+    target = max(int(math.ceil(0.1 * sample_n)), 1)
+    t0 = time.perf_counter()
+    st = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, 16)
+    dt = time.perf_counter() - t0
+    assert st.n == target
+    del lim, np
+    return {"value": sample_n / dt, "unit": "Gaussians/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle (numpy, one thread), {sample_n} splats from the same "
+                      f"generator (seed 2) simplified to 10% with k=16, {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(one scene per GPU shards trivially; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_16103_amd import nanogs as ng
+    from paper_2603_16103_amd.synth import scene_plain_gpu
+
+    torch.cuda.set_device(0)
+    ng.load()
+    eprint("generating scene", args.n)
+    sc, k, target = scene_plain_gpu(args.n)
+    g = ng.GaussianTensors.from_scene(sc)
+    out = ng.GaussianTensors.empty(sc.n)
+    simp = ng.Simplifier(sc.n, k, ng.options(timing=True))
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        simp(g, target, out)
+        eprint(f"warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+
+    stage_ms = {s: 0.0 for s in ng.STAGES}
+    launches = {s: 0 for s in ng.STAGES}
+    bytes_by_stage = {s: 0.0 for s in ng.STAGES}
+    edges_total = 0
+    last = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = ng.Stats()
+        n_out = simp(g, target, out, st)
+        d = st.as_dict()
+        for s in ng.STAGES:
+            stage_ms[s] += d["stage_ms"][s]
+            launches[s] += d["stage_launches"][s]
+        for n_r, e_r in zip(d["n_per_round"], d["edges_per_round"]):
+            edges_total += e_r
+            for s in ng.STAGES:
+                b = algo_bytes(s, n_r, e_r, k)
+                if b is not None:
+                    bytes_by_stage[s] += b
+        last = d
+        eprint(f"step {i + 1}/{args.steps}: {n_out} splats, {d['rounds']} passes")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert n_out == target, (n_out, target)
+
+    ms_step = 1000.0 * dt / args.steps
+    value = args.n * args.steps / dt
+    single = [s for s in ("cost", "knn_query", "precompute") if launches[s] > 0]
+    dom = max(single, key=lambda s: stage_ms[s])
+    avg_ms = stage_ms[dom] / launches[dom]
+    bytes_per_launch = bytes_by_stage[dom] / launches[dom]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, bytes_per_launch),
+            "kernel": KERNEL_OF[dom], "avg_launch_us": round(1000 * avg_ms, 2),
+            "algo_bytes_per_launch": int(bytes_per_launch)}
+    res = {
+        "metric": "Gaussians simplified/s (1M→10%)",
+        "value": round(value, 1),
+        "unit": "Gaussians/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M synthetic 3DGS splats (8 planes, 4 spheres, 10% clutter, "
+                               "seed 2) -> 100k, k=16, S=1, FP32 costs with FP64 fallback",
+                   "n": args.n, "target_n": target, "k": k, "S": 1,
+                   "passes": last["rounds"], "n_per_pass": last["n_per_round"],
+                   "edges_per_pass": last["edges_per_round"],
+                   "fp64_edges_per_pass": last["fallback_per_round"]},
+        "edge_costs_per_s": round(edges_total / (stage_ms["cost"] * 1e-3), 1)
+        if stage_ms["cost"] > 0 else None,
+        "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 4) for s in ng.STAGES},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        eprint("cpu baseline (oracle) on", args.cpu_sample, "splats")
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -90,7 +90,22 @@ typedef struct {
                          pass order, each row (smaller origin, larger) */
   int32_t* d_origin;  /* nullable device [n]: provenance of each output
                          splat (smallest input index it absorbed) */
+  int32_t timing;     /* 1: time each stage with HIP events on the call's
+                         stream into nanogs_stats.stage_ms (0) */
 } nanogs_options;
+
+/* Stages timed into nanogs_stats.stage_ms when options.timing is set. */
+#define NANOGS_T_PRECOMPUTE 0 /* per-splat Cholesky factors and weights */
+#define NANOGS_T_KNN_TREE 1   /* bucket tree boxes */
+#define NANOGS_T_KNN_QUERY 2  /* exact kNN query kernel */
+#define NANOGS_T_EDGES 3      /* union edges (flags, scan, emit) */
+#define NANOGS_T_COST 4       /* FP32 edge-cost kernel */
+#define NANOGS_T_COST_FP64 5  /* FP64 recomputation of flagged edges */
+#define NANOGS_T_SELECT 6     /* matching iterations and budget */
+#define NANOGS_T_MERGE 7      /* merge and compaction */
+#define NANOGS_T_SETUP 8      /* spatial order and activation */
+#define NANOGS_T_OUTPUT 9     /* deactivation into the caller's order */
+#define NANOGS_NTIMED 10
 
 typedef struct {
   int32_t rounds;                          /* passes that merged >= 1 pair */
@@ -101,6 +116,8 @@ typedef struct {
   int64_t pairs_per_round[NANOGS_MAX_ROUNDS];
   int64_t fallback_per_round[NANOGS_MAX_ROUNDS]; /* edges costed in FP64 */
   int32_t ld_iters_per_round[NANOGS_MAX_ROUNDS]; /* matching iterations */
+  double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
+  int32_t stage_launches[NANOGS_NTIMED];
 } nanogs_stats;
 
 /* Fills *opt with the defaults listed above. */

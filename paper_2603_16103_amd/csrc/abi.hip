@@ -45,6 +45,7 @@ struct Opts {
   int max_rounds = 0;
   int* d_trace = nullptr;
   int* d_origin = nullptr;
+  int timing = 0;
 };
 
 nanogs_status read_opts(const nanogs_options* o, Opts* out) {
@@ -58,6 +59,7 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
     r.max_rounds = o->max_rounds;
     r.d_trace = o->d_trace;
     r.d_origin = o->d_origin;
+    r.timing = o->timing;
   }
   if (r.S < 1 || r.S > NANOGS_MAX_S) {
     set_error("options.S must be in [1, 16]");
@@ -249,8 +251,12 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
   long long* host = pinned_host();
   nanogs_stats local;
   std::memset(&local, 0, sizeof(local));
+  thread_local StageTimer T;
+  T.begin_call(o.timing != 0, st);
+  int tk;
 
   // 1. spatial order of the input (Morton order of the centres)
+  tk = T.start(NANOGS_T_SETUP);
   launch_morton_keys(in->pos, nullptr, (int)n, W.keys, W.counters + 8, st);
   k_iota<<<blocks_for(n, 256), 256, 0, st>>>(W.perm, (int)n);
   NG_LAUNCH_CHECK();
@@ -262,9 +268,11 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
                          W.w[0].cen, W.w[0].lg, W.w[0].shp, W.w[0].org, W.counters, st);
   launch_check_finite(in->sh, n * NG_SH, W.counters, st);
   launch_copy_sh_rows(in->sh, W.perm, W.w[0].sh, nullptr, (int)n, st);
+  T.stop(tk);
   NG_HIP(hipMemcpyAsync(host, W.counters, sizeof(int), hipMemcpyDeviceToHost, st));
   NG_HIP(hipStreamSynchronize(st));
   if (*(int*)host != 0) {
+    T.collect(local.stage_ms, local.stage_launches);
     set_error("input contains a non-finite value");
     return NANOGS_ENONFINITE;
   }
@@ -278,9 +286,18 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
     const Work& a = W.w[cur];
     const Work& b = W.w[cur ^ 1];
     const int keff = (int)std::min<long long>(std::max(1, k), N - 1);
+    tk = T.start(NANOGS_T_PRECOMPUTE);
     launch_precompute(a.shp, (int)N, W.pre, st);
-    knn_working(a.cen, (int)N, k, keff, W.nbr, W.temp, st);
+    T.stop(tk);
+    tk = T.start(NANOGS_T_KNN_TREE);
+    knn_working_tree(a.cen, (int)N, W.temp, st);
+    T.stop(tk);
+    tk = T.start(NANOGS_T_KNN_QUERY);
+    knn_working_query(a.cen, (int)N, k, keff, W.nbr, W.temp, st);
+    T.stop(tk);
+    tk = T.start(NANOGS_T_EDGES);
     launch_union_edges(W.nbr, a.lg, (int)N, k, W.ea, W.eb, W.d_m, W.temp, st);
+    T.stop(tk);
     NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st));
     NG_HIP(hipStreamSynchronize(st));
     const long long m = host[0];
@@ -288,17 +305,25 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
     int* fb_count = W.counters + 1;
     fill_i32(fb_count, 0, 1, st);
     if (o.precision == NANOGS_PREC_FP64) {
+      tk = T.start(NANOGS_T_COST_FP64);
       launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, nullptr, nullptr,
                             (int)m, crn, W.cost, nullptr, st);
+      T.stop(tk);
     } else {
+      tk = T.start(NANOGS_T_COST);
       launch_edge_cost(a.cen, W.pre, a.sh, o.app_dims, W.ea, W.eb, (int)m, (int)N, crn,
                        o.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, st);
+      T.stop(tk);
+      tk = T.start(NANOGS_T_COST_FP64);
       launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, W.fb_list,
                             fb_count, (int)m, crn, W.cost, nullptr, st);
+      T.stop(tk);
     }
     const long long P = N - target_n;
+    tk = T.start(NANOGS_T_SELECT);
     SelectResult sel =
         select_pairs(W.ea, W.eb, W.cost, m, (int)N, a.lg, P, W.partner, W.temp, st, nullptr);
+    T.stop(tk);
     long long fb = m;
     if (o.precision != NANOGS_PREC_FP64) {
       NG_HIP(hipMemcpyAsync(host, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -317,8 +342,10 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
       break;
     }
     int* trace = o.d_trace ? o.d_trace + 2 * traced : nullptr;
+    tk = T.start(NANOGS_T_MERGE);
     const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
                                        b.lg, b.shp, b.sh, b.org, trace, W.temp, st, nullptr);
+    T.stop(tk);
     traced += sel.pairs;
     N = nn;
     cur ^= 1;
@@ -328,10 +355,13 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
 
   // 4. output in the caller's (logical) order
   const Work& f = W.w[cur];
+  tk = T.start(NANOGS_T_OUTPUT);
   launch_deactivate_work(f.cen, f.lg, f.shp, f.org, (int)N, out->pos, out->log_scale, out->rot,
                          out->opacity, o.d_origin, st);
   launch_copy_sh_rows(f.sh, nullptr, out->sh, f.lg, (int)N, st);
+  T.stop(tk);
   NG_HIP(hipStreamSynchronize(st));
+  T.collect(local.stage_ms, local.stage_launches);
   local.n_out = N;
   *n_out = N;
   if (stats) *stats = local;
@@ -389,6 +419,7 @@ void nanogs_default_options(nanogs_options* opt) {
   opt->fb_ratio = 1.0f / 256.0f;
   opt->seed = 0;
   opt->max_rounds = 0;
+  opt->timing = 0;
 }
 
 const char* nanogs_last_error(void) { return g_error.c_str(); }

@@ -131,8 +131,11 @@ void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsign
                         void* temp, hipStream_t st);
 // Exact kNN over the splats in working order.  Output nbr[p][k] holds the
 // PHYSICAL indices of the k_eff nearest (key (d2, logical)); -1 padded.
-void knn_working(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
-                 hipStream_t st);
+// Two steps sharing tree_mem: boxes (+ logical -> working inverse), then the
+// query.
+void knn_working_tree(const float4* cen, int n, void* tree_mem, hipStream_t st);
+void knn_working_query(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
+                       hipStream_t st);
 // Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
 size_t knn_plain_bytes(long long n);
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);
@@ -188,5 +191,45 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
 
 // crn.cpp
 void crn_host(uint64_t seed, int round, int S, float* out);
+
+// Stage timing with HIP events recorded on the working stream.
+struct StageTimer {
+  static constexpr int kMax = 4096;
+  bool on = false;
+  hipStream_t st = nullptr;
+  int used = 0;
+  int stage[kMax / 2];
+  hipEvent_t ev[kMax];
+  void begin_call(bool enable, hipStream_t s) {
+    on = enable;
+    st = s;
+    used = 0;
+  }
+  int start(int which) {
+    if (!on || used + 2 > kMax) return -1;
+    const int i = used;
+    used += 2;
+    NG_HIP(hipEventCreate(&ev[i]));
+    NG_HIP(hipEventCreate(&ev[i + 1]));
+    stage[i / 2] = which;
+    NG_HIP(hipEventRecord(ev[i], st));
+    return i;
+  }
+  void stop(int i) {
+    if (i >= 0) NG_HIP(hipEventRecord(ev[i + 1], st));
+  }
+  // after the stream is synchronised: accumulate and release the events
+  void collect(double* ms, int* launches) {
+    for (int i = 0; i < used; i += 2) {
+      float t = 0.f;
+      NG_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[stage[i / 2]] += t;
+      launches[stage[i / 2]] += 1;
+      NG_HIP(hipEventDestroy(ev[i]));
+      NG_HIP(hipEventDestroy(ev[i + 1]));
+    }
+    used = 0;
+  }
+};
 
 }  // namespace ng

@@ -385,8 +385,7 @@ void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsign
   NG_LAUNCH_CHECK();
 }
 
-void knn_working(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
-                 hipStream_t st) {
+void knn_working_tree(const float4* cen, int n, void* tree_mem, hipStream_t st) {
   TreeShape ts = tree_shape(n);
   Carver c(tree_mem);
   float4* bmin = c.take<float4>(2ll * ts.nb2);
@@ -395,6 +394,15 @@ void knn_working(const float4* cen, int n, int k, int keff, int* nbr, void* tree
   build_tree(cen, n, ts, bmin, bmax, st);
   k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, inv);
   NG_LAUNCH_CHECK();
+}
+
+void knn_working_query(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
+                       hipStream_t st) {
+  TreeShape ts = tree_shape(n);
+  Carver c(tree_mem);
+  float4* bmin = c.take<float4>(2ll * ts.nb2);
+  float4* bmax = c.take<float4>(2ll * ts.nb2);
+  int* inv = c.take<int>(n);
   query(cen, n, keff, k, ts, bmin, bmax, inv, 0, nbr, st);
 }
 

@@ -22,6 +22,9 @@ MAX_S = 16
 MAX_ROUNDS = 64
 PREC_FP32 = 0
 PREC_FP64 = 1
+STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "select",
+          "merge", "setup", "output")
+NTIMED = len(STAGES)
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY"}
 
@@ -48,7 +51,8 @@ class Options(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("app_dims", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("fb_ratio", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
-                ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p)]
+                ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p),
+                ("timing", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -58,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("edges_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("pairs_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("fallback_per_round", ctypes.c_int64 * MAX_ROUNDS),
-                ("ld_iters_per_round", ctypes.c_int32 * MAX_ROUNDS)]
+                ("ld_iters_per_round", ctypes.c_int32 * MAX_ROUNDS),
+                ("stage_ms", ctypes.c_double * NTIMED),
+                ("stage_launches", ctypes.c_int32 * NTIMED)]
 
     def as_dict(self):
         r = self.rounds + (1 if self.early_exit else 0)
@@ -69,7 +75,9 @@ class Stats(ctypes.Structure):
                 "edges_per_round": list(self.edges_per_round[:r]),
                 "pairs_per_round": list(self.pairs_per_round[:r]),
                 "fallback_per_round": list(self.fallback_per_round[:r]),
-                "ld_iters_per_round": list(self.ld_iters_per_round[:r])}
+                "ld_iters_per_round": list(self.ld_iters_per_round[:r]),
+                "stage_ms": dict(zip(STAGES, self.stage_ms)),
+                "stage_launches": dict(zip(STAGES, self.stage_launches))}
 
 
 _lib = None
@@ -163,13 +171,14 @@ def _workspace(nbytes: int):
 
 
 def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
-            d_trace=None, d_origin=None) -> Options:
+            d_trace=None, d_origin=None, timing=False) -> Options:
     o = Options()
     load().nanogs_default_options(ctypes.byref(o))
     o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
     o.seed, o.max_rounds = seed, max_rounds
     o.d_trace = _ptr(d_trace).value if d_trace is not None else None
     o.d_origin = _ptr(d_origin).value if d_origin is not None else None
+    o.timing = 1 if timing else 0
     return o
 
 
