@@ -190,9 +190,15 @@ struct SimplifyWs {
   Work w[2];
   float4* pre;
   int* nbr;
-  int* ea;
-  int* eb;
+  int* src;
+  int* tgt;
+  int* islot;
+  int* eoff;
+  int* ioff;
+  int* aoff;
   float* cost;
+  unsigned long long* akey;
+  int* au;
   int* fb_list;
   int* partner;
   unsigned* keys;
@@ -218,9 +224,15 @@ SimplifyWs carve_simplify(void* base, long long n, int k, size_t* bytes_out = nu
   s.w[1] = take_work(c, n);
   s.pre = c.take<float4>(2 * n);
   s.nbr = c.take<int>(n * k);
-  s.ea = c.take<int>(n * k);
-  s.eb = c.take<int>(n * k);
+  s.src = c.take<int>(n * k);
+  s.tgt = c.take<int>(n * k);
+  s.islot = c.take<int>(n * k);
+  s.eoff = c.take<int>(n + 1);
+  s.ioff = c.take<int>(n + 1);
+  s.aoff = c.take<int>(n + 1);
   s.cost = c.take<float>(n * k);
+  s.akey = c.take<unsigned long long>(2 * n * k);
+  s.au = c.take<int>(2 * n * k);
   s.fb_list = c.take<int>(n * k);
   s.partner = c.take<int>(n);
   s.keys = c.take<unsigned>(n);
@@ -278,6 +290,8 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
   }
 
   // 3. passes
+  const unsigned* box = (const unsigned*)(W.counters + 8);  // Morton bounds
+  fill_i32(W.counters + 2, 0, 1, st);
   int cur = 0;
   long long N = n;
   long long traced = 0;
@@ -290,39 +304,46 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
     launch_precompute(a.shp, (int)N, W.pre, st);
     T.stop(tk);
     tk = T.start(NANOGS_T_KNN_TREE);
-    knn_working_tree(a.cen, (int)N, W.temp, st);
+    knn_working_tree(a.cen, (int)N, box, W.temp, W.counters + 2, st);
     T.stop(tk);
     tk = T.start(NANOGS_T_KNN_QUERY);
-    knn_working_query(a.cen, (int)N, k, keff, W.nbr, W.temp, st);
+    knn_working_query(a.cen, (int)N, k, keff, box, W.nbr, W.temp, st);
     T.stop(tk);
     tk = T.start(NANOGS_T_EDGES);
-    launch_union_edges(W.nbr, a.lg, (int)N, k, W.ea, W.eb, W.d_m, W.temp, st);
+    const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
+    launch_union_edges(W.nbr, a.lg, (int)N, k, es, W.d_m, W.temp, st);
     T.stop(tk);
     NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st));
+    NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     NG_HIP(hipStreamSynchronize(st));
     const long long m = host[0];
+    if (*(int*)(host + 1) != 0) {
+      set_error("internal: working set not in Morton order");
+      return NANOGS_EHIP;
+    }
     const CrnArgs crn = make_crn(o.seed, r, o.S);
+    const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
     int* fb_count = W.counters + 1;
     fill_i32(fb_count, 0, 1, st);
     if (o.precision == NANOGS_PREC_FP64) {
       tk = T.start(NANOGS_T_COST_FP64);
-      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, nullptr, nullptr,
-                            (int)m, crn, W.cost, nullptr, st);
+      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.src, W.tgt, (int)N, true, nullptr,
+                            nullptr, (int)m, crn, W.cost, nullptr, adj_out, st);
       T.stop(tk);
     } else {
       tk = T.start(NANOGS_T_COST);
-      launch_edge_cost(a.cen, W.pre, a.sh, o.app_dims, W.ea, W.eb, (int)m, (int)N, crn,
-                       o.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, st);
+      launch_edge_cost(a.cen, W.pre, a.sh, o.app_dims, W.src, W.tgt, (int)m, (int)N, true, crn,
+                       o.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, adj_out, st);
       T.stop(tk);
       tk = T.start(NANOGS_T_COST_FP64);
-      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.ea, W.eb, (int)N, W.fb_list,
-                            fb_count, (int)m, crn, W.cost, nullptr, st);
+      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.src, W.tgt, (int)N, true,
+                            W.fb_list, fb_count, (int)m, crn, W.cost, nullptr, adj_out, st);
       T.stop(tk);
     }
     const long long P = N - target_n;
     tk = T.start(NANOGS_T_SELECT);
-    SelectResult sel =
-        select_pairs(W.ea, W.eb, W.cost, m, (int)N, a.lg, P, W.partner, W.temp, st, nullptr);
+    const Adjacency adj{W.aoff, W.akey, W.au};
+    SelectResult sel = select_pairs(adj, (int)N, a.lg, P, W.partner, W.temp, st, nullptr);
     T.stop(tk);
     long long fb = m;
     if (o.precision != NANOGS_PREC_FP64) {
@@ -344,7 +365,8 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
     int* trace = o.d_trace ? o.d_trace + 2 * traced : nullptr;
     tk = T.start(NANOGS_T_MERGE);
     const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
-                                       b.lg, b.shp, b.sh, b.org, trace, W.temp, st, nullptr);
+                                       b.lg, b.shp, b.sh, b.org, trace, W.temp, st, nullptr,
+                                       box);
     T.stop(tk);
     traced += sel.pairs;
     N = nn;
@@ -525,7 +547,7 @@ nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr, vo
 size_t nanogs_edges_workspace_bytes(int64_t n, int32_t k) {
   if (n < 1) n = 1;
   if (k < 1) k = 1;
-  return edges_temp_bytes(n, k);
+  return edges_public_bytes(n, k);
 }
 
 nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k, int32_t* ei, int32_t* ej,
@@ -540,8 +562,8 @@ nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k, int32_t* ei
     NG_CHECK(check_ptr(nbr, 4, "nbr"));
     NG_CHECK(check_ptr(ei, 4, "ei"));
     NG_CHECK(check_ptr(ej, 4, "ej"));
-    NG_CHECK(check_ws(ws, ws_bytes, edges_temp_bytes(n, k)));
-    launch_union_edges(nbr, nullptr, (int)n, k, ei, ej, (long long*)d_m, ws, stream);
+    NG_CHECK(check_ws(ws, ws_bytes, edges_public_bytes(n, k)));
+    union_edges_public(nbr, (int)n, k, ei, ej, (long long*)d_m, ws, stream);
     return NANOGS_OK;
   });
 }
@@ -581,22 +603,24 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
     launch_pack_splats(s->mu, s->scale, s->quat, s->alpha, s->origin, (int)n, p.cen, p.lg, p.shp,
                        p.org, stream);
     if (o.precision == NANOGS_PREC_FP64) {
-      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, nullptr, nullptr,
-                            (int)m, args, cost, dgeo, stream);
+      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, false, nullptr,
+                            nullptr, (int)m, args, cost, dgeo, AdjOut{}, stream);
     } else {
       launch_precompute(p.shp, (int)n, pre, stream);
       fill_i32(counters, 0, 1, stream);
-      launch_edge_cost(p.cen, pre, s->sh, o.app_dims, ei, ej, (int)m, (int)n, args, o.fb_ratio,
-                       cost, dgeo, fb_list, counters, stream);
-      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, fb_list, counters,
-                            (int)m, args, cost, dgeo, stream);
+      launch_edge_cost(p.cen, pre, s->sh, o.app_dims, ei, ej, (int)m, (int)n, false, args,
+                       o.fb_ratio, cost, dgeo, fb_list, counters, AdjOut{}, stream);
+      launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, false, fb_list,
+                            counters, (int)m, args, cost, dgeo, AdjOut{}, stream);
     }
     return NANOGS_OK;
   });
 }
 
 size_t nanogs_select_workspace_bytes(int64_t n, int64_t m) {
-  return select_temp_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
+  if (n < 1) n = 1;
+  if (m < 1) m = 1;
+  return select_adj_bytes(n, m) + select_temp_bytes(n, m);
 }
 
 nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* cost, int64_t m,
@@ -604,8 +628,8 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* c
                             void* ws, size_t ws_bytes, hipStream_t stream) {
   return guarded([&]() -> nanogs_status {
     NG_CHECK(check_n(n, 1));
-    if (m < 0 || m >= (1ll << 31)) {
-      set_error("m must be in [0, 2^31)");
+    if (m < 0 || m >= (1ll << 30)) {
+      set_error("m must be in [0, 2^30)");
       return NANOGS_EINVAL;
     }
     if (max_pairs < 0) {
@@ -623,9 +647,12 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* c
       NG_CHECK(check_ptr(ej, 4, "ej"));
       NG_CHECK(check_ptr(cost, 4, "cost"));
     }
-    NG_CHECK(check_ws(ws, ws_bytes, select_temp_bytes(n, m < 1 ? 1 : m)));
-    select_pairs(ei, ej, cost, m, (int)n, nullptr, max_pairs, partner, ws, stream,
-                 (long long*)d_npairs);
+    const long long mm = m < 1 ? 1 : m;
+    NG_CHECK(check_ws(ws, ws_bytes, select_adj_bytes(n, mm) + select_temp_bytes(n, mm)));
+    Adjacency adj;
+    build_adjacency(ei, ej, cost, m, (int)n, &adj, ws, stream);
+    void* temp = (char*)ws + select_adj_bytes(n, mm);
+    select_pairs(adj, (int)n, nullptr, max_pairs, partner, temp, stream, (long long*)d_npairs);
     return NANOGS_OK;
   });
 }
@@ -658,7 +685,7 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* pa
                        a.shp, a.org, stream);
     const long long nout = merge_compact(a.cen, nullptr, a.shp, in->sh, a.org, (int)n, partner,
                                          b.cen, b.lg, b.shp, out->sh, b.org, nullptr, temp,
-                                         stream, nullptr);
+                                         stream, nullptr, nullptr);
     launch_unpack_splats(b.cen, b.shp, b.org, (int)nout, out->mu, out->scale, out->quat,
                          out->alpha, (in->origin && out->origin) ? out->origin : nullptr, stream);
     set_i64((long long*)d_nout, nout, stream);

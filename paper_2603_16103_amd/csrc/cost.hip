@@ -232,12 +232,28 @@ NG_DEV void append_wave(bool flag, int value, int* list, int* count) {
   }
 }
 
+NG_DEV unsigned long long adj_key(float c, int other_logical) {
+  if (!isfinite(c)) return ~0ull;
+  return ((unsigned long long)f2ord(c) << 32) | (unsigned)other_logical;
+}
+
+// Writes edge e's two adjacency entries (layout in edges.hip).
+NG_DEV void write_adj(const AdjOut& adj, int e, int s, int t, int ls, int lt, float c) {
+  if (!adj.akey) return;
+  const long long ps = (long long)adj.ioff[s] + e;
+  const long long pt = (long long)adj.eoff[t + 1] + adj.ioff[t] + adj.islot[e];
+  adj.akey[ps] = adj_key(c, lt);
+  adj.au[ps] = t;
+  adj.akey[pt] = adj_key(c, ls);
+  adj.au[pt] = s;
+}
+
 __global__ void __launch_bounds__(256)
 k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
             const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
-            const int* __restrict__ eb, int m, int n, CrnArgs crn, float fb_ratio,
+            const int* __restrict__ eb, int m, int n, int orient, CrnArgs crn, float fb_ratio,
             float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
-            int* __restrict__ fb_count) {
+            int* __restrict__ fb_count, AdjOut adj) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = e < m;
   bool fb = false;
@@ -250,8 +266,12 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
     }
   }
   if (live) {
-    const int a = ea[e], b = eb[e];
-    const float4 ca = cen[a], cb = cen[b];
+    const int s = ea[e], t = eb[e];
+    const float4 cs = cen[s], ct = cen[t];
+    const int ls = __float_as_int(cs.w), lt = __float_as_int(ct.w);
+    const bool sw = orient && lt < ls;  // first component = smaller logical index
+    const int a = sw ? t : s, b = sw ? s : t;
+    const float4 ca = sw ? ct : cs, cb = sw ? cs : ct;
     const float4 pa0 = pre[2 * (long long)a], pa1 = pre[2 * (long long)a + 1];
     const float4 pb0 = pre[2 * (long long)b], pb1 = pre[2 * (long long)b + 1];
     const Tri<float> La = {pa0.x, pa0.y, pa0.z, pa0.w, pa1.x, pa1.y};
@@ -266,6 +286,7 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
     fb = !(ratio >= fb_ratio) || !isfinite(c);
     cost[e] = c;
     if (dgeo_out) dgeo_out[e] = dg;
+    write_adj(adj, e, s, t, ls, lt, c);
   }
   if (fb_list) append_wave(fb, e, fb_list, fb_count);
 }
@@ -273,19 +294,23 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
 __global__ void __launch_bounds__(256)
 k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
                  const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
-                 const int* __restrict__ eb, int n, const int* __restrict__ list,
+                 const int* __restrict__ eb, int n, int orient, const int* __restrict__ list,
                  const int* __restrict__ d_count, int count_cap, CrnArgs crn,
-                 float* __restrict__ cost, float* __restrict__ dgeo_out) {
+                 float* __restrict__ cost, float* __restrict__ dgeo_out, AdjOut adj) {
   const int count = d_count ? min(*d_count, count_cap) : count_cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const int e = list ? list[i] : i;
-    const int a = ea[e], b = eb[e];
-    if (a < 0 || a >= n || b < 0 || b >= n) {
+    const int s = ea[e], t = eb[e];
+    if (s < 0 || s >= n || t < 0 || t >= n) {
       cost[e] = __int_as_float(0x7fc00000);
       if (dgeo_out) dgeo_out[e] = __int_as_float(0x7fc00000);
       continue;
     }
-    const float4 ca = cen[a], cb = cen[b];
+    const float4 cs = cen[s], ct = cen[t];
+    const int ls = __float_as_int(cs.w), lt = __float_as_int(ct.w);
+    const bool sw = orient && lt < ls;
+    const int a = sw ? t : s, b = sw ? s : t;
+    const float4 ca = sw ? ct : cs, cb = sw ? cs : ct;
     const float4 sa = shp[2 * (long long)a], qa = shp[2 * (long long)a + 1];
     const float4 sb = shp[2 * (long long)b], qb = shp[2 * (long long)b + 1];
     const Tri<double> La = chol_from_scale_rot<double>(sa.x, sa.y, sa.z, qa.x, qa.y, qa.z, qa.w);
@@ -302,8 +327,10 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
     double ratio;
     const double dg = dgeo_pair<double>(v3<double>(ca.x, ca.y, ca.z), v3<double>(cb.x, cb.y, cb.z),
                                         La, Lb, lda, ldb, pa, pb, pa32, crn, ratio);
-    cost[e] = (float)(dg + dapp_f64(sh, a, b, app_dims));
+    const float c = (float)(dg + dapp_f64(sh, a, b, app_dims));
+    cost[e] = c;
     if (dgeo_out) dgeo_out[e] = (float)dg;
+    write_adj(adj, e, s, t, ls, lt, c);
   }
 }
 
@@ -316,24 +343,25 @@ void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st) {
 }
 
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
-                      const int* ea, const int* eb, int m, int n, const CrnArgs& crn,
-                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
-                      hipStream_t st) {
+                      const int* ea, const int* eb, int m, int n, bool orient,
+                      const CrnArgs& crn, float fb_ratio, float* cost, float* dgeo, int* fb_list,
+                      int* fb_count, AdjOut adj, hipStream_t st) {
   if (m <= 0) return;
-  k_edge_cost<<<blocks_for(m, 256), 256, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n, crn,
-                                                  fb_ratio, cost, dgeo, fb_list, fb_count);
+  k_edge_cost<<<blocks_for(m, 256), 256, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n,
+                                                  orient ? 1 : 0, crn, fb_ratio, cost, dgeo,
+                                                  fb_list, fb_count, adj);
   NG_LAUNCH_CHECK();
 }
 
 void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
-                           const int* ea, const int* eb, int n, const int* list,
+                           const int* ea, const int* eb, int n, bool orient, const int* list,
                            const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
-                           float* dgeo, hipStream_t st) {
+                           float* dgeo, AdjOut adj, hipStream_t st) {
   if (count_cap <= 0) return;
   unsigned b = blocks_for(count_cap, 256);
   if (b > 2048) b = 2048;
-  k_edge_cost_fp64<<<b, 256, 0, st>>>(cen, shp, sh, app_dims, ea, eb, n, list, d_count, count_cap,
-                                      crn, cost, dgeo);
+  k_edge_cost_fp64<<<b, 256, 0, st>>>(cen, shp, sh, app_dims, ea, eb, n, orient ? 1 : 0, list,
+                                      d_count, count_cap, crn, cost, dgeo, adj);
   NG_LAUNCH_CHECK();
 }
 

@@ -1,8 +1,17 @@
 // Undirected union of the directed kNN lists (Algorithm 1,
-// UndirectedUnionEdges): row i emits its neighbour j unless j also lists i
+// UndirectedUnionEdges): row p emits its neighbour j unless j also lists p
 // and j comes first in the logical order, so every unordered pair appears
-// exactly once.  Count per row, exclusive scan, emit: the output order is
-// deterministic (by row, then slot).
+// exactly once.  Edges are numbered in emission order (by row, then slot);
+// edge e is stored as (src[e] = emitting row, tgt[e] = the neighbour).
+//
+// The same pass builds the incidence structure the pair selection reads:
+//   eoff[p]  first edge emitted by row p (eoff[n] = m): row p's own edges
+//            are the contiguous range [eoff[p], eoff[p+1]);
+//   ioff[p]  start of p's incoming edges in a second numbering (ioff[n] = m);
+//   islot[e] rank of edge e among the edges whose tgt is tgt[e].
+// With aoff[p] = eoff[p] + ioff[p], every splat p owns the adjacency range
+// [aoff[p], aoff[p+1]) holding first its emitted edges, then its incoming
+// ones: each edge has exactly one entry at each of its two ends.
 #include "internal.h"
 
 namespace ng {
@@ -10,46 +19,64 @@ namespace {
 
 NG_DEV int logical(const int* lg, int p) { return lg ? lg[p] : p; }
 
-__global__ void k_edge_flags(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int k,
-                             unsigned char* __restrict__ flag, int* __restrict__ cnt) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int* row = nbr + (long long)p * k;
-  const int lp = logical(lg, p);
-  int c = 0;
-  for (int t = 0; t < k; ++t) {
-    const int j = row[t];
-    bool emit = false;
-    if (j >= 0 && j < n && j != p) {
-      if (lp < logical(lg, j)) {
-        emit = true;
+// thread per directed slot (p, t): 1 if the slot emits an edge
+__global__ void __launch_bounds__(256)
+k_edge_flags(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int k, int vec4,
+             unsigned char* __restrict__ flag) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (long long)n * k) return;
+  const int p = (int)(s / k);
+  const int j = nbr[s];
+  bool emit = false;
+  if (j >= 0 && j < n && j != p) {
+    if (logical(lg, p) < logical(lg, j)) {
+      emit = true;
+    } else {
+      const int* rj = nbr + (long long)j * k;
+      bool mutual = false;
+      if (vec4) {
+        const int4* r4 = (const int4*)rj;
+        for (int u = 0; u < (k >> 2); ++u) {
+          const int4 v = r4[u];
+          mutual |= (v.x == p) | (v.y == p) | (v.z == p) | (v.w == p);
+        }
       } else {
-        const int* rj = nbr + (long long)j * k;
-        bool mutual = false;
         for (int u = 0; u < k; ++u) mutual |= (rj[u] == p);
-        emit = !mutual;
       }
+      emit = !mutual;
     }
-    flag[(long long)p * k + t] = emit ? 1 : 0;
-    c += emit ? 1 : 0;
   }
-  cnt[p] = c;
+  flag[s] = emit ? 1 : 0;
 }
 
-__global__ void k_edge_emit(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int k,
-                            const unsigned char* __restrict__ flag, const int* __restrict__ off,
-                            int* __restrict__ ea, int* __restrict__ eb) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
+// thread per row: emitted count (the row's flags are contiguous bytes)
+__global__ void __launch_bounds__(256)
+k_edge_count(const unsigned char* __restrict__ flag, int n, int k, int* __restrict__ cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > n) return;
+  int c = 0;
+  if (p < n) {
+    const unsigned char* f = flag + (long long)p * k;
+    for (int t = 0; t < k; ++t) c += f[t];
+  }
+  cnt[p] = c;  // cnt[n] = 0, so the scan's entry n is the total
+}
+
+__global__ void __launch_bounds__(256)
+k_edge_emit(const int* __restrict__ nbr, int n, int k, const unsigned char* __restrict__ flag,
+            const int* __restrict__ eoff, int* __restrict__ src, int* __restrict__ tgt,
+            int* __restrict__ indeg, int* __restrict__ islot) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int* row = nbr + (long long)p * k;
-  const int lp = logical(lg, p);
-  int o = off[p];
+  const unsigned char* f = flag + (long long)p * k;
+  int o = eoff[p];
   for (int t = 0; t < k; ++t) {
-    if (flag[(long long)p * k + t]) {
+    if (f[t]) {
       const int j = row[t];
-      const bool first = lp < logical(lg, j);
-      ea[o] = first ? p : j;
-      eb[o] = first ? j : p;
+      src[o] = p;
+      tgt[o] = j;
+      if (islot) islot[o] = atomicAdd(&indeg[j], 1);
       ++o;
     }
   }
@@ -59,31 +86,87 @@ __global__ void k_to_i64(const int* __restrict__ v, long long* __restrict__ out)
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = (long long)*v;
 }
 
+// (src, tgt) -> (smaller, larger) in the caller's numbering
+__global__ void k_edge_minmax(const int* __restrict__ src, const int* __restrict__ tgt,
+                              const int* __restrict__ d_m, int* __restrict__ ei,
+                              int* __restrict__ ej) {
+  const int m = *d_m;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    const int a = src[e], b = tgt[e];
+    ei[e] = a < b ? a : b;
+    ej[e] = a < b ? b : a;
+  }
+}
+
+__global__ void k_add_offsets(const int* __restrict__ a, const int* __restrict__ b, int n1,
+                              int* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n1) out[p] = a[p] + b[p];
+}
+
 }  // namespace
 
 size_t edges_temp_bytes(long long n, int k) {
   Carver c(nullptr);
   c.take<unsigned char>(n * k);
-  c.take<int>(n);
-  c.take<int>(n);
+  c.take<int>(n + 1);
+  c.take<int>(n + 1);
   c.take<int>(4);
-  return c.bytes() + scan_temp_bytes(n);
+  return c.bytes() + scan_temp_bytes(n + 1);
 }
 
-void launch_union_edges(const int* nbr, const int* lg, int n, int k, int* ea, int* eb,
-                        long long* d_m, void* temp, hipStream_t st) {
+size_t edges_public_bytes(long long n, int k) {
+  Carver c(nullptr);
+  c.take<int>(n * k);
+  c.take<int>(n * k);
+  c.take<int>(n + 1);
+  return c.bytes() + edges_temp_bytes(n, k);
+}
+
+void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es, long long* d_m,
+                        void* temp, hipStream_t st) {
   Carver c(temp);
   unsigned char* flag = c.take<unsigned char>((long long)n * k);
-  int* cnt = c.take<int>(n);
-  int* off = c.take<int>(n);
+  int* cnt = c.take<int>(n + 1);
   int* tot = c.take<int>(4);
+  int* ideg = c.take<int>(n + 1);
   void* stemp = (char*)temp + c.bytes();
-  k_edge_flags<<<blocks_for(n, 256), 256, 0, st>>>(nbr, lg, n, k, flag, cnt);
+  const long long slots = (long long)n * k;
+  // rows read as int4 when every row start is 16-byte aligned
+  const int vec4 = (k % 4 == 0) && ((uintptr_t)nbr % 16 == 0);
+  k_edge_flags<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, lg, n, k, vec4, flag);
   NG_LAUNCH_CHECK();
-  scan_exclusive_i32(cnt, off, n, tot, stemp, st);
-  k_edge_emit<<<blocks_for(n, 256), 256, 0, st>>>(nbr, lg, n, k, flag, off, ea, eb);
+  k_edge_count<<<blocks_for(n + 1, 256), 256, 0, st>>>(flag, n, k, cnt);
   NG_LAUNCH_CHECK();
-  k_to_i64<<<1, 64, 0, st>>>(tot, d_m);
+  scan_exclusive_i32(cnt, es.eoff, n + 1, tot, stemp, st);
+  if (es.ioff) fill_i32(ideg, 0, n + 1, st);
+  k_edge_emit<<<blocks_for(n, 256), 256, 0, st>>>(nbr, n, k, flag, es.eoff, es.src, es.tgt,
+                                                  ideg, es.ioff ? es.islot : nullptr);
+  NG_LAUNCH_CHECK();
+  if (es.ioff) {
+    scan_exclusive_i32(ideg, es.ioff, n + 1, nullptr, stemp, st);
+    k_add_offsets<<<blocks_for(n + 1, 256), 256, 0, st>>>(es.eoff, es.ioff, n + 1, es.aoff);
+    NG_LAUNCH_CHECK();
+  }
+  if (d_m) {
+    k_to_i64<<<1, 64, 0, st>>>(tot, d_m);
+    NG_LAUNCH_CHECK();
+  }
+}
+
+void union_edges_public(const int* nbr, int n, int k, int* ei, int* ej, long long* d_m,
+                        void* ws, hipStream_t st) {
+  Carver c(ws);
+  EdgeSet es{};
+  es.src = c.take<int>((long long)n * k);
+  es.tgt = c.take<int>((long long)n * k);
+  es.eoff = c.take<int>(n + 1);
+  void* temp = (char*)ws + c.bytes();
+  launch_union_edges(nbr, nullptr, n, k, es, d_m, temp, st);
+  // the total sits at eoff[n]
+  unsigned b = blocks_for((long long)n * k, 256);
+  if (b > 4096) b = 4096;
+  k_edge_minmax<<<b, 256, 0, st>>>(es.src, es.tgt, es.eoff + n, ei, ej);
   NG_LAUNCH_CHECK();
 }
 

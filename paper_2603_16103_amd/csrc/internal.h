@@ -73,6 +73,42 @@ NG_DEV uint32_t f2ord(float f) {
 
 NG_DEV int lane_id() { return (int)(threadIdx.x & 63); }
 
+NG_DEV float ord2f(unsigned u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+NG_DEV unsigned spread10(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 30-bit Morton key of a point on the 1024^3 grid over the bounding cube
+// whose per-axis bounds box[0..2] (min) and box[3..5] (max) are stored as
+// f2ord values.  Points outside the box clamp to its faces.
+NG_DEV unsigned morton_key(float x, float y, float z, const unsigned* box) {
+  float lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord2f(box[a]);
+    hi[a] = ord2f(box[3 + a]);
+  }
+  const float ext = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
+  const float v[3] = {x, y, z};
+  unsigned q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float t = (v[a] - lo[a]) * sc;
+    t = fminf(fmaxf(t, 0.f), 1023.f);  // NaN -> 0
+    q[a] = (unsigned)t;
+  }
+  return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers (each defined in the .hip file named in the comment)
 // ---------------------------------------------------------------------------
@@ -129,65 +165,104 @@ size_t knn_tree_bytes(long long n);
 // Morton keys of the centres over their bounding cube (10 bits per axis).
 void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
                         void* temp, hipStream_t st);
-// Exact kNN over the splats in working order.  Output nbr[p][k] holds the
-// PHYSICAL indices of the k_eff nearest (key (d2, logical)); -1 padded.
-// Two steps sharing tree_mem: boxes (+ logical -> working inverse), then the
-// query.
-void knn_working_tree(const float4* cen, int n, void* tree_mem, hipStream_t st);
-void knn_working_query(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
-                       hipStream_t st);
+// Exact kNN over the splats in working order, which must be sorted by the
+// Morton key of the centres over `box` (the bounds written by
+// launch_morton_keys).  Output nbr[p][k] holds the PHYSICAL indices of the
+// k_eff nearest (key (d2, logical)); -1 padded.  Two steps sharing tree_mem:
+// the cell table (+ logical -> working inverse; *d_unsorted is or-ed with 1
+// if the order is violated), then the query.
+void knn_working_tree(const float4* cen, int n, const unsigned* box, void* tree_mem,
+                      int* d_unsorted, hipStream_t st);
+void knn_working_query(const float4* cen, int n, int k, int keff, const unsigned* box, int* nbr,
+                       void* tree_mem, hipStream_t st);
 // Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
 size_t knn_plain_bytes(long long n);
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);
 
-// edges.hip -- union edges
+// edges.hip -- union edges and the incidence structure of the selection
+struct EdgeSet {
+  int* src;    // [n*k] emitting row of edge e (physical)
+  int* tgt;    // [n*k] the listed neighbour (physical)
+  int* eoff;   // [n+1] first edge of each row; eoff[n] = m
+  int* ioff;   // [n+1] start of each splat's incoming edges (nullable: none)
+  int* islot;  // [n*k] rank of e among the edges into tgt[e]
+  int* aoff;   // [n+1] eoff + ioff: adjacency range of each splat
+};
 size_t edges_temp_bytes(long long n, int k);
-// ea/eb: edges with lg[ea] < lg[eb] (lg nullable: identity).  Count written
-// to *d_m (int64, device) and returned through temp for the host.
-void launch_union_edges(const int* nbr, const int* lg, int n, int k, int* ea, int* eb,
-                        long long* d_m, void* temp, hipStream_t st);
+// Emits the union edges of the lists in nbr (entries < 0 skipped) in
+// emission order; order between the two ends by lg (nullable: identity).
+// The count goes to *d_m (device int64, nullable) and to es.eoff[n].
+void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es, long long* d_m,
+                        void* temp, hipStream_t st);
+// Stage entry point: ei < ej in the caller's numbering, emission order.
+size_t edges_public_bytes(long long n, int k);
+void union_edges_public(const int* nbr, int n, int k, int* ei, int* ej, long long* d_m, void* ws,
+                        hipStream_t st);
 
 // cost.hip -- per-splat precompute and the edge cost
 struct CrnArgs {
   int S;
   float v[16][4];
 };
+// Adjacency entries written by the cost kernels: each edge (src, tgt) puts
+// key (orderable cost << 32 | logical index of the other end) and the other
+// end's physical index at both ends' positions (see edges.hip).
+struct AdjOut {
+  const int* eoff;
+  const int* ioff;
+  const int* islot;
+  unsigned long long* akey;
+  int* au;
+};
 void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st);
 // FP32 cost of edges [0, m); edges needing FP64 are appended to fb_list.
-// Edges with an end outside [0, n) get a NaN cost.
+// Edges with an end outside [0, n) get a NaN cost.  orient: the end with the
+// smaller logical index (cen[].w) is the mixture's first component;
+// otherwise ea[e] is.  adj.akey nullable.
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
-                      const int* ea, const int* eb, int m, int n, const CrnArgs& crn,
-                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
-                      hipStream_t st);
+                      const int* ea, const int* eb, int m, int n, bool orient,
+                      const CrnArgs& crn, float fb_ratio, float* cost, float* dgeo, int* fb_list,
+                      int* fb_count, AdjOut adj, hipStream_t st);
 // FP64 cost of the listed edges (list nullable: all edges [0, count_host)).
 void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
-                           const int* ea, const int* eb, int n, const int* list,
+                           const int* ea, const int* eb, int n, bool orient, const int* list,
                            const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
-                           float* dgeo, hipStream_t st);
+                           float* dgeo, AdjOut adj, hipStream_t st);
 
 // select.hip -- greedy disjoint pairs by locally-dominant matching
+struct Adjacency {
+  int* aoff;                 // [n+1]
+  unsigned long long* akey;  // [aoff[n]]
+  int* au;                   // [aoff[n]]
+};
 size_t select_temp_bytes(long long n, long long m);
+size_t select_adj_bytes(long long n, long long m);
+// Adjacency of an arbitrary edge list (cost per edge, caller numbering).
+void build_adjacency(const int* ea, const int* eb, const float* cost, long long m, int n,
+                     Adjacency* adj, void* ws, hipStream_t st);
 struct SelectResult {
   long long pairs;
   int iters;
 };
-// partner[n] (physical); key tie-break on lg (nullable: identity).  Edges
-// with an end outside [0, n) are ignored.  d_npairs (nullable, device int64)
-// receives the pair count.  Synchronises st.
-SelectResult select_pairs(const int* ea, const int* eb, const float* cost, long long m, int n,
-                          const int* lg, long long max_pairs, int* partner, void* temp,
-                          hipStream_t st, long long* d_npairs);
+// partner[n] (physical); pair tie-break on lg (nullable: identity).
+// d_npairs (nullable, device int64) receives the pair count.  Synchronises st.
+SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long max_pairs,
+                          int* partner, void* temp, hipStream_t st, long long* d_npairs);
 
 // merge.hip -- MPMM merge + stable compaction in working layout
 size_t merge_temp_bytes(long long n);
-// Returns the new count.  lg nullable (identity).  Writes the provenance pairs
+// Returns the new count.  lg nullable (identity).  morton_box nullable: when
+// given (the bounds written by launch_morton_keys), the output rows are
+// placed in Morton order of the output centres (the physical order of the
+// working set is free; the logical numbering is unaffected); otherwise
+// survivors keep their relative order.  Writes the provenance pairs
 // (min origin, max origin) of the merges to trace (nullable) in the order of
 // the lower logical index.
 // Synchronises st.
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
-                        hipStream_t st, int* d_nout_i32);
+                        hipStream_t st, int* d_nout_i32, const unsigned* morton_box);
 
 // crn.cpp
 void crn_host(uint64_t seed, int round, int S, float* out);

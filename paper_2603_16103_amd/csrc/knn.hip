@@ -1,22 +1,24 @@
 // Exact k-nearest-neighbour graph over splat centres (Sec. 3.1).
 //
-// Spatial structure: the splats sit in the working array in (near) Morton
-// order; consecutive runs of 16 form leaf buckets, and a complete binary tree
-// over the buckets (heap numbering: root 1, children 2i and 2i+1, leaves from
-// nb2) stores an axis-aligned box per node.  The tree is correct for ANY
-// order of the array (boxes are computed from the points); Morton order only
-// keeps the boxes tight.  Rebuilding it costs one pass over the centres, so it
-// is rebuilt every round without re-sorting.
+// Spatial structure: the working array is kept sorted by the 30-bit Morton
+// key of the centres (quantised on a 1024^3 grid over the bounding cube), so
+// every octree cell is a contiguous range of rows; a table of cell starts at
+// one level gives the range of any cell.  Consecutive runs of 16 rows also
+// form the leaves of a complete binary tree of bounding boxes (heap
+// numbering: root 1, children 2i and 2i+1, leaves from nb2).
 //
-// Query: one thread per query splat, consecutive threads = neighbouring
-// splats, so the lanes of a wave walk nearly the same nodes.  The k best
-// (d2, logical index) pairs live in registers, sorted.  The query's own
-// bucket and its two neighbours in the array seed the list, then a stackless
-// left-first walk visits every node whose box is within the current k-th
-// distance (<=, so exact ties are still resolved by index).  Distances and
-// box bounds are double, evaluated as ((dx*dx + dy*dy) + dz*dz) without
-// contraction: the box bound never exceeds the distance of a point inside the
-// box (rounding is monotone), so pruning is exact.
+// Query, in two kernels: queries whose own finest-level cell holds at least
+// k+1 rows (dense surroundings) search that cell and rings of neighbouring
+// cells, skipping cells beyond the current k-th distance, and stop when the
+// k-th distance is inside the searched block (cells are disjoint, so every
+// unseen row is farther); the other queries walk the tree bottom-up from
+// their own leaf.  Candidates are screened in float against a bound derived
+// from the current k-th key (never rejecting a point that the exact key would
+// keep); survivors get the exact key (d2, logical index) with d2 =
+// ((dx*dx + dy*dy) + dz*dz) in double without contraction and a sorted
+// insertion into the k best, kept in registers.  The result is the exact kNN
+// with ties broken by index.
+#include <algorithm>
 #include <climits>
 
 #include "internal.h"
@@ -27,8 +29,10 @@ namespace {
 constexpr int LEAF = 16;
 
 // ---- Morton keys -----------------------------------------------------------
-__global__ void k_bbox(const float* __restrict__ xyz3, const float4* __restrict__ cen4, int n,
-                       unsigned* __restrict__ box) {
+__global__ void __launch_bounds__(256)
+k_bbox(const float* __restrict__ xyz3, const float4* __restrict__ cen4, int n,
+       unsigned* __restrict__ box) {
+  __shared__ float red[4][6];
   float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     float v[3];
@@ -55,40 +59,31 @@ __global__ void k_bbox(const float* __restrict__ xyz3, const float4* __restrict_
       mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], d, 64));
     }
   }
+  const int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      atomicMin(&box[a], f2ord(mn[a]));
-      atomicMax(&box[3 + a], f2ord(mx[a]));
+      red[w][a] = mn[a];
+      red[w][3 + a] = mx[a];
     }
   }
-}
-
-NG_DEV float ord2f(unsigned u) {
-  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
-
-NG_DEV unsigned spread10(unsigned v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
+  __syncthreads();
+  // one atomic per block and bound (the per-wave values are combined first)
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    float v = red[0][a];
+    for (int j = 1; j < 4; ++j) v = a < 3 ? fminf(v, red[j][a]) : fmaxf(v, red[j][a]);
+    if (a < 3)
+      atomicMin(&box[a], f2ord(v));
+    else
+      atomicMax(&box[a], f2ord(v));
+  }
 }
 
 __global__ void k_morton(const float* __restrict__ xyz3, const float4* __restrict__ cen4, int n,
                          const unsigned* __restrict__ box, unsigned* __restrict__ keys) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = ord2f(box[a]);
-    hi[a] = ord2f(box[3 + a]);
-  }
-  float ext = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
-  float sc = ext > 0.f ? 1023.0f / ext : 0.f;
   float v[3];
   if (cen4) {
     float4 c = cen4[i];
@@ -100,14 +95,7 @@ __global__ void k_morton(const float* __restrict__ xyz3, const float4* __restric
     v[1] = xyz3[3 * (long long)i + 1];
     v[2] = xyz3[3 * (long long)i + 2];
   }
-  unsigned q[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float t = (v[a] - lo[a]) * sc;
-    t = fminf(fmaxf(t, 0.f), 1023.f);
-    q[a] = (unsigned)t;
-  }
-  keys[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  keys[i] = morton_key(v[0], v[1], v[2], box);
 }
 
 __global__ void k_iota(int* v, int n) {
@@ -177,6 +165,37 @@ k_tree_levels(const float4* __restrict__ cen, int n, int lc, int levels,
   }
 }
 
+// ---- cell table ------------------------------------------------------------
+// The working array is sorted by the 30-bit Morton key of the centres, so
+// every octree cell (a Morton prefix of 3L bits at level L) is a contiguous
+// range of rows.  The table holds, for every cell c of level LT, the first row
+// whose level-LT cell is >= c (cstart[ncells] = n); a cell of a coarser level
+// L is the range [cstart[c << 3(LT-L)], cstart[(c+1) << 3(LT-L)]).
+
+// hist[c] = rows in level-LT cell c, from the run boundaries of the sorted
+// keys (each run adds its end and subtracts its start); flags a key that is
+// smaller than its predecessor.
+__global__ void k_cell_runs(const float4* __restrict__ cen, int n, const unsigned* __restrict__ box,
+                            int shift, int* __restrict__ hist, int* __restrict__ unsorted) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 c = cen[i];
+  const unsigned key = morton_key(c.x, c.y, c.z, box);
+  const unsigned cell = key >> shift;
+  unsigned prev_key = 0u, next_cell = ~0u;
+  if (i > 0) {
+    const float4 a = cen[i - 1];
+    prev_key = morton_key(a.x, a.y, a.z, box);
+  }
+  if (i + 1 < n) {
+    const float4 b = cen[i + 1];
+    next_cell = morton_key(b.x, b.y, b.z, box) >> shift;
+  }
+  if (i > 0 && prev_key > key) atomicOr(unsorted, 1);
+  if (i == 0 || (prev_key >> shift) != cell) atomicAdd(&hist[cell], -i);
+  if (next_cell != cell) atomicAdd(&hist[cell], i + 1);
+}
+
 // ---- query -----------------------------------------------------------------
 NG_DEV double dist2(double qx, double qy, double qz, float x, float y, float z) {
 #pragma clang fp contract(off)
@@ -186,12 +205,13 @@ NG_DEV double dist2(double qx, double qy, double qz, float x, float y, float z) 
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-NG_DEV double box_dist2(double qx, double qy, double qz, float4 lo, float4 hi) {
-#pragma clang fp contract(off)
-  double gx = fmax(fmax((double)lo.x - qx, qx - (double)hi.x), 0.0);
-  double gy = fmax(fmax((double)lo.y - qy, qy - (double)hi.y), 0.0);
-  double gz = fmax(fmax((double)lo.z - qz, qz - (double)hi.z), 0.0);
-  return (gx * gx + gy * gy) + gz * gz;
+// Float admission bound from the exact k-th key: every point whose double
+// distance is <= d has a float distance <= the returned value.  The float
+// evaluation rounds at most five times (relative 5 * 2^-24 on a squared
+// distance), the conversion once more; 1.0000025 (about 42 * 2^-24) covers it.
+NG_DEV float admit_bound(double d) {
+  const float t = (float)d;
+  return t * 1.0000025f;
 }
 
 template <int K>
@@ -211,7 +231,7 @@ struct Best {
   }
   // sorted insertion; the caller checked that (dc, lc) beats entry K-1
   NG_DEV void insert(double dc, int lc) {
-    bool lt_next = less(dc, lc, d[K - 1], l[K - 1]);  // == true
+    bool lt_next = true;
 #pragma unroll
     for (int t = K - 1; t > 0; --t) {
       const bool lt_prev = less(dc, lc, d[t - 1], l[t - 1]);
@@ -232,71 +252,282 @@ struct Best {
   }
 };
 
+// Geometry of the quantisation grid shared with morton_key: a point v lies in
+// fine cell floor((v - lo) * sc) (clamped to [0, 1023]) per axis.
+struct Grid {
+  double lo[3];
+  double inv_sc;  // real length of one fine cell
+  double margin;  // slack for the float rounding of the quantisation
+};
+
+NG_DEV Grid grid_from_box(const unsigned* box) {
+  Grid g;
+  float lof[3], hif[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lof[a] = ord2f(box[a]);
+    hif[a] = ord2f(box[3 + a]);
+    g.lo[a] = lof[a];
+  }
+  const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
+  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
+  g.inv_sc = sc > 0.f ? 1.0 / (double)sc : 0.0;
+  // the quantised coordinate of a point is within 3 float roundings
+  // (relative) of the exact one: a few 1e-7 of a cell span; 1e-5 of the
+  // extent (plus an absolute floor) covers it
+  g.margin = 1e-5 * (double)ext + 1e-30;
+  return g;
+}
+
+NG_DEV unsigned quant(float v, float lo, float sc) {
+  float t = (v - lo) * sc;
+  t = fminf(fmaxf(t, 0.f), 1023.f);
+  return (unsigned)t;
+}
+
+// Exact k-NN of one query over the cell table at the finest level LT, for
+// queries whose own cell holds at least K + 1 rows (so the own cell alone
+// fills the list and the k-th distance is at most the cell's diagonal: the
+// search never needs more than rings 1 and 2); the others are flagged in
+// sparse_flag for k_knn_tree.  Search:
+// the query's own cell, then rings R = 1, 2, ... of level-L cells (the cells
+// at Chebyshev distance R), skipping cells whose box (widened by the
+// quantisation margin) is beyond the current k-th key.  After ring R the
+// block of (2R+1)^3 cells around the query's cell has been searched; the
+// search stops once the k-th key is closer than the block's boundary (faces
+// on the grid's outer boundary do not count: no row lies beyond them), since
+// every row outside the block is then farther.  Cells are disjoint, so no row
+// is seen twice.
 template <int K>
-__global__ void __launch_bounds__(256)
-k_knn_query(const float4* __restrict__ cen, int n, int keff, int k_out, int nb, int nb2,
-            const float4* __restrict__ bmin, const float4* __restrict__ bmax,
-            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr) {
+__global__ void __launch_bounds__(64)
+k_knn_grid(const float4* __restrict__ cen, int n, int keff, int k_out,
+           const unsigned* __restrict__ box, int LT, const int* __restrict__ cstart,
+           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
+           int* __restrict__ sparse_flag) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float4 cq = cen[p];
   const double qx = cq.x, qy = cq.y, qz = cq.z;
-  const int ql = __float_as_int(cq.w);
+  const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
+  const Grid g = grid_from_box(box);
+  float lof[3], hif[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lof[a] = ord2f(box[a]);
+    hif[a] = ord2f(box[3 + a]);
+  }
+  const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
+  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
+  const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc), quant(qzf, lof[2], sc)};
+
+  // Queries whose own finest-level cell holds fewer than K + 1 rows (sparse
+  // surroundings) go to the tree search instead.
+  const int L = LT;
+  {
+    const unsigned mc = (spread10(qi[0] >> (10 - L)) << 2) | (spread10(qi[1] >> (10 - L)) << 1) |
+                        spread10(qi[2] >> (10 - L));
+    const int cnt = cstart[mc + 1] - cstart[mc];
+    const bool sparse = cnt < K + 1 && sc > 0.f;
+    sparse_flag[p] = sparse ? 1 : 0;
+    if (sparse) return;
+  }
+  const int s = 10 - L;
+  const int G = 1 << L;
+  const int sub = 3 * (LT - L);
+  const double side = (double)(1 << s) * g.inv_sc;
+  const int cx = (int)(qi[0] >> s), cy = (int)(qi[1] >> s), cz = (int)(qi[2] >> s);
+
   Best<K> best;
   best.init();
-
-  const int myleaf = p / LEAF;
-  const int lo_leaf = myleaf > 0 ? myleaf - 1 : 0;
-  const int hi_leaf = myleaf + 1 < nb ? myleaf + 1 : nb - 1;
-  {
-    const int j1 = min((hi_leaf + 1) * LEAF, n);
-    for (int j = lo_leaf * LEAF; j < j1; ++j) {
-      if (j == p) continue;
-      float4 c = cen[j];
-      best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
+  float thr = INFINITY;
+  auto scan = [&](int a, int b) {
+    for (int j = a; j < b; ++j) {
+      const float4 c = cen[j];
+      const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
+      if (dx * dx + dy * dy + dz * dz <= thr && j != p)
+        best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
     }
+    thr = admit_bound(best.d[K - 1]);
+  };
+  auto cell_range = [&](int x, int y, int z, int& a, int& b) {
+    const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                        spread10((unsigned)z);
+    const unsigned f = mc << sub;
+    a = cstart[f];
+    b = cstart[f + (1u << sub)];
+  };
+  {
+    int a, b;
+    cell_range(cx, cy, cz, a, b);
+    scan(a, b);
   }
-
-  unsigned node = 1;
-  while (true) {
-    bool descend = false;
-    const float4 lo = bmin[node], hi = bmax[node];
-    if (lo.x <= hi.x && box_dist2(qx, qy, qz, lo, hi) <= best.d[K - 1]) {
-      if (node >= (unsigned)nb2) {
-        const int leaf = (int)(node - (unsigned)nb2);
-        if (leaf < lo_leaf || leaf > hi_leaf) {
-          const int j0 = leaf * LEAF;
-          const int j1 = min(j0 + LEAF, n);
-          for (int j = j0; j < j1; ++j) {
-            float4 c = cen[j];
-            best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
-          }
+  // a zero-extent grid has every row in one cell: the own cell was all
+  for (int R = 1; sc > 0.f; ++R) {
+    for (int dx = -R; dx <= R; ++dx) {
+      const int x = cx + dx;
+      if (x < 0 || x >= G) continue;
+      for (int dy = -R; dy <= R; ++dy) {
+        const int y = cy + dy;
+        if (y < 0 || y >= G) continue;
+        const bool edge_xy = dx == -R || dx == R || dy == -R || dy == R;
+        for (int dz = -R; dz <= R; dz += (edge_xy ? 1 : 2 * R)) {
+          const int z = cz + dz;
+          if (z < 0 || z >= G) continue;
+          // distance from the query to the cell's widened box, in double
+          const double bx0 = g.lo[0] + x * side - g.margin, bx1 = g.lo[0] + (x + 1) * side + g.margin;
+          const double by0 = g.lo[1] + y * side - g.margin, by1 = g.lo[1] + (y + 1) * side + g.margin;
+          const double bz0 = g.lo[2] + z * side - g.margin, bz1 = g.lo[2] + (z + 1) * side + g.margin;
+          const double gx = fmax(fmax(bx0 - qx, qx - bx1), 0.0);
+          const double gy = fmax(fmax(by0 - qy, qy - by1), 0.0);
+          const double gz = fmax(fmax(bz0 - qz, qz - bz1), 0.0);
+          const double bd = (gx * gx + gy * gy) + gz * gz;
+          if (bd > best.d[K - 1] * (1.0 + 1e-12)) continue;
+          int a, b;
+          cell_range(x, y, z, a, b);
+          if (b > a) scan(a, b);
         }
-      } else {
-        descend = true;
       }
     }
-    if (descend) {
-      node = 2 * node;
-    } else {
-      const unsigned t = __builtin_ctz(node + 1);
-      const unsigned anc = node >> t;
-      if (anc == 0) break;
-      node = anc + 1;
-    }
+    // distance from the query to the boundary of the searched block (shrunk
+    // by the margin); faces on the grid boundary are open
+    double rho = INFINITY;
+    if (cx - R > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - R) * side + g.margin));
+    if (cx + R + 1 < G) rho = fmin(rho, (g.lo[0] + (cx + R + 1) * side - g.margin) - qx);
+    if (cy - R > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - R) * side + g.margin));
+    if (cy + R + 1 < G) rho = fmin(rho, (g.lo[1] + (cy + R + 1) * side - g.margin) - qy);
+    if (cz - R > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - R) * side + g.margin));
+    if (cz + R + 1 < G) rho = fmin(rho, (g.lo[2] + (cz + R + 1) * side - g.margin) - qz);
+    if (!(rho < INFINITY)) break;  // the block covers the whole grid
+    if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.d[K - 1]) break;
   }
 
-  const long long row = rows_logical ? (long long)ql : (long long)p;
+  const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
   int* out = nbr + row * k_out;
 #pragma unroll
   for (int t = 0; t < K; ++t) {
     if (t < k_out) {
-      int v = -1;
-      if (t < keff) v = inv ? inv[best.l[t]] : best.l[t];
-      out[t] = v;
+      int o = -1;
+      if (t < keff) o = inv ? inv[best.l[t]] : best.l[t];
+      out[t] = o;
     }
   }
   for (int t = K; t < k_out; ++t) out[t] = -1;
+}
+
+// ---- sparse queries ------------------------------------------------------------
+NG_DEV float box_d2f(float qx, float qy, float qz, float4 lo, float4 hi) {
+  const float gx = fmaxf(fmaxf(lo.x - qx, qx - hi.x), 0.f);
+  const float gy = fmaxf(fmaxf(lo.y - qy, qy - hi.y), 0.f);
+  const float gz = fmaxf(fmaxf(lo.z - qz, qz - hi.z), 0.f);
+  return gx * gx + gy * gy + gz * gz;
+}
+
+template <int K>
+struct Query {
+  double qx, qy, qz;
+  float qxf, qyf, qzf;
+  int p;
+  Best<K> best;
+  float thr;
+
+  NG_DEV void scan_leaf(const float4* __restrict__ cen, int n, int leaf) {
+    const int j0 = leaf * LEAF;
+    const int j1 = min(j0 + LEAF, n);
+    unsigned mask = 0u;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+      const float4 c = cen[j];
+      const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
+      const bool pass = dx * dx + dy * dy + dz * dz <= thr && j != p;
+      mask |= (unsigned)pass << (j - j0);
+    }
+    if (mask == 0u) return;
+    while (mask) {
+      const int u = __builtin_ctz(mask);
+      mask &= mask - 1;
+      const float4 c = cen[j0 + u];
+      best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
+    }
+    thr = admit_bound(best.d[K - 1]);
+  }
+};
+
+// Exact k-NN of the sparse queries (listed in working order), walking the
+// tree bottom-up: scan the query's own leaf, then for each ancestor v (leaf
+// upwards, up to the root) search the subtree of v's sibling; together these
+// subtrees cover every leaf.  (Boxes of different subtrees may overlap, so no
+// early stop is taken on containment; a far sibling costs one box test.)
+// Each sibling subtree is walked depth-first, left child first, without a
+// stack (heap numbering gives the next node), skipping every node whose box
+// is beyond the current bound.  Each lane advances its walk until it finds a
+// leaf to scan (or finishes); the lanes then scan their leaves together,
+// which keeps the expensive part of the loop in step.
+template <int K>
+__global__ void __launch_bounds__(64)
+k_knn_tree(const float4* __restrict__ cen, int n, int keff, int k_out, int nb2,
+           const float4* __restrict__ bmin, const float4* __restrict__ bmax,
+           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
+           const int* __restrict__ list, const int* __restrict__ d_count) {
+  const int count = *d_count;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int p = list[i];
+    const float4 cq = cen[p];
+    Query<K> Q;
+    Q.qx = cq.x;
+    Q.qy = cq.y;
+    Q.qz = cq.z;
+    Q.qxf = cq.x;
+    Q.qyf = cq.y;
+    Q.qzf = cq.z;
+    Q.p = p;
+    Q.best.init();
+    Q.thr = INFINITY;
+    Q.scan_leaf(cen, n, p / LEAF);
+    unsigned v = (unsigned)nb2 + (unsigned)(p / LEAF);
+    bool done = v <= 1u;
+    unsigned s = v ^ 1u, node = s;
+    while (true) {
+      int leaf = -1;
+      while (!done && leaf < 0) {
+        const float4 lo = bmin[node], hi = bmax[node];
+        const bool hit = lo.x <= hi.x && box_d2f(Q.qxf, Q.qyf, Q.qzf, lo, hi) <= Q.thr;
+        if (hit && node < (unsigned)nb2) {
+          node = 2u * node;  // descend, left child first
+          continue;
+        }
+        if (hit) leaf = (int)(node - (unsigned)nb2);
+        // next node of the subtree in depth-first order, or the next ancestor
+        while (node != s && (node & 1u)) node >>= 1;
+        if (node == s) {
+          v >>= 1;
+          done = v <= 1u;
+          s = v ^ 1u;
+          node = s;
+        } else {
+          node += 1u;
+        }
+      }
+      if (leaf >= 0) Q.scan_leaf(cen, n, leaf);
+      if (__ballot(!done) == 0ull) break;
+    }
+    const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
+    int* out = nbr + row * k_out;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      if (t < k_out) {
+        int o = -1;
+        if (t < keff) o = inv ? inv[Q.best.l[t]] : Q.best.l[t];
+        out[t] = o;
+      }
+    }
+    for (int t = K; t < k_out; ++t) out[t] = -1;
+  }
+}
+
+__global__ void k_scatter_flagged(const int* __restrict__ flag, const int* __restrict__ pos, int n,
+                                  int* __restrict__ list) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n && flag[p]) list[pos[p]] = p;
 }
 
 __global__ void k_invert(const float4* __restrict__ cen, int n, int* __restrict__ inv) {
@@ -342,33 +573,106 @@ void build_tree(const float4* cen, int n, const TreeShape& ts, float4* bmin, flo
   }
 }
 
-void query(const float4* cen, int n, int keff, int k_out, const TreeShape& ts, const float4* bmin,
-           const float4* bmax, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
-  dim3 g(blocks_for(n, 256)), b(256);
-  if (keff <= 8)
-    k_knn_query<8><<<g, b, 0, st>>>(cen, n, keff, k_out, ts.nb, ts.nb2, bmin, bmax, inv,
-                                    rows_logical, nbr);
-  else if (keff <= 16)
-    k_knn_query<16><<<g, b, 0, st>>>(cen, n, keff, k_out, ts.nb, ts.nb2, bmin, bmax, inv,
-                                     rows_logical, nbr);
-  else if (keff <= 24)
-    k_knn_query<24><<<g, b, 0, st>>>(cen, n, keff, k_out, ts.nb, ts.nb2, bmin, bmax, inv,
-                                     rows_logical, nbr);
-  else
-    k_knn_query<32><<<g, b, 0, st>>>(cen, n, keff, k_out, ts.nb, ts.nb2, bmin, bmax, inv,
-                                     rows_logical, nbr);
+// Finest table level: about one level below 8^L ~ n, at most 7 (2M cells).
+int table_level(long long n) {
+  int L = 1;
+  while (L < 7 && (1ll << (3 * L)) < n) ++L;
+  return L;
+}
+
+// Table memory: cell counts, cell starts, the logical -> working inverse and
+// the order-check flag.
+struct TableMem {
+  float4* bmin;
+  float4* bmax;
+  int* hist;
+  int* cstart;
+  int* inv;
+  int* sflag;   // sparse flag per query
+  int* spos;    // its exclusive scan
+  int* sparse;  // sparse queries in working order
+  int* flag;    // [0]: order check (plain entry), [1]: sparse count
+};
+
+TableMem carve_table(void* base, long long n, size_t* bytes = nullptr) {
+  const long long ncells = 1ll << (3 * table_level(n));
+  const TreeShape ts = tree_shape(n);
+  Carver c(base);
+  TableMem t;
+  t.bmin = c.take<float4>(2ll * ts.nb2);
+  t.bmax = c.take<float4>(2ll * ts.nb2);
+  t.hist = c.take<int>(ncells + 1);
+  t.cstart = c.take<int>(ncells + 1);
+  t.inv = c.take<int>(n);
+  t.sflag = c.take<int>(n);
+  t.spos = c.take<int>(n);
+  t.sparse = c.take<int>(n);
+  t.flag = c.take<int>(64);
+  if (bytes) *bytes = c.bytes() + std::max(scan_temp_bytes(ncells + 1), scan_temp_bytes(n));
+  return t;
+}
+
+void build_table(const float4* cen, int n, const unsigned* box, void* mem, int* d_unsorted,
+                 hipStream_t st) {
+  TableMem t = carve_table(mem, n);
+  size_t tb = 0;
+  carve_table(nullptr, n, &tb);
+  void* stemp = (char*)mem + (tb - std::max(scan_temp_bytes((1ll << (3 * table_level(n))) + 1),
+                                            scan_temp_bytes(n)));
+  const int LT = table_level(n);
+  const long long ncells = 1ll << (3 * LT);
+  fill_i32(t.hist, 0, ncells + 1, st);
+  k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, box, 3 * (10 - LT), t.hist,
+                                                  d_unsorted);
   NG_LAUNCH_CHECK();
+  scan_exclusive_i32(t.hist, t.cstart, ncells + 1, nullptr, stemp, st);
+  build_tree(cen, n, tree_shape(n), t.bmin, t.bmax, st);
+}
+
+template <int K>
+void query_k(const float4* cen, int n, int keff, int k_out, const unsigned* box,
+             const TableMem& t, void* stemp, const int* inv, int rows_logical, int* nbr,
+             hipStream_t st) {
+  const int LT = table_level(n);
+  const TreeShape ts = tree_shape(n);
+  k_knn_grid<K><<<blocks_for(n, 64), 64, 0, st>>>(cen, n, keff, k_out, box, LT, t.cstart, inv,
+                                                  rows_logical, nbr, t.sflag);
+  NG_LAUNCH_CHECK();
+  // sparse queries, compacted in working (Morton) order; their count stays
+  // on the device and a grid of fixed size strides over it
+  scan_exclusive_i32(t.sflag, t.spos, n, t.flag + 1, stemp, st);
+  k_scatter_flagged<<<blocks_for(n, 256), 256, 0, st>>>(t.sflag, t.spos, n, t.sparse);
+  NG_LAUNCH_CHECK();
+  unsigned g = blocks_for(n, 64);
+  if (g > 4096) g = 4096;
+  k_knn_tree<K><<<g, 64, 0, st>>>(cen, n, keff, k_out, ts.nb2, t.bmin, t.bmax, inv, rows_logical,
+                                  nbr, t.sparse, t.flag + 1);
+  NG_LAUNCH_CHECK();
+}
+
+void query(const float4* cen, int n, int keff, int k_out, const unsigned* box, void* mem,
+           const int* inv, int rows_logical, int* nbr, hipStream_t st) {
+  const TableMem t = carve_table(mem, n);
+  size_t tb = 0;
+  carve_table(nullptr, n, &tb);
+  void* stemp = (char*)mem + (tb - std::max(scan_temp_bytes((1ll << (3 * table_level(n))) + 1),
+                                            scan_temp_bytes(n)));
+  if (keff <= 8)
+    query_k<8>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
+  else if (keff <= 16)
+    query_k<16>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
+  else if (keff <= 24)
+    query_k<24>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
+  else
+    query_k<32>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
 }
 
 }  // namespace
 
 size_t knn_tree_bytes(long long n) {
-  TreeShape ts = tree_shape(n);
-  Carver c(nullptr);
-  c.take<float4>(2ll * ts.nb2);
-  c.take<float4>(2ll * ts.nb2);
-  c.take<int>(n);
-  return c.bytes();
+  size_t b = 0;
+  carve_table(nullptr, n, &b);
+  return b;
 }
 
 void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
@@ -378,36 +682,29 @@ void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsign
   fill_i32((int*)box, -1, 3, st);
   fill_i32((int*)box + 3, 0, 3, st);
   unsigned b = blocks_for(n, 256);
-  if (b > 1024) b = 1024;
+  if (b > 256) b = 256;
   k_bbox<<<b, 256, 0, st>>>(pos_xyz3, cen4, n, box);
   NG_LAUNCH_CHECK();
   k_morton<<<blocks_for(n, 256), 256, 0, st>>>(pos_xyz3, cen4, n, box, keys);
   NG_LAUNCH_CHECK();
 }
 
-void knn_working_tree(const float4* cen, int n, void* tree_mem, hipStream_t st) {
-  TreeShape ts = tree_shape(n);
-  Carver c(tree_mem);
-  float4* bmin = c.take<float4>(2ll * ts.nb2);
-  float4* bmax = c.take<float4>(2ll * ts.nb2);
-  int* inv = c.take<int>(n);
-  build_tree(cen, n, ts, bmin, bmax, st);
-  k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, inv);
+void knn_working_tree(const float4* cen, int n, const unsigned* box, void* tree_mem,
+                      int* d_unsorted, hipStream_t st) {
+  TableMem t = carve_table(tree_mem, n);
+  build_table(cen, n, box, tree_mem, d_unsorted, st);
+  k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, t.inv);
   NG_LAUNCH_CHECK();
 }
 
-void knn_working_query(const float4* cen, int n, int k, int keff, int* nbr, void* tree_mem,
-                       hipStream_t st) {
-  TreeShape ts = tree_shape(n);
-  Carver c(tree_mem);
-  float4* bmin = c.take<float4>(2ll * ts.nb2);
-  float4* bmax = c.take<float4>(2ll * ts.nb2);
-  int* inv = c.take<int>(n);
-  query(cen, n, keff, k, ts, bmin, bmax, inv, 0, nbr, st);
+void knn_working_query(const float4* cen, int n, int k, int keff, const unsigned* box, int* nbr,
+                       void* tree_mem, hipStream_t st) {
+  TableMem t = carve_table(tree_mem, n);
+  query(cen, n, keff, k, box, tree_mem, t.inv, 0, nbr, st);
 }
 
-// Plain entry: centres in caller order -> sorted copy -> tree -> rows by
-// caller index.
+// Plain entry: centres in caller order -> Morton-sorted copy -> table -> rows
+// by caller index.
 size_t knn_plain_bytes(long long n) {
   Carver c(nullptr);
   c.take<unsigned>(64);
@@ -432,12 +729,10 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   sort_pairs_u32(keys, perm, n, 30, sort_mem, st);
   k_gather_cen<<<blocks_for(n, 256), 256, 0, st>>>(mu, perm, n, cen);
   NG_LAUNCH_CHECK();
-  TreeShape ts = tree_shape(n);
-  Carver t(tree_mem);
-  float4* bmin = t.take<float4>(2ll * ts.nb2);
-  float4* bmax = t.take<float4>(2ll * ts.nb2);
-  build_tree(cen, n, ts, bmin, bmax, st);
-  query(cen, n, keff, k, ts, bmin, bmax, nullptr, 1, nbr, st);
+  TableMem t = carve_table(tree_mem, n);
+  fill_i32(t.flag, 0, 1, st);  // sorted above by the same keys: never set
+  build_table(cen, n, boxmem, tree_mem, t.flag, st);
+  query(cen, n, keff, k, boxmem, tree_mem, nullptr, 1, nbr, st);
 }
 
 }  // namespace ng

@@ -14,6 +14,8 @@
 // Compaction: the merged splat replaces the splat that comes first in the
 // logical order, the other is removed, and survivors keep their relative
 // order, both in the working array and in the logical numbering.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ng {
@@ -159,19 +161,62 @@ __global__ void k_keep_flags(const int* __restrict__ partner, const int* __restr
   remL[lp] = removed ? 1 : 0;
 }
 
+// Mixture weights of a pair (masses w = alpha s0 s1 s2, Eq. vm_weights) and
+// the merged centre rounded to float.  One definition for the sort keys and
+// the merged rows, so the working set is sorted by the keys of its rows.
+NG_DEV void pair_weights(float4 sa, float4 sb, double& pa, double& pb) {
+#pragma clang fp contract(off)
+  const double wa = (double)sa.w * (double)sa.x * (double)sa.y * (double)sa.z;
+  const double wb = (double)sb.w * (double)sb.x * (double)sb.y * (double)sb.z;
+  const double W = wa + wb;
+  pa = W > 0.0 ? wa / W : 0.5;
+  pb = W > 0.0 ? wb / W : 0.5;
+}
+
+NG_DEV float merged_coord(double pa, double pb, float a, float b) {
+#pragma clang fp contract(off)
+  return (float)(pa * (double)a + pb * (double)b);
+}
+
+// Output slot of every kept row (stable order) and, with a Morton box, the
+// sort key of its output centre.
+__global__ void k_out_keys(const float4* __restrict__ cen, const float4* __restrict__ shp, int n,
+                           const int* __restrict__ partner, const int* __restrict__ keep,
+                           const int* __restrict__ newpos, const unsigned* __restrict__ box,
+                           unsigned* __restrict__ keys, int* __restrict__ order) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n || !keep[p]) return;
+  const int q = newpos[p];
+  order[q] = p;
+  if (!box) return;
+  const float4 ca = cen[p];
+  float x = ca.x, y = ca.y, z = ca.z;
+  const int j = partner[p];
+  if (j >= 0 && j < n) {
+    const float4 cb = cen[j];
+    double pa, pb;
+    pair_weights(shp[2 * (long long)p], shp[2 * (long long)j], pa, pb);
+    x = merged_coord(pa, pb, ca.x, cb.x);
+    y = merged_coord(pa, pb, ca.y, cb.y);
+    z = merged_coord(pa, pb, ca.z, cb.z);
+  }
+  keys[q] = morton_key(x, y, z, box);
+}
+
 // float4 desc[q] = (src_a bits, src_b bits, weight_a, weight_b): how output
-// row q of the SH array is formed.
+// row q of the SH array is formed.  Thread per output row q, source row
+// order[q].
 __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restrict__ lg,
                               const float4* __restrict__ shp, const int* __restrict__ org, int n,
-                              const int* __restrict__ partner, const int* __restrict__ keep,
-                              const int* __restrict__ newpos, const int* __restrict__ rsum,
+                              const int* __restrict__ partner, const int* __restrict__ order,
+                              int nout, const int* __restrict__ rsum,
                               float4* __restrict__ cen_o, int* __restrict__ lg_o,
                               float4* __restrict__ shp_o, int* __restrict__ org_o,
                               float4* __restrict__ desc, int* __restrict__ trace,
                               int* __restrict__ trace_count) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n || !keep[p]) return;
-  const int q = newpos[p];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nout) return;
+  const int p = order[q];
   const int lp = logical(lg, p);
   const int newL = lp - rsum[lp];
   const int j = partner[p];
@@ -188,17 +233,13 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
   }
   const float4 cb = cen[j];
   const float4 sb = shp[2 * (long long)j], qb = shp[2 * (long long)j + 1];
-  const double wa = (double)sa.w * (double)sa.x * (double)sa.y * (double)sa.z;
-  const double wb = (double)sb.w * (double)sb.x * (double)sb.y * (double)sb.z;
-  const double W = wa + wb;
-  const double pa = W > 0.0 ? wa / W : 0.5;
-  const double pb = W > 0.0 ? wb / W : 0.5;
+  double pa, pb;
+  pair_weights(sa, sb, pa, pb);
   const double ma[3] = {ca.x, ca.y, ca.z}, mb[3] = {cb.x, cb.y, cb.z};
-  double mm[3], d[3];
-  for (int k = 0; k < 3; ++k) {
-    mm[k] = pa * ma[k] + pb * mb[k];
-    d[k] = ma[k] - mb[k];
-  }
+  const float mf[3] = {merged_coord(pa, pb, ca.x, cb.x), merged_coord(pa, pb, ca.y, cb.y),
+                       merged_coord(pa, pb, ca.z, cb.z)};
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = ma[k] - mb[k];
   const Mat3 Sa = cov_from(sa.x, sa.y, sa.z, qa.x, qa.y, qa.z, qa.w);
   const Mat3 Sb = cov_from(sb.x, sb.y, sb.z, qb.x, qb.y, qb.z, qb.w);
   Mat3 Sm;
@@ -207,7 +248,7 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
     for (int k = 0; k < 3; ++k) Sm.m[i][k] = pa * Sa.m[i][k] + pb * Sb.m[i][k] + c * d[i] * d[k];
   const double am = 1.0 - (1.0 - (double)sa.w) * (1.0 - (double)sb.w);
   const ScaleRot sr = scale_rot_from_cov(Sm);
-  cen_o[q] = make_float4((float)mm[0], (float)mm[1], (float)mm[2], __int_as_float(newL));
+  cen_o[q] = make_float4(mf[0], mf[1], mf[2], __int_as_float(newL));
   lg_o[q] = newL;
   shp_o[2 * (long long)q] = make_float4((float)sr.s[0], (float)sr.s[1], (float)sr.s[2], (float)am);
   shp_o[2 * (long long)q + 1] =
@@ -249,20 +290,24 @@ size_t merge_temp_bytes(long long n) {
   c.take<int>(n);
   c.take<int>(n);
   c.take<int>(n);
+  c.take<unsigned>(n);
+  c.take<int>(n);
   c.take<float4>(n);
   c.take<int>(64);
-  return c.bytes() + scan_temp_bytes(n);
+  return c.bytes() + std::max(scan_temp_bytes(n), sort_temp_bytes(n));
 }
 
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
-                        hipStream_t st, int* d_nout_i32) {
+                        hipStream_t st, int* d_nout_i32, const unsigned* morton_box) {
   Carver c(temp);
   int* keep = c.take<int>(n);
   int* newpos = c.take<int>(n);
   int* remL = c.take<int>(n);
   int* rsum = c.take<int>(n);
+  unsigned* keys = c.take<unsigned>(n);
+  int* order = c.take<int>(n);
   float4* desc = c.take<float4>(n);
   int* counters = c.take<int>(64);
   void* stemp = (char*)temp + c.bytes();
@@ -272,14 +317,21 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   scan_exclusive_i32(keep, newpos, n, counters, stemp, st);
   scan_exclusive_i32(remL, rsum, n, counters + 1, stemp, st);
   if (trace) fill_i32(counters + 2, 0, 1, st);
-  k_merge_attrs<<<blocks_for(n, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, keep, newpos,
-                                                    rsum, cen_o, lg_o, shp_o, org_o, desc, trace,
-                                                    counters + 2);
+  k_out_keys<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, n, partner, keep, newpos, morton_box,
+                                                 keys, order);
   NG_LAUNCH_CHECK();
   NG_HIP(hipMemcpyAsync(host, counters, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (d_nout_i32) NG_HIP(hipMemcpyAsync(d_nout_i32, counters, sizeof(int), hipMemcpyDeviceToDevice, st));
+  if (d_nout_i32)
+    NG_HIP(hipMemcpyAsync(d_nout_i32, counters, sizeof(int), hipMemcpyDeviceToDevice, st));
   NG_HIP(hipStreamSynchronize(st));
   const long long nout = *(int*)host;
+  // Morton order of the output centres (stable: equal keys keep the
+  // compacted order)
+  if (morton_box) sort_pairs_u32(keys, order, nout, 30, stemp, st);
+  k_merge_attrs<<<blocks_for(nout, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order,
+                                                       (int)nout, rsum, cen_o, lg_o, shp_o, org_o,
+                                                       desc, trace, counters + 2);
+  NG_LAUNCH_CHECK();
   k_merge_sh<<<blocks_for(nout * 12, 256), 256, 0, st>>>((const float4*)sh, desc, (int)nout,
                                                          (float4*)sh_o);
   NG_LAUNCH_CHECK();

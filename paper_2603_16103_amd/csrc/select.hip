@@ -5,12 +5,21 @@
 //
 // Without the budget, the scan's result is the unique locally-dominant
 // matching under that strict total order: repeatedly take every live edge
-// that is the smallest at both of its ends, then drop edges touching a taken
-// vertex.  On the edges of one vertex v, the order (cost, i, j) equals the
-// order (cost, other endpoint), so each vertex's minimum is a single 64-bit
-// atomicMin of (orderable cost bits << 32 | logical index of the other end).
-// With a budget the scan keeps exactly the P smallest keys of that matching
-// (later scan decisions never change earlier ones), found by radix select.
+// that is the smallest at both of its ends, then drop the taken vertices.
+// On the edges of one vertex v the order (cost, i, j) equals the order
+// (cost, logical index of the other end), so each adjacency entry carries the
+// 64-bit key (orderable cost bits << 32 | logical index of the other end).
+//
+// Vertex-centric iterations over the incidence ranges (no atomics on keys):
+//   pick : every active vertex takes the smallest key among its entries whose
+//          other end is still free (pick[v] = that end, or -1 if none);
+//   match: v with pick[pick[v]] == v is matched to it (each end writes only
+//          its own partner entry); vertices with pick = -1 can never match and
+//          leave; the rest form the next active list.
+// A vertex picked by an active v is itself active (v is one of its free
+// ends), so pick[] is never read stale.  With a budget the scan keeps exactly
+// the P smallest keys of that matching (later scan decisions never change
+// earlier ones), found by radix select over (cost, i, j).
 #include "internal.h"
 
 namespace ng {
@@ -20,9 +29,8 @@ constexpr unsigned long long KEY_MAX = ~0ull;
 
 NG_DEV int logical(const int* lg, int p) { return lg ? lg[p] : p; }
 
-// Appends `value` for every lane with `flag`, one atomic per wave; slots at
-// or beyond `cap` are counted but not written.
-NG_DEV void append_wave(bool flag, int value, int* list, int* count, int cap) {
+// Appends `value` for every lane with `flag`, one atomic per wave.
+NG_DEV void append_wave(bool flag, int value, int* list, int* count) {
   const unsigned long long m = __ballot(flag);
   if (m == 0) return;
   const int lane = lane_id();
@@ -32,82 +40,130 @@ NG_DEV void append_wave(bool flag, int value, int* list, int* count, int cap) {
   base = __shfl(base, leader, 64);
   if (flag) {
     const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-    const int slot = base + __popcll(below);
-    if (slot < cap) list[slot] = value;
+    list[base + __popcll(below)] = value;
   }
 }
 
-// Filter the previous live list (or all edges when in_list is null), keep the
-// edges whose ends are both free, and post their keys to both ends.
+// ---- generic incidence from an arbitrary edge list (stage entry point) ----
+NG_DEV bool edge_ok(int a, int b, int n) { return a >= 0 && a < n && b >= 0 && b < n && a != b; }
+
+__global__ void k_deg_count(const int* __restrict__ ea, const int* __restrict__ eb, int m, int n,
+                            int* __restrict__ deg) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    const int a = ea[e], b = eb[e];
+    if (!edge_ok(a, b, n)) continue;
+    atomicAdd(&deg[a], 1);
+    atomicAdd(&deg[b], 1);
+  }
+}
+
+NG_DEV unsigned long long entry_key(float c, int other_logical) {
+  if (!isfinite(c)) return KEY_MAX;
+  return ((unsigned long long)f2ord(c) << 32) | (unsigned)other_logical;
+}
+
+__global__ void k_adj_fill(const int* __restrict__ ea, const int* __restrict__ eb,
+                           const float* __restrict__ cost, int m, int n,
+                           const int* __restrict__ aoff, int* __restrict__ cursor,
+                           unsigned long long* __restrict__ akey, int* __restrict__ au) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    const int a = ea[e], b = eb[e];
+    if (!edge_ok(a, b, n)) continue;
+    const float c = cost[e];
+    const int sa = aoff[a] + atomicAdd(&cursor[a], 1);
+    const int sb = aoff[b] + atomicAdd(&cursor[b], 1);
+    akey[sa] = entry_key(c, b);
+    au[sa] = b;
+    akey[sb] = entry_key(c, a);
+    au[sb] = a;
+  }
+}
+
+// ---- matching iterations ----------------------------------------------------
+// act == nullptr: every vertex [0, n) is active.
 __global__ void __launch_bounds__(256)
-k_ld_min(const int* __restrict__ ea, const int* __restrict__ eb, const float* __restrict__ cost,
-         const int* __restrict__ lg, int n, int m_all, const int* __restrict__ in_list,
-         const int* __restrict__ in_count, const int* __restrict__ partner,
-         unsigned long long* __restrict__ best, int* __restrict__ out_list,
-         int* __restrict__ out_count) {
-  const int cnt = in_list ? *in_count : m_all;
-  const int nb = (cnt + 255) / 256;
-  for (int blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-    const int i = blk * 256 + threadIdx.x;
-    bool keep = false;
-    int e = 0;
-    if (i < cnt) {
-      e = in_list ? in_list[i] : i;
-      const int a = ea[e], b = eb[e];
-      const float c = cost[e];
-      keep = a >= 0 && a < n && b >= 0 && b < n && a != b && isfinite(c) && partner[a] < 0 &&
-             partner[b] < 0;
-      if (keep) {
-        const unsigned long long hi = (unsigned long long)f2ord(c) << 32;
-        atomicMin(&best[a], hi | (unsigned)logical(lg, b));
-        atomicMin(&best[b], hi | (unsigned)logical(lg, a));
+k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
+          const int* __restrict__ au, const int* __restrict__ partner,
+          const int* __restrict__ act, const int* __restrict__ act_count, int n,
+          int* __restrict__ pick, unsigned* __restrict__ pcost, int* __restrict__ next_count) {
+  const int cnt = act ? *act_count : n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int v = act ? act[i] : i;
+    unsigned long long best = KEY_MAX;
+    int bu = -1;
+    const int t1 = aoff[v + 1];
+    for (int t = aoff[v]; t < t1; ++t) {
+      const unsigned long long key = akey[t];
+      if (key < best) {
+        const int u = au[t];
+        if (partner[u] < 0) {
+          best = key;
+          bu = u;
+        }
       }
     }
-    append_wave(keep, e, out_list, out_count, m_all);
+    pick[v] = bu;
+    pcost[v] = (unsigned)(best >> 32);
   }
 }
 
-// Take the edges that are the minimum at both ends; clear the next round's
-// minima at the ends of every live edge.
 __global__ void __launch_bounds__(256)
-k_ld_match(const int* __restrict__ ea, const int* __restrict__ eb, const float* __restrict__ cost,
-           const int* __restrict__ lg, const int* __restrict__ list, const int* __restrict__ count,
-           const unsigned long long* __restrict__ best, unsigned long long* __restrict__ best_next,
-           int* __restrict__ partner, int* __restrict__ matched, int* __restrict__ n_matched,
-           int matched_cap) {
-  const int cnt = *count;
-  const int nb = (cnt + 255) / 256;
-  for (int blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-    const int i = blk * 256 + threadIdx.x;
-    bool take = false;
-    int e = 0;
+k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n,
+           const int* __restrict__ pick, const unsigned* __restrict__ pcost,
+           const int* __restrict__ lg, int* __restrict__ partner, int* __restrict__ next_act,
+           int* __restrict__ next_count, int* __restrict__ pair_a, int* __restrict__ pair_b,
+           unsigned* __restrict__ pair_c, int* __restrict__ npairs) {
+  const int cnt = act ? *act_count : n;
+  const int span = (cnt + 255) & ~255;  // whole waves stay in the loop for the ballots
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < span; i += gridDim.x * blockDim.x) {
+    bool keep = false, rec = false;
+    int v = 0, u = -1;
     if (i < cnt) {
-      e = list[i];
-      const int a = ea[e], b = eb[e];
-      const unsigned long long hi = (unsigned long long)f2ord(cost[e]) << 32;
-      take = best[a] == (hi | (unsigned)logical(lg, b)) &&
-             best[b] == (hi | (unsigned)logical(lg, a));
-      if (take) {
-        partner[a] = b;
-        partner[b] = a;
+      v = act ? act[i] : i;
+      u = pick[v];
+      if (u >= 0) {
+        if (pick[u] == v) {
+          partner[v] = u;
+          rec = logical(lg, v) < logical(lg, u);
+        } else {
+          keep = true;
+        }
       }
-      best_next[a] = KEY_MAX;
-      best_next[b] = KEY_MAX;
     }
-    append_wave(take, e, matched, n_matched, matched_cap);
+    append_wave(keep, v, next_act, next_count);
+    // the lower logical end records the pair
+    const unsigned long long m = __ballot(rec);
+    if (m) {
+      const int lane = lane_id();
+      const int leader = __ffsll((long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(npairs, __popcll(m));
+      base = __shfl(base, leader, 64);
+      if (rec) {
+        const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+        const int s = base + __popcll(below);
+        pair_a[s] = v;
+        pair_b[s] = u;
+        pair_c[s] = pcost[v];
+      }
+    }
   }
 }
 
-// Single-workgroup radix select of the P smallest matched edges under
-// (orderable cost, min logical, max logical); keep[i] = 1 for those.
+// ---- budget: keep the P smallest (cost, i, j) of the matching --------------
+// Single workgroup radix select (the matching of the last pass only).
 __global__ void __launch_bounds__(1024)
-k_topp(const int* __restrict__ matched, int M, const int* __restrict__ ea,
-       const int* __restrict__ eb, const float* __restrict__ cost, const int* __restrict__ lg,
-       int P, unsigned char* __restrict__ keep) {
+k_topp(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
+       const unsigned* __restrict__ pair_c, const int* __restrict__ d_M,
+       const int* __restrict__ lg, long long Pll, int* __restrict__ partner) {
   __shared__ int hist[256];
   __shared__ unsigned s_prefix;
   __shared__ int s_need, s_tie_count;
   __shared__ unsigned long long s_prefix2;
+  const int M = *d_M;
+  if ((long long)M <= Pll) return;
+  const int P = (int)Pll;
   if (threadIdx.x == 0) {
     s_prefix = 0u;
     s_need = P;
@@ -119,7 +175,7 @@ k_topp(const int* __restrict__ matched, int M, const int* __restrict__ ea,
     __syncthreads();
     const unsigned pref = s_prefix;
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
-      const unsigned k = f2ord(cost[matched[i]]);
+      const unsigned k = pair_c[i];
       if ((k & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k >> shift) & 255u], 1);
     }
     __syncthreads();
@@ -147,11 +203,10 @@ k_topp(const int* __restrict__ matched, int M, const int* __restrict__ ea,
       __syncthreads();
       const unsigned long long pref = s_prefix2;
       for (int i = threadIdx.x; i < M; i += blockDim.x) {
-        const int e = matched[i];
-        if (f2ord(cost[e]) != T) continue;
-        const unsigned la = (unsigned)logical(lg, ea[e]), lb = (unsigned)logical(lg, eb[e]);
+        if (pair_c[i] != T) continue;
         const unsigned long long k2 =
-            ((unsigned long long)min(la, lb) << 32) | (unsigned long long)max(la, lb);
+            ((unsigned long long)(unsigned)logical(lg, pair_a[i]) << 32) |
+            (unsigned long long)(unsigned)logical(lg, pair_b[i]);
         if ((k2 & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k2 >> shift) & 255ull], 1);
       }
       __syncthreads();
@@ -169,106 +224,133 @@ k_topp(const int* __restrict__ matched, int M, const int* __restrict__ ea,
   }
   const unsigned long long T2 = s_prefix2;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const int e = matched[i];
-    const unsigned k = f2ord(cost[e]);
+    const unsigned k = pair_c[i];
     bool kp = k < T;
     if (k == T) {
-      const unsigned la = (unsigned)logical(lg, ea[e]), lb = (unsigned)logical(lg, eb[e]);
-      const unsigned long long k2 =
-          ((unsigned long long)min(la, lb) << 32) | (unsigned long long)max(la, lb);
+      const unsigned long long k2 = ((unsigned long long)(unsigned)logical(lg, pair_a[i]) << 32) |
+                                    (unsigned long long)(unsigned)logical(lg, pair_b[i]);
       kp = k2 <= T2;
     }
-    keep[i] = kp ? 1 : 0;
+    if (!kp) {
+      partner[pair_a[i]] = -1;
+      partner[pair_b[i]] = -1;
+    }
   }
 }
 
-__global__ void k_unmatch(const int* __restrict__ matched, int M, const int* __restrict__ ea,
-                          const int* __restrict__ eb, const unsigned char* __restrict__ keep,
-                          int* __restrict__ partner) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M || keep[i]) return;
-  const int e = matched[i];
-  partner[ea[e]] = -1;
-  partner[eb[e]] = -1;
-}
-
-__global__ void k_store_i64(const int* __restrict__ v, long long cap, long long* __restrict__ out) {
+__global__ void k_store_npairs(const int* __restrict__ v, long long cap, long long* __restrict__ out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     long long x = *v;
     *out = x < cap ? x : cap;
   }
 }
 
-unsigned grid_for(long long m) {
-  unsigned b = blocks_for(m, 256);
-  return b > 4096 ? 4096 : b;
+unsigned grid_for(long long cnt) {
+  unsigned b = blocks_for(cnt, 256);
+  return b > 8192 ? 8192 : b;
 }
 
 }  // namespace
 
 size_t select_temp_bytes(long long n, long long m) {
   Carver c(nullptr);
-  c.take<unsigned long long>(n);
-  c.take<unsigned long long>(n);
-  c.take<int>(m);
-  c.take<int>(m);
-  c.take<int>(n / 2 + 1);
-  c.take<unsigned char>(n / 2 + 1);
-  c.take<int>(64);
+  c.take<int>(n);                 // pick
+  c.take<unsigned>(n);            // pcost
+  c.take<int>(n);                 // act A
+  c.take<int>(n);                 // act B
+  c.take<int>(n / 2 + 1);         // pair_a
+  c.take<int>(n / 2 + 1);         // pair_b
+  c.take<unsigned>(n / 2 + 1);    // pair_c
+  c.take<int>(64);                // counters
+  (void)m;
   return c.bytes();
 }
 
-SelectResult select_pairs(const int* ea, const int* eb, const float* cost, long long m, int n,
-                          const int* lg, long long max_pairs, int* partner, void* temp,
-                          hipStream_t st, long long* d_npairs) {
+size_t select_adj_bytes(long long n, long long m) {
+  Carver c(nullptr);
+  c.take<int>(n + 1);
+  c.take<int>(n + 1);
+  c.take<int>(n + 1);
+  c.take<unsigned long long>(2 * m);
+  c.take<int>(2 * m);
+  return c.bytes() + scan_temp_bytes(n + 1);
+}
+
+void build_adjacency(const int* ea, const int* eb, const float* cost, long long m, int n,
+                     Adjacency* adj, void* ws, hipStream_t st) {
+  Carver c(ws);
+  int* deg = c.take<int>(n + 1);
+  int* cursor = c.take<int>(n + 1);
+  adj->aoff = c.take<int>(n + 1);
+  adj->akey = c.take<unsigned long long>(2 * m);
+  adj->au = c.take<int>(2 * m);
+  void* stemp = (char*)ws + c.bytes();
+  fill_i32(deg, 0, n + 1, st);
+  fill_i32(cursor, 0, n + 1, st);
+  if (m > 0) {
+    unsigned b = blocks_for(m, 256);
+    if (b > 4096) b = 4096;
+    k_deg_count<<<b, 256, 0, st>>>(ea, eb, (int)m, n, deg);
+    NG_LAUNCH_CHECK();
+  }
+  scan_exclusive_i32(deg, adj->aoff, n + 1, nullptr, stemp, st);
+  if (m > 0) {
+    unsigned b = blocks_for(m, 256);
+    if (b > 4096) b = 4096;
+    k_adj_fill<<<b, 256, 0, st>>>(ea, eb, cost, (int)m, n, adj->aoff, cursor, adj->akey, adj->au);
+    NG_LAUNCH_CHECK();
+  }
+}
+
+SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long max_pairs,
+                          int* partner, void* temp, hipStream_t st, long long* d_npairs) {
   Carver c(temp);
-  unsigned long long* best[2] = {c.take<unsigned long long>(n), c.take<unsigned long long>(n)};
-  int* list[2] = {c.take<int>(m), c.take<int>(m)};
-  int* matched = c.take<int>(n / 2 + 1);
-  unsigned char* keep = c.take<unsigned char>(n / 2 + 1);
-  int* counters = c.take<int>(64);  // [0..1]: live counts, [2]: matched count
+  int* pick = c.take<int>(n);
+  unsigned* pcost = c.take<unsigned>(n);
+  int* act[2] = {c.take<int>(n), c.take<int>(n)};
+  int* pair_a = c.take<int>(n / 2 + 1);
+  int* pair_b = c.take<int>(n / 2 + 1);
+  unsigned* pair_c = c.take<unsigned>(n / 2 + 1);
+  int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs
   long long* host = pinned_host();
 
   fill_i32(partner, -1, n, st);
-  fill_u64(best[0], KEY_MAX, n, st);
   fill_i32(counters, 0, 64, st);
   SelectResult r{0, 0};
-  int cur = 0;
-  long long live = m;
-  for (int it = 0; live > 0; ++it) {
-    int* cnt_out = counters + (it & 1);
-    fill_i32(cnt_out, 0, 1, st);
-    k_ld_min<<<grid_for(live), 256, 0, st>>>(ea, eb, cost, lg, n, (int)m,
-                                             it == 0 ? nullptr : list[cur ^ 1],
-                                             counters + ((it & 1) ^ 1), partner, best[it & 1],
-                                             list[cur], cnt_out);
-    NG_LAUNCH_CHECK();
-    NG_HIP(hipMemcpyAsync(host, cnt_out, sizeof(int), hipMemcpyDeviceToHost, st));
+  long long known = n;  // upper bound of the active count
+  int it = 0;
+  // Iterations run without a host round trip; the host reads the active
+  // count every `batch` iterations (an empty iteration is two tiny launches).
+  const int batch = 4;
+  while (true) {
+    for (int b = 0; b < batch; ++b, ++it) {
+      const int* in_list = it == 0 ? nullptr : act[(it + 1) & 1];
+      const int* in_cnt = counters + ((it + 1) & 1);
+      int* out_list = act[it & 1];
+      int* out_cnt = counters + (it & 1);
+      const unsigned g = grid_for(known);
+      k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n,
+                                   pick, pcost, out_cnt);
+      NG_LAUNCH_CHECK();
+      k_ld_match<<<g, 256, 0, st>>>(in_list, in_cnt, n, pick, pcost, lg, partner, out_list,
+                                    out_cnt, pair_a, pair_b, pair_c, counters + 2);
+      NG_LAUNCH_CHECK();
+    }
+    NG_HIP(hipMemcpyAsync(host, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     NG_HIP(hipStreamSynchronize(st));
-    live = *(int*)host;
-    if (live == 0) break;
-    k_ld_match<<<grid_for(live), 256, 0, st>>>(ea, eb, cost, lg, list[cur], cnt_out, best[it & 1],
-                                               best[(it & 1) ^ 1], partner, matched,
-                                               counters + 2, n / 2 + 1);
-    NG_LAUNCH_CHECK();
-    cur ^= 1;
-    r.iters = it + 1;
+    const int* hc = (const int*)host;
+    known = hc[(it + 1) & 1];  // count produced by the last iteration
+    if (known == 0) break;
   }
-  NG_HIP(hipMemcpyAsync(host, counters + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-  NG_HIP(hipStreamSynchronize(st));
-  long long M = *(int*)host;
-  // duplicate edges in a caller's list can over-count; a matching has at
-  // most n/2 edges
-  if (M > n / 2 + 1) M = n / 2 + 1;
+  r.iters = it;
+  long long M = ((const int*)host)[2];
   if (M > max_pairs) {
-    k_topp<<<1, 1024, 0, st>>>(matched, (int)M, ea, eb, cost, lg, (int)max_pairs, keep);
-    NG_LAUNCH_CHECK();
-    k_unmatch<<<blocks_for(M, 256), 256, 0, st>>>(matched, (int)M, ea, eb, keep, partner);
+    k_topp<<<1, 1024, 0, st>>>(pair_a, pair_b, pair_c, counters + 2, lg, max_pairs, partner);
     NG_LAUNCH_CHECK();
     M = max_pairs;
   }
   if (d_npairs) {
-    k_store_i64<<<1, 64, 0, st>>>(counters + 2, max_pairs, d_npairs);
+    k_store_npairs<<<1, 64, 0, st>>>(counters + 2, max_pairs, d_npairs);
     NG_LAUNCH_CHECK();
   }
   r.pairs = M;
