@@ -96,7 +96,7 @@ typedef struct {
 
 /* Stages timed into nanogs_stats.stage_ms when options.timing is set. */
 #define NANOGS_T_PRECOMPUTE 0 /* per-splat Cholesky factors and weights */
-#define NANOGS_T_KNN_TREE 1   /* bucket tree boxes */
+#define NANOGS_T_KNN_TREE 1   /* cell table of the Morton-sorted centres */
 #define NANOGS_T_KNN_QUERY 2  /* exact kNN query kernel */
 #define NANOGS_T_EDGES 3      /* union edges (flags, scan, emit) */
 #define NANOGS_T_COST 4       /* FP32 edge-cost kernel */

@@ -3,21 +3,21 @@
 // Spatial structure: the working array is kept sorted by the 30-bit Morton
 // key of the centres (quantised on a 1024^3 grid over the bounding cube), so
 // every octree cell is a contiguous range of rows; a table of cell starts at
-// one level gives the range of any cell.  Consecutive runs of 16 rows also
-// form the leaves of a complete binary tree of bounding boxes (heap
-// numbering: root 1, children 2i and 2i+1, leaves from nb2).
+// one level gives the range of any cell at that level or coarser.
 //
-// Query, in two kernels: queries whose own finest-level cell holds at least
-// k+1 rows (dense surroundings) search that cell and rings of neighbouring
-// cells, skipping cells beyond the current k-th distance, and stop when the
-// k-th distance is inside the searched block (cells are disjoint, so every
-// unseen row is farther); the other queries walk the tree bottom-up from
-// their own leaf.  Candidates are screened in float against a bound derived
-// from the current k-th key (never rejecting a point that the exact key would
-// keep); survivors get the exact key (d2, logical index) with d2 =
-// ((dx*dx + dy*dy) + dz*dz) in double without contraction and a sorted
-// insertion into the k best, kept in registers.  The result is the exact kNN
-// with ties broken by index.
+// Query, in two kernels.  A query whose own finest-level cell holds at least
+// k+1 rows (dense surroundings) is served by one lane: it scans that cell,
+// then rings of neighbouring cells, skipping cells beyond the current k-th
+// distance, and stops when the k-th distance is inside the searched block
+// (cells are disjoint, so every unseen row is farther).  The other queries
+// are served by a whole wave each, at a coarser level: the lanes share the
+// cells and rows and hold the k best one entry per lane, so a query near a
+// dense surface costs its rows / 64 steps instead of stalling 63 idle lanes.
+// Candidates are screened in float against a bound derived from the current
+// k-th key (never rejecting a point that the exact key would keep); survivors
+// get the exact key (d2, logical index) with d2 = ((dx*dx + dy*dy) + dz*dz)
+// in double without contraction.  The result is the exact kNN with ties
+// broken by index.
 #include <algorithm>
 #include <climits>
 
@@ -26,7 +26,6 @@
 namespace ng {
 namespace {
 
-constexpr int LEAF = 16;
 
 // ---- Morton keys -----------------------------------------------------------
 __global__ void __launch_bounds__(256)
@@ -101,68 +100,6 @@ __global__ void k_morton(const float* __restrict__ xyz3, const float4* __restric
 __global__ void k_iota(int* v, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
-}
-
-// ---- tree ------------------------------------------------------------------
-struct Box {
-  float lx, ly, lz, hx, hy, hz;
-};
-
-NG_DEV Box box_empty() { return {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY}; }
-
-NG_DEV Box box_join(const Box& a, const Box& b) {
-  return {fminf(a.lx, b.lx), fminf(a.ly, b.ly), fminf(a.lz, b.lz),
-          fmaxf(a.hx, b.hx), fmaxf(a.hy, b.hy), fmaxf(a.hz, b.hz)};
-}
-
-NG_DEV void box_store(float4* bmin, float4* bmax, long long node, const Box& b) {
-  bmin[node] = make_float4(b.lx, b.ly, b.lz, 0.f);
-  bmax[node] = make_float4(b.hx, b.hy, b.hz, 0.f);
-}
-
-// Builds up to 8 levels of the tree per block, from 256 consecutive nodes of
-// level `lc` (leaf level when cen != nullptr: the leaf boxes come from points).
-__global__ void __launch_bounds__(256)
-k_tree_levels(const float4* __restrict__ cen, int n, int lc, int levels,
-              float4* __restrict__ bmin, float4* __restrict__ bmax) {
-  __shared__ Box sb[256];
-  const long long first = 1ll << lc;
-  const long long cnt = first;  // nodes on level lc
-  const long long li = (long long)blockIdx.x * 256 + threadIdx.x;
-  const bool valid = li < cnt;
-  Box b = box_empty();
-  if (valid) {
-    if (cen) {
-      long long p0 = li * LEAF;
-      for (int j = 0; j < LEAF; ++j) {
-        long long p = p0 + j;
-        if (p < n) {
-          float4 c = cen[p];
-          b.lx = fminf(b.lx, c.x);
-          b.ly = fminf(b.ly, c.y);
-          b.lz = fminf(b.lz, c.z);
-          b.hx = fmaxf(b.hx, c.x);
-          b.hy = fmaxf(b.hy, c.y);
-          b.hz = fmaxf(b.hz, c.z);
-        }
-      }
-      box_store(bmin, bmax, first + li, b);
-    } else {
-      float4 a = bmin[first + li], c = bmax[first + li];
-      b = {a.x, a.y, a.z, c.x, c.y, c.z};
-    }
-  }
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  for (int s = 1; s <= levels; ++s) {
-    const int step = 1 << s;
-    if (valid && (threadIdx.x & (step - 1)) == 0) {
-      Box j = box_join(sb[threadIdx.x], sb[threadIdx.x + (step >> 1)]);
-      sb[threadIdx.x] = j;
-      box_store(bmin, bmax, (first + li) >> s, j);
-    }
-    __syncthreads();
-  }
 }
 
 // ---- cell table ------------------------------------------------------------
@@ -289,7 +226,7 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
 // queries whose own cell holds at least K + 1 rows (so the own cell alone
 // fills the list and the k-th distance is at most the cell's diagonal: the
 // search never needs more than rings 1 and 2); the others are flagged in
-// sparse_flag for k_knn_tree.  Search:
+// sparse_flag for k_knn_wave.  Search:
 // the query's own cell, then rings R = 1, 2, ... of level-L cells (the cells
 // at Chebyshev distance R), skipping cells whose box (widened by the
 // quantisation margin) is beyond the current k-th key.  After ring R the
@@ -321,7 +258,7 @@ k_knn_grid(const float4* __restrict__ cen, int n, int keff, int k_out,
   const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc), quant(qzf, lof[2], sc)};
 
   // Queries whose own finest-level cell holds fewer than K + 1 rows (sparse
-  // surroundings) go to the tree search instead.
+  // surroundings) are flagged for k_knn_wave instead.
   const int L = LT;
   {
     const unsigned mc = (spread10(qi[0] >> (10 - L)) << 2) | (spread10(qi[1] >> (10 - L)) << 1) |
@@ -415,112 +352,209 @@ k_knn_grid(const float4* __restrict__ cen, int n, int keff, int k_out,
 }
 
 // ---- sparse queries ------------------------------------------------------------
-NG_DEV float box_d2f(float qx, float qy, float qz, float4 lo, float4 hi) {
-  const float gx = fmaxf(fmaxf(lo.x - qx, qx - hi.x), 0.f);
-  const float gy = fmaxf(fmaxf(lo.y - qy, qy - hi.y), 0.f);
-  const float gz = fmaxf(fmaxf(lo.z - qz, qz - hi.z), 0.f);
-  return gx * gx + gy * gy + gz * gz;
-}
-
+// Exact k-NN of the sparse queries, one wave per query.  Level: the finest
+// L < LT whose cell around the query holds at least K + 1 rows (or level 1),
+// so rings 1 and 2 suffice as in k_knn_grid.  The lanes share the work: the
+// cells of a ring are tested one per lane (box against the current k-th
+// distance), the rows of the cells that pass are dealt out 64 at a time, and
+// the k best live one entry per lane (lanes 0..K-1, sorted), so an insertion
+// is a ballot and a shift.  The own cell is scanned first.
 template <int K>
-struct Query {
-  double qx, qy, qz;
-  float qxf, qyf, qzf;
-  int p;
-  Best<K> best;
-  float thr;
+struct WaveBest {
+  double d;  // entry of this lane (lanes >= K hold +inf)
+  int l;
 
-  NG_DEV void scan_leaf(const float4* __restrict__ cen, int n, int leaf) {
-    const int j0 = leaf * LEAF;
-    const int j1 = min(j0 + LEAF, n);
-    unsigned mask = 0u;
-#pragma unroll 4
-    for (int j = j0; j < j1; ++j) {
-      const float4 c = cen[j];
-      const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
-      const bool pass = dx * dx + dy * dy + dz * dz <= thr && j != p;
-      mask |= (unsigned)pass << (j - j0);
+  NG_DEV void init() {
+    d = INFINITY;
+    l = INT_MAX;
+  }
+  NG_DEV double kth() const {
+    const int lo = __shfl(__double2loint(d), K - 1, 64);
+    const int hi = __shfl(__double2hiint(d), K - 1, 64);
+    return __hiloint2double(hi, lo);
+  }
+  // insert (dc, lc) (wave-uniform); no-op if it does not beat entry K-1
+  NG_DEV void insert(double dc, int lc) {
+    const int lane = lane_id();
+    const bool lt = dc < d || (dc == d && lc < l);
+    // position = number of entries smaller than the candidate
+    const unsigned long long ge = __ballot(lt) & ((1ull << K) - 1ull);
+    if (ge == 0ull) return;
+    const int pos = __ffsll((long long)ge) - 1;
+    const int plo = __shfl_up(__double2loint(d), 1, 64);
+    const int phi = __shfl_up(__double2hiint(d), 1, 64);
+    const int pl = __shfl_up(l, 1, 64);
+    if (lane < K) {
+      if (lane == pos) {
+        d = dc;
+        l = lc;
+      } else if (lane > pos) {
+        d = __hiloint2double(phi, plo);
+        l = pl;
+      }
     }
-    if (mask == 0u) return;
-    while (mask) {
-      const int u = __builtin_ctz(mask);
-      mask &= mask - 1;
-      const float4 c = cen[j0 + u];
-      best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
-    }
-    thr = admit_bound(best.d[K - 1]);
   }
 };
 
-// Exact k-NN of the sparse queries (listed in working order), walking the
-// tree bottom-up: scan the query's own leaf, then for each ancestor v (leaf
-// upwards, up to the root) search the subtree of v's sibling; together these
-// subtrees cover every leaf.  (Boxes of different subtrees may overlap, so no
-// early stop is taken on containment; a far sibling costs one box test.)
-// Each sibling subtree is walked depth-first, left child first, without a
-// stack (heap numbering gives the next node), skipping every node whose box
-// is beyond the current bound.  Each lane advances its walk until it finds a
-// leaf to scan (or finishes); the lanes then scan their leaves together,
-// which keeps the expensive part of the loop in step.
 template <int K>
 __global__ void __launch_bounds__(64)
-k_knn_tree(const float4* __restrict__ cen, int n, int keff, int k_out, int nb2,
-           const float4* __restrict__ bmin, const float4* __restrict__ bmax,
+k_knn_wave(const float4* __restrict__ cen, int n, int keff, int k_out,
+           const unsigned* __restrict__ box, int LT, const int* __restrict__ cstart,
            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
            const int* __restrict__ list, const int* __restrict__ d_count) {
+  __shared__ int s_start[128];
+  __shared__ int s_pref[129];
+  const int lane = threadIdx.x;
   const int count = *d_count;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-    const int p = list[i];
+  const Grid g = grid_from_box(box);
+  float lof[3], hif[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lof[a] = ord2f(box[a]);
+    hif[a] = ord2f(box[3 + a]);
+  }
+  const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
+  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
+  for (int qidx = blockIdx.x; qidx < count; qidx += gridDim.x) {
+    const int p = list[qidx];
     const float4 cq = cen[p];
-    Query<K> Q;
-    Q.qx = cq.x;
-    Q.qy = cq.y;
-    Q.qz = cq.z;
-    Q.qxf = cq.x;
-    Q.qyf = cq.y;
-    Q.qzf = cq.z;
-    Q.p = p;
-    Q.best.init();
-    Q.thr = INFINITY;
-    Q.scan_leaf(cen, n, p / LEAF);
-    unsigned v = (unsigned)nb2 + (unsigned)(p / LEAF);
-    bool done = v <= 1u;
-    unsigned s = v ^ 1u, node = s;
-    while (true) {
-      int leaf = -1;
-      while (!done && leaf < 0) {
-        const float4 lo = bmin[node], hi = bmax[node];
-        const bool hit = lo.x <= hi.x && box_d2f(Q.qxf, Q.qyf, Q.qzf, lo, hi) <= Q.thr;
-        if (hit && node < (unsigned)nb2) {
-          node = 2u * node;  // descend, left child first
-          continue;
+    const double qx = cq.x, qy = cq.y, qz = cq.z;
+    const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
+    const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc),
+                            quant(qzf, lof[2], sc)};
+    int L = LT - 1 >= 1 ? LT - 1 : 1;
+    while (L > 1) {
+      const int sl = 10 - L;
+      const unsigned mc = (spread10(qi[0] >> sl) << 2) | (spread10(qi[1] >> sl) << 1) |
+                          spread10(qi[2] >> sl);
+      const unsigned f = mc << (3 * (LT - L));
+      if (cstart[f + (1u << (3 * (LT - L)))] - cstart[f] >= K + 1) break;
+      --L;
+    }
+    const int sl = 10 - L;
+    const int G = 1 << L;
+    const int sub = 3 * (LT - L);
+    const double side = (double)(1 << sl) * g.inv_sc;
+    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+    WaveBest<K> best;
+    best.init();
+
+    // scans the rows of the cells listed in s_start / s_pref (ncell cells)
+    auto scan_cells = [&](int ncell) {
+      const int total = s_pref[ncell];
+      for (int t0 = 0; t0 < total; t0 += 64) {
+        const int t = t0 + lane;
+        bool pass = false;
+        int j = -1;
+        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float thr = admit_bound(best.kth());
+        if (t < total) {
+          int lo = 0, hi = ncell - 1;  // last cell with s_pref <= t
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+          }
+          j = s_start[lo] + (t - s_pref[lo]);
+          c = cen[j];
+          const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
+          pass = dx * dx + dy * dy + dz * dz <= thr && j != p;
         }
-        if (hit) leaf = (int)(node - (unsigned)nb2);
-        // next node of the subtree in depth-first order, or the next ancestor
-        while (node != s && (node & 1u)) node >>= 1;
-        if (node == s) {
-          v >>= 1;
-          done = v <= 1u;
-          s = v ^ 1u;
-          node = s;
-        } else {
-          node += 1u;
+        unsigned long long m = __ballot(pass);
+        const double dme = pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0;
+        const int lme = __float_as_int(c.w);
+        while (m) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int dlo = __shfl(__double2loint(dme), src, 64);
+          const int dhi = __shfl(__double2hiint(dme), src, 64);
+          const int ls = __shfl(lme, src, 64);
+          best.insert(__hiloint2double(dhi, dlo), ls);
         }
       }
-      if (leaf >= 0) Q.scan_leaf(cen, n, leaf);
-      if (__ballot(!done) == 0ull) break;
+    };
+    // own cell
+    {
+      const unsigned mc = (spread10((unsigned)cx) << 2) | (spread10((unsigned)cy) << 1) |
+                          spread10((unsigned)cz);
+      const unsigned f = mc << sub;
+      if (lane == 0) {
+        s_start[0] = cstart[f];
+        s_pref[0] = 0;
+        s_pref[1] = cstart[f + (1u << sub)] - cstart[f];
+      }
+      __syncthreads();
+      scan_cells(1);
+      __syncthreads();
     }
+    for (int R = 1; sc > 0.f; ++R) {
+      // cells of ring R, enumerated over the (2R+1)^3 cube, 64 per step
+      const int side_n = 2 * R + 1;
+      const int ncube = side_n * side_n * side_n;
+      for (int c0 = 0; c0 < ncube; c0 += 64) {
+        const int ci = c0 + lane;
+        const double kd = best.kth();  // wave-uniform, read before any branch
+        int a = 0, b = 0;
+        if (ci < ncube) {
+          const int dx = ci % side_n - R, dy = (ci / side_n) % side_n - R, dz = ci / (side_n * side_n) - R;
+          const int x = cx + dx, y = cy + dy, z = cz + dz;
+          const bool on_ring = max(max(abs(dx), abs(dy)), abs(dz)) == R;
+          if (on_ring && x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
+            const double bx0 = g.lo[0] + x * side - g.margin, bx1 = g.lo[0] + (x + 1) * side + g.margin;
+            const double by0 = g.lo[1] + y * side - g.margin, by1 = g.lo[1] + (y + 1) * side + g.margin;
+            const double bz0 = g.lo[2] + z * side - g.margin, bz1 = g.lo[2] + (z + 1) * side + g.margin;
+            const double gx = fmax(fmax(bx0 - qx, qx - bx1), 0.0);
+            const double gy = fmax(fmax(by0 - qy, qy - by1), 0.0);
+            const double gz = fmax(fmax(bz0 - qz, qz - bz1), 0.0);
+            const double bd = (gx * gx + gy * gy) + gz * gz;
+            if (!(bd > kd * (1.0 + 1e-12))) {
+              const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                                  spread10((unsigned)z);
+              const unsigned f = mc << sub;
+              a = cstart[f];
+              b = cstart[f + (1u << sub)];
+            }
+          }
+        }
+        // compact the non-empty cells of this step into s_start / s_pref
+        const bool has = b > a;
+        const unsigned long long hm = __ballot(has);
+        const int rank = __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+        int cnt = has ? b - a : 0;
+        int incl = cnt;  // inclusive prefix of counts over the non-empty cells
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(incl, d, 64);
+          if (lane >= d) incl += y;
+        }
+        if (has) {
+          s_start[rank] = a;
+          s_pref[rank] = incl - cnt;
+        }
+        const int ncell = __popcll(hm);
+        if (lane == 63) s_pref[ncell] = incl;
+        __syncthreads();
+        if (ncell > 0) scan_cells(ncell);
+        __syncthreads();
+      }
+      double rho = INFINITY;
+      if (cx - R > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - R) * side + g.margin));
+      if (cx + R + 1 < G) rho = fmin(rho, (g.lo[0] + (cx + R + 1) * side - g.margin) - qx);
+      if (cy - R > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - R) * side + g.margin));
+      if (cy + R + 1 < G) rho = fmin(rho, (g.lo[1] + (cy + R + 1) * side - g.margin) - qy);
+      if (cz - R > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - R) * side + g.margin));
+      if (cz + R + 1 < G) rho = fmin(rho, (g.lo[2] + (cz + R + 1) * side - g.margin) - qz);
+      if (!(rho < INFINITY)) break;
+      if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.kth()) break;
+    }
+    // row out: lane t < keff holds entry t
     const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
     int* out = nbr + row * k_out;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      if (t < k_out) {
-        int o = -1;
-        if (t < keff) o = inv ? inv[Q.best.l[t]] : Q.best.l[t];
-        out[t] = o;
-      }
+    if (lane < k_out) {
+      int o = -1;
+      if (lane < keff) o = inv ? inv[best.l] : best.l;
+      out[lane] = o;
     }
-    for (int t = K; t < k_out; ++t) out[t] = -1;
+    __syncthreads();
   }
 }
 
@@ -544,35 +578,6 @@ __global__ void k_gather_cen(const float* __restrict__ xyz3, const int* __restri
                        xyz3[3 * (long long)i + 2], __int_as_float(i));
 }
 
-struct TreeShape {
-  int nb, nb2, H;
-};
-
-TreeShape tree_shape(long long n) {
-  TreeShape s;
-  s.nb = (int)((n + LEAF - 1) / LEAF);
-  if (s.nb < 1) s.nb = 1;
-  s.H = 0;
-  while ((1ll << s.H) < s.nb) ++s.H;
-  s.nb2 = 1 << s.H;
-  return s;
-}
-
-void build_tree(const float4* cen, int n, const TreeShape& ts, float4* bmin, float4* bmax,
-                hipStream_t st) {
-  int lc = ts.H;
-  int levels = lc < 8 ? lc : 8;
-  k_tree_levels<<<blocks_for(1ll << lc, 256), 256, 0, st>>>(cen, n, lc, levels, bmin, bmax);
-  NG_LAUNCH_CHECK();
-  lc -= levels;
-  while (lc > 0) {
-    levels = lc < 8 ? lc : 8;
-    k_tree_levels<<<blocks_for(1ll << lc, 256), 256, 0, st>>>(nullptr, n, lc, levels, bmin, bmax);
-    NG_LAUNCH_CHECK();
-    lc -= levels;
-  }
-}
-
 // Finest table level: about one level below 8^L ~ n, at most 7 (2M cells).
 int table_level(long long n) {
   int L = 1;
@@ -583,8 +588,6 @@ int table_level(long long n) {
 // Table memory: cell counts, cell starts, the logical -> working inverse and
 // the order-check flag.
 struct TableMem {
-  float4* bmin;
-  float4* bmax;
   int* hist;
   int* cstart;
   int* inv;
@@ -596,11 +599,8 @@ struct TableMem {
 
 TableMem carve_table(void* base, long long n, size_t* bytes = nullptr) {
   const long long ncells = 1ll << (3 * table_level(n));
-  const TreeShape ts = tree_shape(n);
   Carver c(base);
   TableMem t;
-  t.bmin = c.take<float4>(2ll * ts.nb2);
-  t.bmax = c.take<float4>(2ll * ts.nb2);
   t.hist = c.take<int>(ncells + 1);
   t.cstart = c.take<int>(ncells + 1);
   t.inv = c.take<int>(n);
@@ -626,7 +626,6 @@ void build_table(const float4* cen, int n, const unsigned* box, void* mem, int* 
                                                   d_unsorted);
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(t.hist, t.cstart, ncells + 1, nullptr, stemp, st);
-  build_tree(cen, n, tree_shape(n), t.bmin, t.bmax, st);
 }
 
 template <int K>
@@ -634,7 +633,6 @@ void query_k(const float4* cen, int n, int keff, int k_out, const unsigned* box,
              const TableMem& t, void* stemp, const int* inv, int rows_logical, int* nbr,
              hipStream_t st) {
   const int LT = table_level(n);
-  const TreeShape ts = tree_shape(n);
   k_knn_grid<K><<<blocks_for(n, 64), 64, 0, st>>>(cen, n, keff, k_out, box, LT, t.cstart, inv,
                                                   rows_logical, nbr, t.sflag);
   NG_LAUNCH_CHECK();
@@ -643,10 +641,10 @@ void query_k(const float4* cen, int n, int keff, int k_out, const unsigned* box,
   scan_exclusive_i32(t.sflag, t.spos, n, t.flag + 1, stemp, st);
   k_scatter_flagged<<<blocks_for(n, 256), 256, 0, st>>>(t.sflag, t.spos, n, t.sparse);
   NG_LAUNCH_CHECK();
-  unsigned g = blocks_for(n, 64);
-  if (g > 4096) g = 4096;
-  k_knn_tree<K><<<g, 64, 0, st>>>(cen, n, keff, k_out, ts.nb2, t.bmin, t.bmax, inv, rows_logical,
-                                  nbr, t.sparse, t.flag + 1);
+  unsigned g = (unsigned)(n < 16384 ? n : 16384);
+  if (g < 1) g = 1;
+  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, keff, k_out, box, LT, t.cstart, inv, rows_logical, nbr,
+                                  t.sparse, t.flag + 1);
   NG_LAUNCH_CHECK();
 }
 
