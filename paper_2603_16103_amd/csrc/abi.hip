@@ -6,7 +6,7 @@
 #include <string>
 
 #include "../../include/nanogs.h"
-#include "internal.h"
+#include "engine.h"
 
 namespace ng {
 
@@ -17,36 +17,6 @@ thread_local std::string g_error;
 void set_error(const std::string& msg) { g_error = msg; }
 
 namespace {
-
-struct Work {
-  float4* cen;
-  int* lg;
-  float4* shp;
-  float* sh;
-  int* org;
-};
-
-Work take_work(Carver& c, long long n) {
-  Work w;
-  w.cen = c.take<float4>(n);
-  w.lg = c.take<int>(n);
-  w.shp = c.take<float4>(2 * n);
-  w.sh = c.take<float>(n * NG_SH);
-  w.org = c.take<int>(n);
-  return w;
-}
-
-struct Opts {
-  int S = 1;
-  int app_dims = NG_SH;
-  int precision = NANOGS_PREC_FP32;
-  float fb_ratio = 1.0f / 256.0f;
-  uint64_t seed = 0;
-  int max_rounds = 0;
-  int* d_trace = nullptr;
-  int* d_origin = nullptr;
-  int timing = 0;
-};
 
 nanogs_status read_opts(const nanogs_options* o, Opts* out) {
   Opts r;
@@ -83,14 +53,6 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
   }
   *out = r;
   return NANOGS_OK;
-}
-
-CrnArgs make_crn(uint64_t seed, int round, int S) {
-  CrnArgs c;
-  std::memset(&c, 0, sizeof(c));
-  c.S = S;
-  crn_host(seed, round, S, &c.v[0][0]);
-  return c;
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -184,208 +146,40 @@ nanogs_status guarded(F&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// simplify: workspace layout
+// simplify: one job on an engine sized for it
 // ---------------------------------------------------------------------------
-struct SimplifyWs {
-  Work w[2];
-  float4* pre;
-  int* nbr;
-  int* src;
-  int* tgt;
-  int* islot;
-  int* eoff;
-  int* ioff;
-  int* aoff;
-  float* cost;
-  unsigned long long* akey;
-  int* au;
-  int* fb_list;
-  int* partner;
-  unsigned* keys;
-  int* perm;
-  int* counters;
-  long long* d_m;
-  void* temp;
-};
-
-size_t big_temp_bytes(long long n, int k) {
-  size_t t = sort_temp_bytes(n);
-  t = std::max(t, knn_tree_bytes(n));
-  t = std::max(t, edges_temp_bytes(n, k));
-  t = std::max(t, select_temp_bytes(n, n * k));
-  t = std::max(t, merge_temp_bytes(n));
-  return t + 4096;
-}
-
-SimplifyWs carve_simplify(void* base, long long n, int k, size_t* bytes_out = nullptr) {
-  Carver c(base);
-  SimplifyWs s;
-  s.w[0] = take_work(c, n);
-  s.w[1] = take_work(c, n);
-  s.pre = c.take<float4>(2 * n);
-  s.nbr = c.take<int>(n * k);
-  s.src = c.take<int>(n * k);
-  s.tgt = c.take<int>(n * k);
-  s.islot = c.take<int>(n * k);
-  s.eoff = c.take<int>(n + 1);
-  s.ioff = c.take<int>(n + 1);
-  s.aoff = c.take<int>(n + 1);
-  s.cost = c.take<float>(n * k);
-  s.akey = c.take<unsigned long long>(2 * n * k);
-  s.au = c.take<int>(2 * n * k);
-  s.fb_list = c.take<int>(n * k);
-  s.partner = c.take<int>(n);
-  s.keys = c.take<unsigned>(n);
-  s.perm = c.take<int>(n);
-  s.counters = c.take<int>(64);
-  s.d_m = c.take<long long>(8);
-  s.temp = base ? (char*)base + c.bytes() : nullptr;
-  if (bytes_out) *bytes_out = c.bytes();
-  return s;
-}
-
 size_t simplify_bytes(long long n, int k) {
   if (n < 1) n = 1;
-  size_t b = 0;
-  carve_simplify(nullptr, n, k, &b);
-  return b + big_temp_bytes(n, k);
-}
-
-__global__ void k_iota(int* v, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = i;
+  return Engine::workspace_bytes(n, k, 1);
 }
 
 nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long target_n, int k,
                            const Opts& o, nanogs_gaussians* out, int64_t* n_out,
                            nanogs_stats* stats, void* ws, hipStream_t st) {
-  SimplifyWs W = carve_simplify(ws, n, k);
-  long long* host = pinned_host();
-  nanogs_stats local;
-  std::memset(&local, 0, sizeof(local));
   thread_local StageTimer T;
   T.begin_call(o.timing != 0, st);
-  int tk;
-
-  // 1. spatial order of the input (Morton order of the centres)
-  tk = T.start(NANOGS_T_SETUP);
-  launch_morton_keys(in->pos, nullptr, (int)n, W.keys, W.counters + 8, st);
-  k_iota<<<blocks_for(n, 256), 256, 0, st>>>(W.perm, (int)n);
-  NG_LAUNCH_CHECK();
-  sort_pairs_u32(W.keys, W.perm, n, 30, W.temp, st);
-
-  // 2. activation into working set 0, in that order
-  fill_i32(W.counters, 0, 1, st);
-  launch_activate_stored(in->pos, in->log_scale, in->rot, in->opacity, W.perm, (int)n,
-                         W.w[0].cen, W.w[0].lg, W.w[0].shp, W.w[0].org, W.counters, st);
-  launch_check_finite(in->sh, n * NG_SH, W.counters, st);
-  launch_copy_sh_rows(in->sh, W.perm, W.w[0].sh, nullptr, (int)n, st);
-  T.stop(tk);
-  NG_HIP(hipMemcpyAsync(host, W.counters, sizeof(int), hipMemcpyDeviceToHost, st));
-  NG_HIP(hipStreamSynchronize(st));
-  if (*(int*)host != 0) {
-    T.collect(local.stage_ms, local.stage_launches);
-    set_error("input contains a non-finite value");
-    return NANOGS_ENONFINITE;
-  }
-
-  // 3. passes
-  const unsigned* box = (const unsigned*)(W.counters + 8);  // Morton bounds
-  fill_i32(W.counters + 2, 0, 1, st);
-  int cur = 0;
-  long long N = n;
-  long long traced = 0;
-  int r = 0;
-  while (N > target_n && (o.max_rounds == 0 || r < o.max_rounds)) {
-    const Work& a = W.w[cur];
-    const Work& b = W.w[cur ^ 1];
-    const int keff = (int)std::min<long long>(std::max(1, k), N - 1);
-    tk = T.start(NANOGS_T_PRECOMPUTE);
-    launch_precompute(a.shp, (int)N, W.pre, st);
-    T.stop(tk);
-    tk = T.start(NANOGS_T_KNN_TREE);
-    knn_working_tree(a.cen, (int)N, box, W.temp, W.counters + 2, st);
-    T.stop(tk);
-    tk = T.start(NANOGS_T_KNN_QUERY);
-    knn_working_query(a.cen, (int)N, k, keff, box, W.nbr, W.temp, st);
-    T.stop(tk);
-    tk = T.start(NANOGS_T_EDGES);
-    const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
-    launch_union_edges(W.nbr, a.lg, (int)N, k, es, W.d_m, W.temp, st);
-    T.stop(tk);
-    NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st));
-    NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-    NG_HIP(hipStreamSynchronize(st));
-    const long long m = host[0];
-    if (*(int*)(host + 1) != 0) {
-      set_error("internal: working set not in Morton order");
-      return NANOGS_EHIP;
-    }
-    const CrnArgs crn = make_crn(o.seed, r, o.S);
-    const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
-    int* fb_count = W.counters + 1;
-    fill_i32(fb_count, 0, 1, st);
-    if (o.precision == NANOGS_PREC_FP64) {
-      tk = T.start(NANOGS_T_COST_FP64);
-      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.src, W.tgt, (int)N, true, nullptr,
-                            nullptr, (int)m, crn, W.cost, nullptr, adj_out, st);
-      T.stop(tk);
-    } else {
-      tk = T.start(NANOGS_T_COST);
-      launch_edge_cost(a.cen, W.pre, a.sh, o.app_dims, W.src, W.tgt, (int)m, (int)N, true, crn,
-                       o.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, adj_out, st);
-      T.stop(tk);
-      tk = T.start(NANOGS_T_COST_FP64);
-      launch_edge_cost_fp64(a.cen, a.shp, a.sh, o.app_dims, W.src, W.tgt, (int)N, true,
-                            W.fb_list, fb_count, (int)m, crn, W.cost, nullptr, adj_out, st);
-      T.stop(tk);
-    }
-    const long long P = N - target_n;
-    tk = T.start(NANOGS_T_SELECT);
-    const Adjacency adj{W.aoff, W.akey, W.au};
-    SelectResult sel = select_pairs(adj, (int)N, a.lg, P, W.partner, W.temp, st, nullptr);
-    T.stop(tk);
-    long long fb = m;
-    if (o.precision != NANOGS_PREC_FP64) {
-      NG_HIP(hipMemcpyAsync(host, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
-      NG_HIP(hipStreamSynchronize(st));
-      fb = *(int*)host;
-    }
-    if (r < NANOGS_MAX_ROUNDS) {
-      local.n_per_round[r] = N;
-      local.edges_per_round[r] = m;
-      local.pairs_per_round[r] = sel.pairs;
-      local.fallback_per_round[r] = fb;
-      local.ld_iters_per_round[r] = sel.iters;
-    }
-    if (sel.pairs == 0) {
-      local.early_exit = 1;
-      break;
-    }
-    int* trace = o.d_trace ? o.d_trace + 2 * traced : nullptr;
-    tk = T.start(NANOGS_T_MERGE);
-    const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
-                                       b.lg, b.shp, b.sh, b.org, trace, W.temp, st, nullptr,
-                                       box);
-    T.stop(tk);
-    traced += sel.pairs;
-    N = nn;
-    cur ^= 1;
-    ++r;
-  }
-  local.rounds = r;
-
-  // 4. output in the caller's (logical) order
-  const Work& f = W.w[cur];
-  tk = T.start(NANOGS_T_OUTPUT);
-  launch_deactivate_work(f.cen, f.lg, f.shp, f.org, (int)N, out->pos, out->log_scale, out->rot,
-                         out->opacity, o.d_origin, st);
-  launch_copy_sh_rows(f.sh, nullptr, out->sh, f.lg, (int)N, st);
-  T.stop(tk);
-  NG_HIP(hipStreamSynchronize(st));
+  Engine E(n, k, 1, o, ws, st);
+  JobSpec js;
+  js.in = *in;
+  js.out = *out;
+  js.n = n;
+  js.target = target_n;
+  js.k = k;
+  js.seed = o.seed;
+  js.d_origin = o.d_origin;
+  js.d_trace = o.d_trace;
+  const int id = E.submit(js);
+  E.run(&T);
+  nanogs_stats local = E.job(id).stats;
   T.collect(local.stage_ms, local.stage_launches);
-  local.n_out = N;
-  *n_out = N;
+  const Job& j = E.job(id);
+  if (j.state == JOB_FAILED) {
+    set_error(j.error);
+    if (stats) *stats = local;
+    return (nanogs_status)j.status;
+  }
+  local.n_out = j.stats.n_out;
+  *n_out = j.stats.n_out;
   if (stats) *stats = local;
   return NANOGS_OK;
 }
@@ -415,6 +209,7 @@ size_t cost_bytes(long long n, long long m) {
   c.take<float4>(2 * n);
   c.take<int>(m);
   c.take<int>(64);
+  c.take<float>(NG_CRN_ROW);
   return c.bytes();
 }
 
@@ -596,10 +391,9 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
     float4* pre = c.take<float4>(2 * n);
     int* fb_list = c.take<int>(m);
     int* counters = c.take<int>(64);
-    CrnArgs args;
-    std::memset(&args, 0, sizeof(args));
-    args.S = o.S;
-    std::memcpy(&args.v[0][0], crn, sizeof(float) * 4 * o.S);
+    float* dcrn = c.take<float>(NG_CRN_ROW);
+    NG_HIP(hipMemcpyAsync(dcrn, crn, sizeof(float) * 4 * o.S, hipMemcpyHostToDevice, stream));
+    const CrnTab args{dcrn, o.S, nullptr, nullptr};
     launch_pack_splats(s->mu, s->scale, s->quat, s->alpha, s->origin, (int)n, p.cen, p.lg, p.shp,
                        p.org, stream);
     if (o.precision == NANOGS_PREC_FP64) {
@@ -620,7 +414,7 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
 size_t nanogs_select_workspace_bytes(int64_t n, int64_t m) {
   if (n < 1) n = 1;
   if (m < 1) m = 1;
-  return select_adj_bytes(n, m) + select_temp_bytes(n, m);
+  return select_adj_bytes(n, m) + select_temp_bytes(n, m, 1);
 }
 
 nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* cost, int64_t m,
@@ -648,11 +442,13 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* c
       NG_CHECK(check_ptr(cost, 4, "cost"));
     }
     const long long mm = m < 1 ? 1 : m;
-    NG_CHECK(check_ws(ws, ws_bytes, select_adj_bytes(n, mm) + select_temp_bytes(n, mm)));
+    NG_CHECK(check_ws(ws, ws_bytes, select_adj_bytes(n, mm) + select_temp_bytes(n, mm, 1)));
     Adjacency adj;
     build_adjacency(ei, ej, cost, m, (int)n, &adj, ws, stream);
     void* temp = (char*)ws + select_adj_bytes(n, mm);
-    select_pairs(adj, (int)n, nullptr, max_pairs, partner, temp, stream, (long long*)d_npairs);
+    const long long P = max_pairs;
+    select_pairs(adj, (int)n, nullptr, nullptr, 1, &P, partner, temp, stream,
+                 (long long*)d_npairs, nullptr);
     return NANOGS_OK;
   });
 }
@@ -685,7 +481,7 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* pa
                        a.shp, a.org, stream);
     const long long nout = merge_compact(a.cen, nullptr, a.shp, in->sh, a.org, (int)n, partner,
                                          b.cen, b.lg, b.shp, out->sh, b.org, nullptr, temp,
-                                         stream, nullptr, nullptr);
+                                         stream, nullptr, nullptr, nullptr, nullptr, 1);
     launch_unpack_splats(b.cen, b.shp, b.org, (int)nout, out->mu, out->scale, out->quat,
                          out->alpha, (in->origin && out->origin) ? out->origin : nullptr, stream);
     set_i64((long long*)d_nout, nout, stream);

@@ -70,17 +70,19 @@ NG_DEV Deact deactivate_one(float s0, float s1, float s2, float alpha, float qw,
 
 __global__ void k_activate_stored(const float* __restrict__ pos, const float* __restrict__ ls,
                                   const float* __restrict__ rot, const float* __restrict__ op,
-                                  const int* __restrict__ perm, int n, float4* __restrict__ cen,
-                                  int* __restrict__ lg, float4* __restrict__ shp,
-                                  int* __restrict__ org, int* __restrict__ nonfinite) {
+                                  const int* __restrict__ perm, int n, int lbase,
+                                  float4* __restrict__ cen, int* __restrict__ lg,
+                                  float4* __restrict__ shp, int* __restrict__ org,
+                                  int* __restrict__ sg, int sgid, int* __restrict__ nonfinite) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int i = perm ? perm[p] : p;
+  if (sg) sg[p] = sgid;
   float x = pos[3 * (long long)i], y = pos[3 * (long long)i + 1], z = pos[3 * (long long)i + 2];
   Act a = activate_one(ls + 3 * (long long)i, rot + 4 * (long long)i, op[i]);
   if (!(a.finite && isfinite(x) && isfinite(y) && isfinite(z))) *nonfinite = 1;
-  cen[p] = make_float4(x, y, z, __int_as_float(i));
-  lg[p] = i;
+  cen[p] = make_float4(x, y, z, __int_as_float(lbase + i));
+  lg[p] = lbase + i;
   shp[2 * (long long)p] = make_float4(a.s0, a.s1, a.s2, a.alpha);
   shp[2 * (long long)p + 1] = make_float4(a.qw, a.qx, a.qy, a.qz);
   org[p] = i;
@@ -123,23 +125,23 @@ __global__ void k_check_finite(const float* __restrict__ x, long long count,
 // 16-byte words of a row, so each row is read and written in full lines.
 __global__ void k_copy_sh_rows(const float4* __restrict__ src, const int* __restrict__ src_map,
                                float4* __restrict__ dst, const int* __restrict__ dst_map,
-                               int rows) {
+                               int dst_base, int rows) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)rows * 12) return;
   int r = (int)(t / 12), c = (int)(t % 12);
   int sr = src_map ? src_map[r] : r;
-  int dr = dst_map ? dst_map[r] : r;
+  int dr = dst_map ? dst_map[r] - dst_base : r;
   dst[(long long)dr * 12 + c] = src[(long long)sr * 12 + c];
 }
 
 __global__ void k_deactivate_work(const float4* __restrict__ cen, const int* __restrict__ lg,
                                   const float4* __restrict__ shp, const int* __restrict__ org,
-                                  int n, float* __restrict__ pos, float* __restrict__ ls,
-                                  float* __restrict__ rot, float* __restrict__ op,
-                                  int* __restrict__ origin_out) {
+                                  int n, int lbase, float* __restrict__ pos,
+                                  float* __restrict__ ls, float* __restrict__ rot,
+                                  float* __restrict__ op, int* __restrict__ origin_out) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  long long L = lg[p];
+  long long L = lg[p] - lbase;
   float4 c = cen[p];
   float4 a = shp[2 * (long long)p];
   float4 q = shp[2 * (long long)p + 1];
@@ -220,11 +222,13 @@ __global__ void k_unpack(const float4* __restrict__ cen, const float4* __restric
 }  // namespace
 
 void launch_activate_stored(const float* pos, const float* log_scale, const float* rot,
-                            const float* opacity, const int* perm, int n, float4* cen, int* lg,
-                            float4* shp, int* org, int* nonfinite, hipStream_t st) {
+                            const float* opacity, const int* perm, int n, int lbase, float4* cen,
+                            int* lg, float4* shp, int* org, int* sg, int sgid, int* nonfinite,
+                            hipStream_t st) {
   if (n <= 0) return;
-  k_activate_stored<<<blocks_for(n, 256), 256, 0, st>>>(pos, log_scale, rot, opacity, perm, n, cen,
-                                                        lg, shp, org, nonfinite);
+  k_activate_stored<<<blocks_for(n, 256), 256, 0, st>>>(pos, log_scale, rot, opacity, perm, n,
+                                                        lbase, cen, lg, shp, org, sg, sgid,
+                                                        nonfinite);
   NG_LAUNCH_CHECK();
 }
 
@@ -237,19 +241,19 @@ void launch_check_finite(const float* x, long long count, int* nonfinite, hipStr
 }
 
 void launch_copy_sh_rows(const float* src, const int* src_map, float* dst, const int* dst_map,
-                         int rows, hipStream_t st) {
+                         int dst_base, int rows, hipStream_t st) {
   if (rows <= 0) return;
   k_copy_sh_rows<<<blocks_for((long long)rows * 12, 256), 256, 0, st>>>(
-      (const float4*)src, src_map, (float4*)dst, dst_map, rows);
+      (const float4*)src, src_map, (float4*)dst, dst_map, dst_base, rows);
   NG_LAUNCH_CHECK();
 }
 
 void launch_deactivate_work(const float4* cen, const int* lg, const float4* shp, const int* org,
-                            int n, float* pos, float* log_scale, float* rot, float* opacity,
-                            int* origin_out, hipStream_t st) {
+                            int n, int lbase, float* pos, float* log_scale, float* rot,
+                            float* opacity, int* origin_out, hipStream_t st) {
   if (n <= 0) return;
-  k_deactivate_work<<<blocks_for(n, 256), 256, 0, st>>>(cen, lg, shp, org, n, pos, log_scale, rot,
-                                                        opacity, origin_out);
+  k_deactivate_work<<<blocks_for(n, 256), 256, 0, st>>>(cen, lg, shp, org, n, lbase, pos,
+                                                        log_scale, rot, opacity, origin_out);
   NG_LAUNCH_CHECK();
 }
 

@@ -126,7 +126,8 @@ NG_DEV Tri<T> chol_from_scale_rot(T s0, T s1, T s2, T w, T x, T y, T z) {
 // D_geo of one pair.  ratio receives the smallest diagonal ratio seen.
 template <typename T>
 NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const Tri<T>& Lb,
-                   T ldLa, T ldLb, T pa, T pb, float pa32, const CrnArgs& crn, T& ratio) {
+                   T ldLa, T ldLb, T pa, T pb, float pa32, const float* __restrict__ cv, int S,
+                   T& ratio) {
   const V3<T> d = {mua.x - mub.x, mua.y - mub.y, mua.z - mub.z};
   const Tri<T> LA = chol_of_mix(La, Lb, sqrt(pa), sqrt(pb));
   ratio = fmin(fmin(tri_ratio(La), tri_ratio(Lb)), tri_ratio(LA));
@@ -140,9 +141,9 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
   const T inv_ne = ne > T(0) ? T(1) / ne : T(0);
   const V3<T> eh = {e.x * inv_ne, e.y * inv_ne, e.z * inv_ne};
   T acc = T(0);
-  for (int s = 0; s < crn.S; ++s) {
-    const float u = crn.v[s][0];
-    const V3<T> zz = {(T)crn.v[s][1], (T)crn.v[s][2], (T)crn.v[s][3]};
+  for (int s = 0; s < S; ++s) {
+    const float u = cv[4 * s];
+    const V3<T> zz = {(T)cv[4 * s + 1], (T)cv[4 * s + 2], (T)cv[4 * s + 3]};
     const bool ca = u < pa32;
     const Tri<T>& Lc = ca ? La : Lb;
     const Tri<T>& Lo = ca ? Lb : La;
@@ -168,7 +169,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
     const T lse = mx + log1p(exp(mn - mx));
     acc += lse - lnm;
   }
-  return acc / (T)crn.S;
+  return acc / (T)S;
 }
 
 NG_DEV float dapp_f32(const float* __restrict__ sh, long long a, long long b, int app_dims) {
@@ -251,7 +252,8 @@ NG_DEV void write_adj(const AdjOut& adj, int e, int s, int t, int ls, int lt, fl
 __global__ void __launch_bounds__(256)
 k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
             const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
-            const int* __restrict__ eb, int m, int n, int orient, CrnArgs crn, float fb_ratio,
+            const int* __restrict__ eb, int m, int n, int orient, const float* __restrict__ crn,
+            int S, const int* __restrict__ sg, const SegInfo* __restrict__ seg, float fb_ratio,
             float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
             int* __restrict__ fb_count, AdjOut adj) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,8 +282,9 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
     const float W = pa1.w + pb1.w;
     const float pb = W > 0.f ? pb1.w / W : 0.5f;
     float ratio;
+    const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const float dg = dgeo_pair<float>(v3(ca.x, ca.y, ca.z), v3(cb.x, cb.y, cb.z), La, Lb, pa1.z,
-                                      pb1.z, pa, pb, pa, crn, ratio);
+                                      pb1.z, pa, pb, pa, cv, S, ratio);
     const float c = dg + dapp_f32(sh, a, b, app_dims);
     fb = !(ratio >= fb_ratio) || !isfinite(c);
     cost[e] = c;
@@ -295,7 +298,8 @@ __global__ void __launch_bounds__(256)
 k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
                  const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
                  const int* __restrict__ eb, int n, int orient, const int* __restrict__ list,
-                 const int* __restrict__ d_count, int count_cap, CrnArgs crn,
+                 const int* __restrict__ d_count, int count_cap, const float* __restrict__ crn,
+                 int S, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
                  float* __restrict__ cost, float* __restrict__ dgeo_out, AdjOut adj) {
   const int count = d_count ? min(*d_count, count_cap) : count_cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
@@ -325,8 +329,9 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
     const double pa = W > 0.0 ? wa / W : 0.5;
     const double pb = W > 0.0 ? wb / W : 0.5;
     double ratio;
+    const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const double dg = dgeo_pair<double>(v3<double>(ca.x, ca.y, ca.z), v3<double>(cb.x, cb.y, cb.z),
-                                        La, Lb, lda, ldb, pa, pb, pa32, crn, ratio);
+                                        La, Lb, lda, ldb, pa, pb, pa32, cv, S, ratio);
     const float c = (float)(dg + dapp_f64(sh, a, b, app_dims));
     cost[e] = c;
     if (dgeo_out) dgeo_out[e] = (float)dg;
@@ -343,25 +348,26 @@ void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st) {
 }
 
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
-                      const int* ea, const int* eb, int m, int n, bool orient,
-                      const CrnArgs& crn, float fb_ratio, float* cost, float* dgeo, int* fb_list,
-                      int* fb_count, AdjOut adj, hipStream_t st) {
+                      const int* ea, const int* eb, int m, int n, bool orient, const CrnTab& crn,
+                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
+                      AdjOut adj, hipStream_t st) {
   if (m <= 0) return;
   k_edge_cost<<<blocks_for(m, 256), 256, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n,
-                                                  orient ? 1 : 0, crn, fb_ratio, cost, dgeo,
-                                                  fb_list, fb_count, adj);
+                                                  orient ? 1 : 0, crn.tab, crn.S, crn.sg, crn.seg,
+                                                  fb_ratio, cost, dgeo, fb_list, fb_count, adj);
   NG_LAUNCH_CHECK();
 }
 
 void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
                            const int* ea, const int* eb, int n, bool orient, const int* list,
-                           const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
+                           const int* d_count, int count_cap, const CrnTab& crn, float* cost,
                            float* dgeo, AdjOut adj, hipStream_t st) {
   if (count_cap <= 0) return;
   unsigned b = blocks_for(count_cap, 256);
   if (b > 2048) b = 2048;
   k_edge_cost_fp64<<<b, 256, 0, st>>>(cen, shp, sh, app_dims, ea, eb, n, orient ? 1 : 0, list,
-                                      d_count, count_cap, crn, cost, dgeo, adj);
+                                      d_count, count_cap, crn.tab, crn.S, crn.sg, crn.seg, cost,
+                                      dgeo, adj);
   NG_LAUNCH_CHECK();
 }
 

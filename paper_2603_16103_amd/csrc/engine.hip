@@ -1,0 +1,404 @@
+// Round driver of Algorithm 1 for one or many scenes at once.
+//
+// The engine keeps every live scene ("job") as a segment of one working set
+// (rows [row0, row0 + N) of each scene, which are also its logical indices;
+// see internal.h).  One step is one pass of Algorithm 1 for every live
+// segment together, one launch per stage:
+//   precompute -> cell tables -> kNN -> union edges -> edge costs (+ FP64
+//   fallback) -> greedy pairs with a budget P = N - N_tgt per segment ->
+//   merge + compaction (rows re-sorted by (segment, Morton key)).
+// Jobs queued with submit() join at the next step when their rows fit; a job
+// whose segment reaches its target (or finds no pair) is written to its
+// output buffers in the stored form at the end of that step, and its rows are
+// dropped by the next compaction.  Each job's draws are keyed by its own
+// (seed, pass), so a job's result does not depend on what else is in the
+// batch.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nanogs.h"
+#include "engine.h"
+
+namespace ng {
+
+namespace {
+
+__global__ void k_iota_e(int* v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+namespace {
+
+Work take_work_e(Carver& c, long long n) {
+  Work w;
+  w.cen = c.take<float4>(n);
+  w.lg = c.take<int>(n);
+  w.shp = c.take<float4>(2 * n);
+  w.sh = c.take<float>(n * NG_SH);
+  w.org = c.take<int>(n);
+  w.sg = c.take<int>(n);
+  return w;
+}
+
+long long table_bound(long long rows, int jobs) {
+  // per segment: 8^LT + 1 < 8 n + 1 (LT is the smallest level with 8^LT >= n,
+  // at least 1, so also <= 9 for tiny n)
+  return 8 * rows + 10ll * jobs + 16;
+}
+
+}  // namespace
+
+struct EngineWs {
+  Work w[2];
+  float4* pre;
+  int* nbr;
+  int* src;
+  int* tgt;
+  int* islot;
+  int* eoff;
+  int* ioff;
+  int* aoff;
+  float* cost;
+  unsigned long long* akey;
+  int* au;
+  int* fb_list;
+  int* partner;
+  unsigned* keys;
+  int* perm;
+  int* counters;
+  long long* d_m;
+  SegInfo* seg;
+  float* crn;
+  unsigned* boxes;  // [jobs][8]
+  void* temp;
+  size_t bytes;
+};
+
+static EngineWs carve_engine(void* base, long long R, int K, int J) {
+  Carver c(base);
+  EngineWs s;
+  s.w[0] = take_work_e(c, R);
+  s.w[1] = take_work_e(c, R);
+  s.pre = c.take<float4>(2 * R);
+  s.nbr = c.take<int>(R * K);
+  s.src = c.take<int>(R * K);
+  s.tgt = c.take<int>(R * K);
+  s.islot = c.take<int>(R * K);
+  s.eoff = c.take<int>(R + 1);
+  s.ioff = c.take<int>(R + 1);
+  s.aoff = c.take<int>(R + 1);
+  s.cost = c.take<float>(R * K);
+  s.akey = c.take<unsigned long long>(2 * R * K);
+  s.au = c.take<int>(2 * R * K);
+  s.fb_list = c.take<int>(R * K);
+  s.partner = c.take<int>(R);
+  s.keys = c.take<unsigned>(R);
+  s.perm = c.take<int>(R);
+  s.counters = c.take<int>(64);
+  s.d_m = c.take<long long>(8);
+  s.seg = c.take<SegInfo>(J);
+  s.crn = c.take<float>((size_t)J * NG_CRN_ROW);
+  s.boxes = c.take<unsigned>((size_t)J * 8);
+  s.temp = base ? (char*)base + c.bytes() : nullptr;
+  size_t kb = 0;
+  carve_knn(nullptr, R, table_bound(R, J), &kb);
+  size_t t = sort_temp_bytes(R);
+  t = std::max(t, kb);
+  t = std::max(t, edges_temp_bytes(R, K));
+  t = std::max(t, select_temp_bytes(R, R * K, J));
+  t = std::max(t, merge_temp_bytes(R));
+  s.bytes = c.bytes() + t + 4096;
+  return s;
+}
+
+size_t Engine::workspace_bytes(long long rows, int kmax, int jobs) {
+  if (rows < 2) rows = 2;
+  return carve_engine(nullptr, rows, kmax, jobs).bytes;
+}
+
+Engine::Engine(long long rows, int kmax, int jobs, const Opts& o, void* ws, hipStream_t st)
+    : R_(rows < 2 ? 2 : rows), K_(kmax), J_(jobs), o_(o), st_(st) {
+  W_ = new EngineWs(carve_engine(ws, R_, K_, J_));
+}
+
+Engine::~Engine() { delete W_; }
+
+int Engine::submit(const JobSpec& spec) {
+  Job j;
+  j.spec = spec;
+  j.id = (int)jobs_.size();
+  j.N = spec.n;
+  std::memset(&j.stats, 0, sizeof(j.stats));
+  jobs_.push_back(j);
+  queue_.push_back(j.id);
+  return j.id;
+}
+
+long long Engine::rows_in_use() const { return Ntot_; }
+
+// ---------------------------------------------------------------------------
+// job set-up: Morton order of the job's centres, activation into rows
+// [Ntot, Ntot + n) of the working set, SH rows, non-finite check
+// ---------------------------------------------------------------------------
+bool Engine::setup_job(Job& j, int pos) {
+  EngineWs& W = *W_;
+  const long long n = j.spec.n;
+  const Work& a = W.w[cur_];
+  unsigned* box = W.boxes + 8 * (size_t)pos;  // scratch for the bounds
+  long long* host = pinned_host();
+  launch_morton_keys(j.spec.in.pos, nullptr, (int)n, W.keys, box, st_);
+  k_iota_e<<<blocks_for(n, 256), 256, 0, st_>>>(W.perm, (int)n);
+  NG_LAUNCH_CHECK();
+  sort_pairs_u32(W.keys, W.perm, n, 30, W.temp, st_);
+  fill_i32(W.counters, 0, 1, st_);
+  const long long r0 = Ntot_;
+  launch_activate_stored(j.spec.in.pos, j.spec.in.log_scale, j.spec.in.rot, j.spec.in.opacity,
+                         W.perm, (int)n, (int)r0, a.cen + r0, a.lg + r0, a.shp + 2 * r0, a.org + r0,
+                         a.sg + r0, pos, W.counters, st_);
+  launch_check_finite(j.spec.in.sh, n * NG_SH, W.counters, st_);
+  launch_copy_sh_rows(j.spec.in.sh, W.perm, a.sh + r0 * NG_SH, nullptr, 0, (int)n, st_);
+  NG_HIP(hipMemcpyAsync(host, W.counters, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(host + 1, box, 6 * sizeof(unsigned), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipStreamSynchronize(st_));
+  std::memcpy(j.box, host + 1, 6 * sizeof(unsigned));
+  if (*(int*)host != 0) {
+    j.state = JOB_FAILED;
+    j.status = NANOGS_ENONFINITE;
+    j.error = "input contains a non-finite value";
+    return false;
+  }
+  j.row0 = r0;
+  j.state = JOB_RUNNING;
+  Ntot_ += n;
+  return true;
+}
+
+// Writes job j's rows [row0, row0 + N) of working set w to its outputs.
+void Engine::finish_job(Job& j, const Work& w) {
+  const long long r0 = j.row0, N = j.N;
+  launch_deactivate_work(w.cen + r0, w.lg + r0, w.shp + 2 * r0, w.org + r0, (int)N, (int)r0,
+                         j.spec.out.pos, j.spec.out.log_scale, j.spec.out.rot, j.spec.out.opacity,
+                         j.spec.d_origin, st_);
+  launch_copy_sh_rows(w.sh + r0 * NG_SH, nullptr, j.spec.out.sh, w.lg + r0, (int)r0, (int)N, st_);
+  j.stats.n_out = N;
+  j.state = JOB_DRAINING;
+}
+
+// ---------------------------------------------------------------------------
+// one pass
+// ---------------------------------------------------------------------------
+int Engine::step(StageTimer* T) {
+  EngineWs& W = *W_;
+  long long* host = pinned_host();
+  int tk;
+  int finished = 0;
+
+  // 1. admit queued jobs whose rows fit (in submission order)
+  tk = T ? T->start(NANOGS_T_SETUP) : -1;
+  while (!queue_.empty()) {
+    Job& j = jobs_[queue_.front()];
+    if (j.spec.n > R_) {
+      queue_.erase(queue_.begin());
+      j.state = JOB_FAILED;
+      j.status = NANOGS_EINVAL;
+      j.error = "job larger than the batch capacity";
+      ++finished;
+      continue;
+    }
+    if (Ntot_ + j.spec.n > R_ || (int)live_.size() >= J_) break;
+    queue_.erase(queue_.begin());
+    const int pos = (int)live_.size();
+    if (!setup_job(j, pos)) {
+      ++finished;
+      continue;
+    }
+    live_.push_back(j.id);
+    if (j.N <= j.spec.target || j.N <= 1) {
+      finish_job(j, W.w[cur_]);
+      ++finished;
+    }
+  }
+  if (T) T->stop(tk);
+
+  // 2. segment table: searching segments (running), draining ones (rows
+  // dropped by this pass's compaction)
+  std::vector<SegInfo> hs(live_.size());
+  std::vector<long long> hP(live_.size(), 0);
+  long long entries = 0;
+  unsigned class_mask = 0u;
+  int searching = 0, next = 0;
+  for (size_t i = 0; i < live_.size(); ++i) {
+    const Job& j = jobs_[live_[i]];
+    SegInfo& S = hs[i];
+    std::memset(&S, 0, sizeof(S));
+    std::memcpy(S.box, j.box, sizeof(S.box));
+    S.row0 = (int)j.row0;
+    S.nrows = (int)j.N;
+    S.crn = (int)i;
+    if (j.state == JOB_RUNNING) {
+      S.LT = table_level(j.N);
+      S.toff = (int)entries;
+      entries += table_entries(S.LT);
+      S.keff = (int)std::min<long long>(std::max(1, j.spec.k), j.N - 1);
+      S.kclass = kclass_of(S.keff);
+      class_mask |= class_bit(S.kclass);
+      S.next = next++;
+      hP[i] = j.N - j.spec.target;
+      ++searching;
+    } else {
+      S.next = -1;
+    }
+  }
+  if (live_.empty()) return finished;
+  const int nseg = (int)live_.size();
+  if (searching == 0) {
+    // only draining segments: the working set empties
+    Ntot_ = 0;
+    live_.clear();
+    for (Job& j : jobs_)
+      if (j.state == JOB_DRAINING) j.state = JOB_DONE;
+    NG_HIP(hipStreamSynchronize(st_));
+    return finished;
+  }
+  NG_HIP(hipMemcpyAsync(W.seg, hs.data(), hs.size() * sizeof(SegInfo), hipMemcpyHostToDevice,
+                        st_));
+  // draws of every segment's current pass
+  std::vector<float> crn((size_t)nseg * NG_CRN_ROW, 0.f);
+  for (int i = 0; i < nseg; ++i) {
+    const Job& j = jobs_[live_[i]];
+    crn_host(j.spec.seed, j.round, o_.S, &crn[(size_t)i * NG_CRN_ROW]);
+  }
+  NG_HIP(hipMemcpyAsync(W.crn, crn.data(), crn.size() * sizeof(float), hipMemcpyHostToDevice,
+                        st_));
+
+  const Work& a = W.w[cur_];
+  const Work& b = W.w[cur_ ^ 1];
+  const long long N = Ntot_;
+  const int* sg = a.sg;
+
+  tk = T ? T->start(NANOGS_T_PRECOMPUTE) : -1;
+  launch_precompute(a.shp, (int)N, W.pre, st_);
+  if (T) T->stop(tk);
+  tk = T ? T->start(NANOGS_T_KNN_TREE) : -1;
+  fill_i32(W.counters + 2, 0, 1, st_);
+  knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, true, st_);
+  if (T) T->stop(tk);
+  tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
+  knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, st_);
+  if (T) T->stop(tk);
+  tk = T ? T->start(NANOGS_T_EDGES) : -1;
+  const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
+  launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
+  if (T) T->stop(tk);
+  NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipStreamSynchronize(st_));
+  const long long m = host[0];
+  if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
+
+  const CrnTab ct{W.crn, o_.S, sg, W.seg};
+  const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
+  int* fb_count = W.counters + 1;
+  fill_i32(fb_count, 0, 1, st_);
+  if (o_.precision == NANOGS_PREC_FP64) {
+    tk = T ? T->start(NANOGS_T_COST_FP64) : -1;
+    launch_edge_cost_fp64(a.cen, a.shp, a.sh, o_.app_dims, W.src, W.tgt, (int)N, true, nullptr,
+                          nullptr, (int)m, ct, W.cost, nullptr, adj_out, st_);
+    if (T) T->stop(tk);
+  } else {
+    tk = T ? T->start(NANOGS_T_COST) : -1;
+    launch_edge_cost(a.cen, W.pre, a.sh, o_.app_dims, W.src, W.tgt, (int)m, (int)N, true, ct,
+                     o_.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, adj_out, st_);
+    if (T) T->stop(tk);
+    tk = T ? T->start(NANOGS_T_COST_FP64) : -1;
+    launch_edge_cost_fp64(a.cen, a.shp, a.sh, o_.app_dims, W.src, W.tgt, (int)N, true, W.fb_list,
+                          fb_count, (int)m, ct, W.cost, nullptr, adj_out, st_);
+    if (T) T->stop(tk);
+  }
+
+  tk = T ? T->start(NANOGS_T_SELECT) : -1;
+  const Adjacency adj{W.aoff, W.akey, W.au};
+  std::vector<long long> hM(nseg, 0);
+  SelectResult sel = select_pairs(adj, (int)N, a.lg, sg, nseg, hP.data(), W.partner, W.temp, st_,
+                                  nullptr, hM.data());
+  if (T) T->stop(tk);
+  long long fb = m;
+  if (o_.precision != NANOGS_PREC_FP64) {
+    NG_HIP(hipMemcpyAsync(host, fb_count, sizeof(int), hipMemcpyDeviceToHost, st_));
+    NG_HIP(hipStreamSynchronize(st_));
+    fb = *(int*)host;
+  }
+
+  // per-job bookkeeping of the pass
+  for (int i = 0; i < nseg; ++i) {
+    Job& j = jobs_[live_[i]];
+    if (j.state != JOB_RUNNING) continue;
+    const int r = j.round;
+    if (r < NANOGS_MAX_ROUNDS) {
+      j.stats.n_per_round[r] = j.N;
+      j.stats.edges_per_round[r] = searching == 1 ? m : 0;
+      j.stats.pairs_per_round[r] = hM[i];
+      j.stats.fallback_per_round[r] = searching == 1 ? fb : 0;
+      j.stats.ld_iters_per_round[r] = sel.iters;
+    }
+  }
+
+  // single running job with a trace buffer: provenance pairs of this pass
+  int* trace = nullptr;
+  if (searching == 1 && nseg == 1) {
+    Job& j = jobs_[live_[0]];
+    if (j.spec.d_trace) trace = j.spec.d_trace + 2 * j.traced;
+  }
+  tk = T ? T->start(NANOGS_T_MERGE) : -1;
+  const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
+                                     b.lg, b.shp, b.sh, b.org, trace, W.temp, st_, nullptr, sg,
+                                     b.sg, W.seg, nseg);
+  if (T) T->stop(tk);
+  cur_ ^= 1;
+  Ntot_ = nn;
+
+  // new segment rows (same order, draining segments gone) and job states
+  std::vector<int> still;
+  long long row = 0;
+  for (int i = 0; i < nseg; ++i) {
+    Job& j = jobs_[live_[i]];
+    if (j.state != JOB_RUNNING) {
+      j.state = JOB_DONE;
+      continue;
+    }
+    j.N -= hM[i];
+    j.row0 = row;
+    row += j.N;
+    if (hM[i] > 0) {
+      j.stats.rounds = ++j.round;
+      j.traced += hM[i];
+    }
+    still.push_back(j.id);
+    const bool stop = j.N <= j.spec.target || hM[i] == 0 ||
+                      (o_.max_rounds > 0 && j.round >= o_.max_rounds);
+    if (hM[i] == 0 && j.N > j.spec.target) j.stats.early_exit = 1;
+    if (stop) {
+      finish_job(j, W.w[cur_]);
+      ++finished;
+    }
+  }
+  live_ = still;
+  return finished;
+}
+
+bool Engine::idle() const { return queue_.empty() && live_.empty(); }
+
+void Engine::run(StageTimer* T) {
+  while (!idle()) step(T);
+  NG_HIP(hipStreamSynchronize(st_));
+}
+
+}  // namespace ng

@@ -109,6 +109,21 @@ NG_DEV unsigned morton_key(float x, float y, float z, const unsigned* box) {
   return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
 }
 
+// A segment = one scene of a batch, rows [row0, row0 + nrows) of the working
+// set, which is also its range of logical indices.  A single scene is one
+// segment.
+struct SegInfo {
+  unsigned box[6];  // Morton bounds: f2ord of the min and max corner
+  int row0;
+  int nrows;
+  int LT;      // cell table level (0: no search this pass)
+  int toff;    // first entry of its cell table
+  int keff;    // kNN size in use this pass
+  int kclass;  // kernel class serving it (8, 16, 24, 32), 0: no search
+  int crn;     // its row of the draw table
+  int next;    // its position after this pass's compaction, -1: its rows are dropped
+};
+
 // ---------------------------------------------------------------------------
 // host-side launchers (each defined in the .hip file named in the comment)
 // ---------------------------------------------------------------------------
@@ -132,21 +147,23 @@ void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* 
                     hipStream_t st);
 
 // activate.hip -- boundary conversions and packing
-// Stored form -> working layout; row p takes input row perm[p] (perm
-// nullable: identity) and gets logical index perm[p].
+// Stored form -> working layout; row p takes input row i = perm[p] (perm
+// nullable: identity), gets logical index lbase + i, provenance i and (sg
+// nullable) segment sgid.
 void launch_activate_stored(const float* pos, const float* log_scale, const float* rot,
-                            const float* opacity, const int* perm, int n, float4* cen, int* lg,
-                            float4* shp, int* org, int* nonfinite, hipStream_t st);
+                            const float* opacity, const int* perm, int n, int lbase, float4* cen,
+                            int* lg, float4* shp, int* org, int* sg, int sgid, int* nonfinite,
+                            hipStream_t st);
 // Checks the SH rows for non-finite values.
 void launch_check_finite(const float* x, long long count, int* nonfinite, hipStream_t st);
 // Row copy of [rows][48] float arrays: dst[dst_row(r)] = src[src_row(r)],
-// dst_row = dst_map ? dst_map[r] : r, src_row = src_map ? src_map[r] : r.
+// dst_row = dst_map ? dst_map[r] - dst_base : r, src_row = src_map ? src_map[r] : r.
 void launch_copy_sh_rows(const float* src, const int* src_map, float* dst, const int* dst_map,
-                         int rows, hipStream_t st);
-// Working layout -> stored form at the logical positions.
+                         int dst_base, int rows, hipStream_t st);
+// Working layout -> stored form at the logical positions minus lbase.
 void launch_deactivate_work(const float4* cen, const int* lg, const float4* shp, const int* org,
-                            int n, float* pos, float* log_scale, float* rot, float* opacity,
-                            int* origin_out, hipStream_t st);
+                            int n, int lbase, float* pos, float* log_scale, float* rot,
+                            float* opacity, int* origin_out, hipStream_t st);
 // Activated plain arrays <-> working layout (stage entry points).
 void launch_pack_splats(const float* mu, const float* scale, const float* quat, const float* alpha,
                         const int* origin, int n, float4* cen, int* lg, float4* shp, int* org,
@@ -161,20 +178,40 @@ void launch_deactivate_plain(const float* mu, const float* scale, const float* q
                              float* opacity, hipStream_t st);
 
 // knn.hip -- spatial order and exact kNN
-size_t knn_tree_bytes(long long n);
-// Morton keys of the centres over their bounding cube (10 bits per axis).
+// Morton keys of the centres over their bounding cube (10 bits per axis);
+// the bounds go to temp[0..5] (f2ord values).
 void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
                         void* temp, hipStream_t st);
-// Exact kNN over the splats in working order, which must be sorted by the
-// Morton key of the centres over `box` (the bounds written by
-// launch_morton_keys).  Output nbr[p][k] holds the PHYSICAL indices of the
-// k_eff nearest (key (d2, logical)); -1 padded.  Two steps sharing tree_mem:
-// the cell table (+ logical -> working inverse; *d_unsorted is or-ed with 1
-// if the order is violated), then the query.
-void knn_working_tree(const float4* cen, int n, const unsigned* box, void* tree_mem,
-                      int* d_unsorted, hipStream_t st);
-void knn_working_query(const float4* cen, int n, int k, int keff, const unsigned* box, int* nbr,
-                       void* tree_mem, hipStream_t st);
+int table_level(long long n);
+int kclass_of(int keff);
+unsigned class_bit(int kclass);
+long long table_entries(int LT);
+// kNN scratch: concatenated per-segment cell tables, logical -> working
+// inverse, sparse-query list.
+struct KnnMem {
+  int* hist;
+  int* table;
+  int* inv;
+  int* sflag;
+  int* spos;
+  int* sparse;
+  int* counters;  // [1]: sparse count
+  void* scan_temp;
+};
+KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes);
+// Cell tables of every segment with LT > 0 (rows sorted by Morton key within
+// each segment; *d_unsorted or-ed with 1 if not).  invert: also the logical
+// -> working inverse (rows carry their logical index in cen[].w).
+void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
+               void* mem, int* d_unsorted, bool invert, hipStream_t st);
+// Exact kNN of every row of a segment with kclass > 0 among the rows of its
+// segment: nbr[p][t], t < keff of the segment, key (d2, logical); rows of
+// other segments get -1.  Entries are working rows (use_inv) or logical
+// indices; rows_logical: row index = logical index.  class_mask: bits of
+// the kernel classes present (class_bit).
+void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
+               unsigned class_mask, long long entries, void* mem, bool use_inv, int rows_logical,
+               int* nbr, hipStream_t st);
 // Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
 size_t knn_plain_bytes(long long n);
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);
@@ -200,9 +237,15 @@ void union_edges_public(const int* nbr, int n, int k, int* ei, int* ej, long lon
                         hipStream_t st);
 
 // cost.hip -- per-splat precompute and the edge cost
-struct CrnArgs {
+// Shared draws of a pass (Appendix A): tab[r * NG_CRN_ROW + 4 s + c] is draw
+// s (u, z0, z1, z2) of table row r; a segment reads row seg[sg[p]].crn (row
+// 0 when sg is null).
+#define NG_CRN_ROW 64
+struct CrnTab {
+  const float* tab;  // device
   int S;
-  float v[16][4];
+  const int* sg;
+  const SegInfo* seg;
 };
 // Adjacency entries written by the cost kernels: each edge (src, tgt) puts
 // key (orderable cost << 32 | logical index of the other end) and the other
@@ -220,13 +263,13 @@ void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st);
 // smaller logical index (cen[].w) is the mixture's first component;
 // otherwise ea[e] is.  adj.akey nullable.
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
-                      const int* ea, const int* eb, int m, int n, bool orient,
-                      const CrnArgs& crn, float fb_ratio, float* cost, float* dgeo, int* fb_list,
-                      int* fb_count, AdjOut adj, hipStream_t st);
+                      const int* ea, const int* eb, int m, int n, bool orient, const CrnTab& crn,
+                      float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
+                      AdjOut adj, hipStream_t st);
 // FP64 cost of the listed edges (list nullable: all edges [0, count_host)).
 void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
                            const int* ea, const int* eb, int n, bool orient, const int* list,
-                           const int* d_count, int count_cap, const CrnArgs& crn, float* cost,
+                           const int* d_count, int count_cap, const CrnTab& crn, float* cost,
                            float* dgeo, AdjOut adj, hipStream_t st);
 
 // select.hip -- greedy disjoint pairs by locally-dominant matching
@@ -235,7 +278,7 @@ struct Adjacency {
   unsigned long long* akey;  // [aoff[n]]
   int* au;                   // [aoff[n]]
 };
-size_t select_temp_bytes(long long n, long long m);
+size_t select_temp_bytes(long long n, long long m, int nseg);
 size_t select_adj_bytes(long long n, long long m);
 // Adjacency of an arbitrary edge list (cost per edge, caller numbering).
 void build_adjacency(const int* ea, const int* eb, const float* cost, long long m, int n,
@@ -244,25 +287,32 @@ struct SelectResult {
   long long pairs;
   int iters;
 };
-// partner[n] (physical); pair tie-break on lg (nullable: identity).
-// d_npairs (nullable, device int64) receives the pair count.  Synchronises st.
-SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long max_pairs,
-                          int* partner, void* temp, hipStream_t st, long long* d_npairs);
+// partner[n] (physical); pair tie-break on lg (nullable: identity).  Each of
+// the nseg segments (row -> segment in sg, nullable when nseg = 1) keeps at
+// most hP[s] pairs (host array); hM (host, nullable) receives the pairs kept
+// per segment, d_npairs (device int64, nullable) segment 0's count.
+// Synchronises st.
+SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
+                          const long long* hP, int* partner, void* temp, hipStream_t st,
+                          long long* d_npairs, long long* hM);
 
 // merge.hip -- MPMM merge + stable compaction in working layout
 size_t merge_temp_bytes(long long n);
-// Returns the new count.  lg nullable (identity).  morton_box nullable: when
-// given (the bounds written by launch_morton_keys), the output rows are
-// placed in Morton order of the output centres (the physical order of the
-// working set is free; the logical numbering is unaffected); otherwise
-// survivors keep their relative order.  Writes the provenance pairs
+// Returns the new count.  lg nullable (identity).  seg nullable: when given
+// (segments of the rows in sg), rows of segments with next < 0 are dropped,
+// sg_o receives each row's new segment position, and the output rows are
+// placed by (segment, Morton key of the output centre over the segment's
+// box): the physical order of the working set is free, the logical
+// numbering is unaffected.  Without seg, survivors keep their relative
+// order.  Writes the provenance pairs
 // (min origin, max origin) of the merges to trace (nullable) in the order of
 // the lower logical index.
 // Synchronises st.
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
-                        hipStream_t st, int* d_nout_i32, const unsigned* morton_box);
+                        hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
+                        const SegInfo* seg, int nseg);
 
 // crn.cpp
 void crn_host(uint64_t seed, int round, int S, float* out);

@@ -19,6 +19,7 @@
 // in double without contraction.  The result is the exact kNN with ties
 // broken by index.
 #include <algorithm>
+#include <cstring>
 #include <climits>
 
 #include "internal.h"
@@ -109,28 +110,46 @@ __global__ void k_iota(int* v, int n) {
 // whose level-LT cell is >= c (cstart[ncells] = n); a cell of a coarser level
 // L is the range [cstart[c << 3(LT-L)], cstart[(c+1) << 3(LT-L)]).
 
-// hist[c] = rows in level-LT cell c, from the run boundaries of the sorted
-// keys (each run adds its end and subtracts its start); flags a key that is
-// smaller than its predecessor.
-__global__ void k_cell_runs(const float4* __restrict__ cen, int n, const unsigned* __restrict__ box,
-                            int shift, int* __restrict__ hist, int* __restrict__ unsorted) {
+// hist[toff + c] = rows of segment sid in its level-LT cell c, from the run
+// boundaries of the sorted keys (each run adds its end and subtracts its
+// start); flags a key that is smaller than its predecessor in the segment.
+// Segments without a table (LT = 0) are skipped.
+__global__ void k_cell_runs(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
+                            const SegInfo* __restrict__ seg, int* __restrict__ hist,
+                            int* __restrict__ unsorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const SegInfo& S = seg[sg ? sg[i] : 0];
+  if (S.LT <= 0) return;
+  const int shift = 3 * (10 - S.LT);
   const float4 c = cen[i];
-  const unsigned key = morton_key(c.x, c.y, c.z, box);
+  const unsigned key = morton_key(c.x, c.y, c.z, S.box);
   const unsigned cell = key >> shift;
+  const bool first = i == S.row0;
+  const bool last = i + 1 == S.row0 + S.nrows;
   unsigned prev_key = 0u, next_cell = ~0u;
-  if (i > 0) {
+  if (!first) {
     const float4 a = cen[i - 1];
-    prev_key = morton_key(a.x, a.y, a.z, box);
+    prev_key = morton_key(a.x, a.y, a.z, S.box);
   }
-  if (i + 1 < n) {
+  if (!last) {
     const float4 b = cen[i + 1];
-    next_cell = morton_key(b.x, b.y, b.z, box) >> shift;
+    next_cell = morton_key(b.x, b.y, b.z, S.box) >> shift;
   }
-  if (i > 0 && prev_key > key) atomicOr(unsorted, 1);
-  if (i == 0 || (prev_key >> shift) != cell) atomicAdd(&hist[cell], -i);
-  if (next_cell != cell) atomicAdd(&hist[cell], i + 1);
+  if (!first && prev_key > key) atomicOr(unsorted, 1);
+  if (first || (prev_key >> shift) != cell) atomicAdd(&hist[S.toff + cell], -(i - S.row0));
+  if (last || next_cell != cell) atomicAdd(&hist[S.toff + cell], i - S.row0 + 1);
+}
+
+// Rows of segments without a search (inert): empty lists.  Every row starts
+// as not sparse.
+__global__ void k_knn_prefill(int n, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
+                              int k_out, int* __restrict__ nbr, int* __restrict__ sparse_flag) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  sparse_flag[p] = 0;
+  if (seg[sg ? sg[p] : 0].kclass == 0)
+    for (int t = 0; t < k_out; ++t) nbr[(long long)p * k_out + t] = -1;
 }
 
 // ---- query -----------------------------------------------------------------
@@ -237,12 +256,19 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
 // is seen twice.
 template <int K>
 __global__ void __launch_bounds__(64)
-k_knn_grid(const float4* __restrict__ cen, int n, int keff, int k_out,
-           const unsigned* __restrict__ box, int LT, const int* __restrict__ cstart,
+k_knn_grid(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
+           const SegInfo* __restrict__ seg, const int* __restrict__ table,
            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
            int* __restrict__ sparse_flag) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
+  const SegInfo& S = seg[sg ? sg[p] : 0];
+  if (S.kclass != K) return;  // another launch (or none: inert) serves it
+  const int keff = S.keff;
+  const int LT = S.LT;
+  const unsigned* box = S.box;
+  const int* cstart = table + S.toff;
+  const int rb = S.row0 - cstart[0];  // table values -> rows
   const float4 cq = cen[p];
   const double qx = cq.x, qy = cq.y, qz = cq.z;
   const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
@@ -290,8 +316,8 @@ k_knn_grid(const float4* __restrict__ cen, int n, int keff, int k_out,
     const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                         spread10((unsigned)z);
     const unsigned f = mc << sub;
-    a = cstart[f];
-    b = cstart[f + (1u << sub)];
+    a = cstart[f] + rb;
+    b = cstart[f + (1u << sub)] + rb;
   };
   {
     int a, b;
@@ -398,25 +424,32 @@ struct WaveBest {
 
 template <int K>
 __global__ void __launch_bounds__(64)
-k_knn_wave(const float4* __restrict__ cen, int n, int keff, int k_out,
-           const unsigned* __restrict__ box, int LT, const int* __restrict__ cstart,
+k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
+           const SegInfo* __restrict__ seg, const int* __restrict__ table,
            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
            const int* __restrict__ list, const int* __restrict__ d_count) {
   __shared__ int s_start[128];
   __shared__ int s_pref[129];
   const int lane = threadIdx.x;
   const int count = *d_count;
-  const Grid g = grid_from_box(box);
-  float lof[3], hif[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lof[a] = ord2f(box[a]);
-    hif[a] = ord2f(box[3 + a]);
-  }
-  const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
-  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
   for (int qidx = blockIdx.x; qidx < count; qidx += gridDim.x) {
     const int p = list[qidx];
+    const SegInfo& S = seg[sg ? sg[p] : 0];
+    if (S.kclass != K) continue;  // wave-uniform: one query per wave
+    const int keff = S.keff;
+    const int LT = S.LT;
+    const unsigned* box = S.box;
+    const int* cstart = table + S.toff;
+    const int rb = S.row0 - cstart[0];
+    const Grid g = grid_from_box(box);
+    float lof[3], hif[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lof[a] = ord2f(box[a]);
+      hif[a] = ord2f(box[3 + a]);
+    }
+    const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
+    const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
     const float4 cq = cen[p];
     const double qx = cq.x, qy = cq.y, qz = cq.z;
     const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
@@ -478,7 +511,7 @@ k_knn_wave(const float4* __restrict__ cen, int n, int keff, int k_out,
                           spread10((unsigned)cz);
       const unsigned f = mc << sub;
       if (lane == 0) {
-        s_start[0] = cstart[f];
+        s_start[0] = cstart[f] + rb;
         s_pref[0] = 0;
         s_pref[1] = cstart[f + (1u << sub)] - cstart[f];
       }
@@ -510,8 +543,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int keff, int k_out,
               const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                                   spread10((unsigned)z);
               const unsigned f = mc << sub;
-              a = cstart[f];
-              b = cstart[f + (1u << sub)];
+              a = cstart[f] + rb;
+              b = cstart[f + (1u << sub)] + rb;
             }
           }
         }
@@ -578,99 +611,93 @@ __global__ void k_gather_cen(const float* __restrict__ xyz3, const int* __restri
                        xyz3[3 * (long long)i + 2], __int_as_float(i));
 }
 
-// Finest table level: about one level below 8^L ~ n, at most 7 (2M cells).
+}  // namespace
+
+// Finest table level of a segment of n rows: about 8^L >= n, at most 7.
 int table_level(long long n) {
   int L = 1;
   while (L < 7 && (1ll << (3 * L)) < n) ++L;
   return L;
 }
 
-// Table memory: cell counts, cell starts, the logical -> working inverse and
-// the order-check flag.
-struct TableMem {
-  int* hist;
-  int* cstart;
-  int* inv;
-  int* sflag;   // sparse flag per query
-  int* spos;    // its exclusive scan
-  int* sparse;  // sparse queries in working order
-  int* flag;    // [0]: order check (plain entry), [1]: sparse count
-};
-
-TableMem carve_table(void* base, long long n, size_t* bytes = nullptr) {
-  const long long ncells = 1ll << (3 * table_level(n));
-  Carver c(base);
-  TableMem t;
-  t.hist = c.take<int>(ncells + 1);
-  t.cstart = c.take<int>(ncells + 1);
-  t.inv = c.take<int>(n);
-  t.sflag = c.take<int>(n);
-  t.spos = c.take<int>(n);
-  t.sparse = c.take<int>(n);
-  t.flag = c.take<int>(64);
-  if (bytes) *bytes = c.bytes() + std::max(scan_temp_bytes(ncells + 1), scan_temp_bytes(n));
-  return t;
+int kclass_of(int keff) {
+  if (keff <= 0) return 0;
+  return keff <= 8 ? 8 : keff <= 16 ? 16 : keff <= 24 ? 24 : 32;
 }
 
-void build_table(const float4* cen, int n, const unsigned* box, void* mem, int* d_unsorted,
-                 hipStream_t st) {
-  TableMem t = carve_table(mem, n);
-  size_t tb = 0;
-  carve_table(nullptr, n, &tb);
-  void* stemp = (char*)mem + (tb - std::max(scan_temp_bytes((1ll << (3 * table_level(n))) + 1),
-                                            scan_temp_bytes(n)));
-  const int LT = table_level(n);
-  const long long ncells = 1ll << (3 * LT);
-  fill_i32(t.hist, 0, ncells + 1, st);
-  k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, box, 3 * (10 - LT), t.hist,
-                                                  d_unsorted);
+long long table_entries(int LT) { return LT > 0 ? (1ll << (3 * LT)) + 1 : 0; }
+
+KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes) {
+  Carver c(base);
+  KnnMem m;
+  m.hist = c.take<int>(entries + 1);
+  m.table = c.take<int>(entries + 1);
+  m.inv = c.take<int>(n);
+  m.sflag = c.take<int>(n);
+  m.spos = c.take<int>(n);
+  m.sparse = c.take<int>(n);
+  m.counters = c.take<int>(64);
+  const size_t scan = std::max(scan_temp_bytes(entries + 1), scan_temp_bytes(n));
+  m.scan_temp = base ? (char*)base + c.bytes() : nullptr;
+  if (bytes) *bytes = c.bytes() + scan;
+  return m;
+}
+
+void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
+               void* mem, int* d_unsorted, bool invert, hipStream_t st) {
+  KnnMem m = carve_knn(mem, n, entries, nullptr);
+  fill_i32(m.hist, 0, entries + 1, st);
+  k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, m.hist, d_unsorted);
   NG_LAUNCH_CHECK();
-  scan_exclusive_i32(t.hist, t.cstart, ncells + 1, nullptr, stemp, st);
+  scan_exclusive_i32(m.hist, m.table, entries + 1, nullptr, m.scan_temp, st);
+  if (invert) {
+    k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, m.inv);
+    NG_LAUNCH_CHECK();
+  }
 }
 
 template <int K>
-void query_k(const float4* cen, int n, int keff, int k_out, const unsigned* box,
-             const TableMem& t, void* stemp, const int* inv, int rows_logical, int* nbr,
-             hipStream_t st) {
-  const int LT = table_level(n);
-  k_knn_grid<K><<<blocks_for(n, 64), 64, 0, st>>>(cen, n, keff, k_out, box, LT, t.cstart, inv,
-                                                  rows_logical, nbr, t.sflag);
+void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
+             const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
+  k_knn_grid<K><<<blocks_for(n, 64), 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
+                                                  rows_logical, nbr, m.sflag);
   NG_LAUNCH_CHECK();
-  // sparse queries, compacted in working (Morton) order; their count stays
-  // on the device and a grid of fixed size strides over it
-  scan_exclusive_i32(t.sflag, t.spos, n, t.flag + 1, stemp, st);
-  k_scatter_flagged<<<blocks_for(n, 256), 256, 0, st>>>(t.sflag, t.spos, n, t.sparse);
-  NG_LAUNCH_CHECK();
+}
+
+template <int K>
+void query_wave_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
+                  const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
+  // the sparse count stays on the device: a grid of fixed size strides over it
   unsigned g = (unsigned)(n < 16384 ? n : 16384);
   if (g < 1) g = 1;
-  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, keff, k_out, box, LT, t.cstart, inv, rows_logical, nbr,
-                                  t.sparse, t.flag + 1);
+  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr,
+                                  m.sparse, m.counters + 1);
   NG_LAUNCH_CHECK();
 }
 
-void query(const float4* cen, int n, int keff, int k_out, const unsigned* box, void* mem,
-           const int* inv, int rows_logical, int* nbr, hipStream_t st) {
-  const TableMem t = carve_table(mem, n);
-  size_t tb = 0;
-  carve_table(nullptr, n, &tb);
-  void* stemp = (char*)mem + (tb - std::max(scan_temp_bytes((1ll << (3 * table_level(n))) + 1),
-                                            scan_temp_bytes(n)));
-  if (keff <= 8)
-    query_k<8>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
-  else if (keff <= 16)
-    query_k<16>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
-  else if (keff <= 24)
-    query_k<24>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
-  else
-    query_k<32>(cen, n, keff, k_out, box, t, stemp, inv, rows_logical, nbr, st);
+void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
+               unsigned class_mask, long long entries, void* mem, bool use_inv, int rows_logical,
+               int* nbr, hipStream_t st) {
+  KnnMem m = carve_knn(mem, n, entries, nullptr);
+  const int* inv = use_inv ? m.inv : nullptr;
+  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr, m.sflag);
+  NG_LAUNCH_CHECK();
+  if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 4u) query_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 8u) query_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  // sparse queries, compacted in working (Morton) order
+  scan_exclusive_i32(m.sflag, m.spos, n, m.counters + 1, m.scan_temp, st);
+  k_scatter_flagged<<<blocks_for(n, 256), 256, 0, st>>>(m.sflag, m.spos, n, m.sparse);
+  NG_LAUNCH_CHECK();
+  if (class_mask & 1u) query_wave_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 2u) query_wave_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 4u) query_wave_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 8u) query_wave_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
 }
 
-}  // namespace
-
-size_t knn_tree_bytes(long long n) {
-  size_t b = 0;
-  carve_table(nullptr, n, &b);
-  return b;
+unsigned class_bit(int kclass) {
+  return kclass == 8 ? 1u : kclass == 16 ? 2u : kclass == 24 ? 4u : kclass == 32 ? 8u : 0u;
 }
 
 void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
@@ -687,29 +714,18 @@ void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsign
   NG_LAUNCH_CHECK();
 }
 
-void knn_working_tree(const float4* cen, int n, const unsigned* box, void* tree_mem,
-                      int* d_unsorted, hipStream_t st) {
-  TableMem t = carve_table(tree_mem, n);
-  build_table(cen, n, box, tree_mem, d_unsorted, st);
-  k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, t.inv);
-  NG_LAUNCH_CHECK();
-}
-
-void knn_working_query(const float4* cen, int n, int k, int keff, const unsigned* box, int* nbr,
-                       void* tree_mem, hipStream_t st) {
-  TableMem t = carve_table(tree_mem, n);
-  query(cen, n, keff, k, box, tree_mem, t.inv, 0, nbr, st);
-}
-
-// Plain entry: centres in caller order -> Morton-sorted copy -> table -> rows
-// by caller index.
+// Plain entry: centres in caller order -> Morton-sorted copy -> one-segment
+// table -> rows by caller index.
 size_t knn_plain_bytes(long long n) {
   Carver c(nullptr);
   c.take<unsigned>(64);
   c.take<unsigned>(n);
   c.take<int>(n);
   c.take<float4>(n);
-  return c.bytes() + knn_tree_bytes(n) + sort_temp_bytes(n);
+  c.take<SegInfo>(1);
+  size_t kb = 0;
+  carve_knn(nullptr, n, table_entries(table_level(n)), &kb);
+  return c.bytes() + std::max(kb, sort_temp_bytes(n));
 }
 
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st) {
@@ -718,19 +734,31 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   unsigned* keys = c.take<unsigned>(n);
   int* perm = c.take<int>(n);
   float4* cen = c.take<float4>(n);
-  char* rest = (char*)ws + c.bytes();
-  void* tree_mem = rest;
-  void* sort_mem = rest + knn_tree_bytes(n);
+  SegInfo* dseg = c.take<SegInfo>(1);
+  void* rest = (char*)ws + c.bytes();
   launch_morton_keys(mu, nullptr, n, keys, boxmem, st);
   k_iota<<<blocks_for(n, 256), 256, 0, st>>>(perm, n);
   NG_LAUNCH_CHECK();
-  sort_pairs_u32(keys, perm, n, 30, sort_mem, st);
+  sort_pairs_u32(keys, perm, n, 30, rest, st);
   k_gather_cen<<<blocks_for(n, 256), 256, 0, st>>>(mu, perm, n, cen);
   NG_LAUNCH_CHECK();
-  TableMem t = carve_table(tree_mem, n);
-  fill_i32(t.flag, 0, 1, st);  // sorted above by the same keys: never set
-  build_table(cen, n, boxmem, tree_mem, t.flag, st);
-  query(cen, n, keff, k, boxmem, tree_mem, nullptr, 1, nbr, st);
+  SegInfo h;
+  std::memset(&h, 0, sizeof(h));
+  h.row0 = 0;
+  h.nrows = n;
+  h.LT = table_level(n);
+  h.toff = 0;
+  h.keff = keff;
+  h.kclass = kclass_of(keff);
+  NG_HIP(hipMemcpyAsync(dseg, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  NG_HIP(hipMemcpyAsync(dseg->box, boxmem, 6 * sizeof(unsigned), hipMemcpyDeviceToDevice, st));
+  const long long entries = table_entries(h.LT);
+  KnnMem m = carve_knn(rest, n, entries, nullptr);
+  fill_i32(m.counters, 0, 1, st);  // order check: sorted above by the same keys
+  knn_build(cen, n, nullptr, dseg, entries, rest, m.counters, false, st);
+  knn_query(cen, n, k, nullptr, dseg, class_bit(h.kclass), entries, rest, false, 1, nbr, st);
+  // the host copy of h must outlive the async copy
+  NG_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace ng

@@ -151,12 +151,14 @@ NG_DEV ScaleRot scale_rot_from_cov(Mat3 S) {
 }
 
 __global__ void k_keep_flags(const int* __restrict__ partner, const int* __restrict__ lg, int n,
+                             const int* __restrict__ sg, const SegInfo* __restrict__ seg,
                              int* __restrict__ keep, int* __restrict__ remL) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int j = partner[p];
   const int lp = logical(lg, p);
-  const bool removed = j >= 0 && j < n && logical(lg, j) < lp;
+  const bool dropped = seg && seg[sg[p]].next < 0;
+  const bool removed = dropped || (j >= 0 && j < n && logical(lg, j) < lp);
   keep[p] = removed ? 0 : 1;
   remL[lp] = removed ? 1 : 0;
 }
@@ -182,13 +184,15 @@ NG_DEV float merged_coord(double pa, double pb, float a, float b) {
 // sort key of its output centre.
 __global__ void k_out_keys(const float4* __restrict__ cen, const float4* __restrict__ shp, int n,
                            const int* __restrict__ partner, const int* __restrict__ keep,
-                           const int* __restrict__ newpos, const unsigned* __restrict__ box,
-                           unsigned* __restrict__ keys, int* __restrict__ order) {
+                           const int* __restrict__ newpos, const int* __restrict__ sg,
+                           const SegInfo* __restrict__ seg, unsigned* __restrict__ keys,
+                           int* __restrict__ order) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n || !keep[p]) return;
   const int q = newpos[p];
   order[q] = p;
-  if (!box) return;
+  if (!seg) return;
+  const unsigned* box = seg[sg[p]].box;
   const float4 ca = cen[p];
   float x = ca.x, y = ca.y, z = ca.z;
   const int j = partner[p];
@@ -203,13 +207,22 @@ __global__ void k_out_keys(const float4* __restrict__ cen, const float4* __restr
   keys[q] = morton_key(x, y, z, box);
 }
 
+// segment of each row in the Morton-sorted order (key of the stable second
+// sort that groups the rows by segment)
+__global__ void k_order_seg(const int* __restrict__ order, const int* __restrict__ sg, int nout,
+                            unsigned* __restrict__ segkey) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nout) segkey[q] = (unsigned)sg[order[q]];
+}
+
 // float4 desc[q] = (src_a bits, src_b bits, weight_a, weight_b): how output
 // row q of the SH array is formed.  Thread per output row q, source row
 // order[q].
 __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restrict__ lg,
                               const float4* __restrict__ shp, const int* __restrict__ org, int n,
                               const int* __restrict__ partner, const int* __restrict__ order,
-                              int nout, const int* __restrict__ rsum,
+                              int nout, const int* __restrict__ rsum, const int* __restrict__ sg,
+                              int* __restrict__ sg_o, const SegInfo* __restrict__ seg,
                               float4* __restrict__ cen_o, int* __restrict__ lg_o,
                               float4* __restrict__ shp_o, int* __restrict__ org_o,
                               float4* __restrict__ desc, int* __restrict__ trace,
@@ -219,6 +232,7 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
   const int p = order[q];
   const int lp = logical(lg, p);
   const int newL = lp - rsum[lp];
+  if (sg_o) sg_o[q] = seg ? seg[sg[p]].next : 0;
   const int j = partner[p];
   const float4 ca = cen[p];
   const float4 sa = shp[2 * (long long)p], qa = shp[2 * (long long)p + 1];
@@ -300,7 +314,8 @@ size_t merge_temp_bytes(long long n) {
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
-                        hipStream_t st, int* d_nout_i32, const unsigned* morton_box) {
+                        hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
+                        const SegInfo* seg, int nseg) {
   Carver c(temp);
   int* keep = c.take<int>(n);
   int* newpos = c.take<int>(n);
@@ -312,29 +327,42 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   int* counters = c.take<int>(64);
   void* stemp = (char*)temp + c.bytes();
   long long* host = pinned_host();
-  k_keep_flags<<<blocks_for(n, 256), 256, 0, st>>>(partner, lg, n, keep, remL);
+  k_keep_flags<<<blocks_for(n, 256), 256, 0, st>>>(partner, lg, n, seg ? sg : nullptr, seg, keep,
+                                                   remL);
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(keep, newpos, n, counters, stemp, st);
   scan_exclusive_i32(remL, rsum, n, counters + 1, stemp, st);
   if (trace) fill_i32(counters + 2, 0, 1, st);
-  k_out_keys<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, n, partner, keep, newpos, morton_box,
-                                                 keys, order);
+  k_out_keys<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, n, partner, keep, newpos,
+                                                 seg ? sg : nullptr, seg, keys, order);
   NG_LAUNCH_CHECK();
   NG_HIP(hipMemcpyAsync(host, counters, sizeof(int), hipMemcpyDeviceToHost, st));
   if (d_nout_i32)
     NG_HIP(hipMemcpyAsync(d_nout_i32, counters, sizeof(int), hipMemcpyDeviceToDevice, st));
   NG_HIP(hipStreamSynchronize(st));
   const long long nout = *(int*)host;
-  // Morton order of the output centres (stable: equal keys keep the
-  // compacted order)
-  if (morton_box) sort_pairs_u32(keys, order, nout, 30, stemp, st);
-  k_merge_attrs<<<blocks_for(nout, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order,
-                                                       (int)nout, rsum, cen_o, lg_o, shp_o, org_o,
-                                                       desc, trace, counters + 2);
-  NG_LAUNCH_CHECK();
-  k_merge_sh<<<blocks_for(nout * 12, 256), 256, 0, st>>>((const float4*)sh, desc, (int)nout,
-                                                         (float4*)sh_o);
-  NG_LAUNCH_CHECK();
+  if (seg && nout > 0) {
+    // Morton order of the output centres within each segment (stable:
+    // equal keys keep the compacted order), then grouped by segment
+    sort_pairs_u32(keys, order, nout, 30, stemp, st);
+    if (nseg > 1) {
+      k_order_seg<<<blocks_for(nout, 256), 256, 0, st>>>(order, sg, (int)nout, keys);
+      NG_LAUNCH_CHECK();
+      int bits = 1;
+      while ((1 << bits) < nseg) ++bits;
+      sort_pairs_u32(keys, order, nout, bits, stemp, st);
+    }
+  }
+  if (nout > 0) {
+    k_merge_attrs<<<blocks_for(nout, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order,
+                                                         (int)nout, rsum, seg ? sg : nullptr,
+                                                         sg_o, seg, cen_o, lg_o, shp_o, org_o,
+                                                         desc, trace, counters + 2);
+    NG_LAUNCH_CHECK();
+    k_merge_sh<<<blocks_for(nout * 12, 256), 256, 0, st>>>((const float4*)sh, desc, (int)nout,
+                                                           (float4*)sh_o);
+    NG_LAUNCH_CHECK();
+  }
   return nout;
 }
 

@@ -151,22 +151,44 @@ k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n
   }
 }
 
-// ---- budget: keep the P smallest (cost, i, j) of the matching --------------
-// Single workgroup radix select (the matching of the last pass only).
+// ---- budget: keep the P smallest (cost, i, j) of each segment's matching --
+// Pairs of segment b: idx[pstart[b] .. pend[b]) (idx null: pairs [0, M)).
+// One workgroup per segment runs a radix select when its matching exceeds
+// its budget P[b] (the matching of a segment's last pass only); mseg[b]
+// receives the pairs kept.
 __global__ void __launch_bounds__(1024)
-k_topp(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
-       const unsigned* __restrict__ pair_c, const int* __restrict__ d_M,
-       const int* __restrict__ lg, long long Pll, int* __restrict__ partner) {
+k_topp_seg(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
+           const unsigned* __restrict__ pair_c, const int* __restrict__ idx,
+           const int* __restrict__ pstart, const int* __restrict__ pend,
+           const int* __restrict__ d_M, const long long* __restrict__ Pseg,
+           const int* __restrict__ lg, int* __restrict__ partner, int* __restrict__ mseg) {
   __shared__ int hist[256];
   __shared__ unsigned s_prefix;
   __shared__ int s_need, s_tie_count;
   __shared__ unsigned long long s_prefix2;
-  const int M = *d_M;
-  if ((long long)M <= Pll) return;
-  const int P = (int)Pll;
+  const int b = blockIdx.x;
+  const int i0 = idx ? pstart[b] : 0;
+  const int M = idx ? pend[b] - pstart[b] : *d_M;
+  const long long Pll = Pseg[b];
+  if ((long long)M <= Pll) {
+    if (threadIdx.x == 0) mseg[b] = M;
+    return;
+  }
+  const int P = (int)(Pll > 0 ? Pll : 0);
+  auto at = [&](int i) { return idx ? idx[i0 + i] : i; };
   if (threadIdx.x == 0) {
     s_prefix = 0u;
     s_need = P;
+    mseg[b] = P;
+  }
+  __syncthreads();
+  if (P == 0) {
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+      const int e = at(i);
+      partner[pair_a[e]] = -1;
+      partner[pair_b[e]] = -1;
+    }
+    return;
   }
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
@@ -175,7 +197,7 @@ k_topp(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
     __syncthreads();
     const unsigned pref = s_prefix;
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
-      const unsigned k = pair_c[i];
+      const unsigned k = pair_c[at(i)];
       if ((k & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k >> shift) & 255u], 1);
     }
     __syncthreads();
@@ -203,10 +225,11 @@ k_topp(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
       __syncthreads();
       const unsigned long long pref = s_prefix2;
       for (int i = threadIdx.x; i < M; i += blockDim.x) {
-        if (pair_c[i] != T) continue;
+        const int e = at(i);
+        if (pair_c[e] != T) continue;
         const unsigned long long k2 =
-            ((unsigned long long)(unsigned)logical(lg, pair_a[i]) << 32) |
-            (unsigned long long)(unsigned)logical(lg, pair_b[i]);
+            ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
+            (unsigned long long)(unsigned)logical(lg, pair_b[e]);
         if ((k2 & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k2 >> shift) & 255ull], 1);
       }
       __syncthreads();
@@ -224,25 +247,42 @@ k_topp(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
   }
   const unsigned long long T2 = s_prefix2;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const unsigned k = pair_c[i];
+    const int e = at(i);
+    const unsigned k = pair_c[e];
     bool kp = k < T;
     if (k == T) {
-      const unsigned long long k2 = ((unsigned long long)(unsigned)logical(lg, pair_a[i]) << 32) |
-                                    (unsigned long long)(unsigned)logical(lg, pair_b[i]);
+      const unsigned long long k2 = ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
+                                    (unsigned long long)(unsigned)logical(lg, pair_b[e]);
       kp = k2 <= T2;
     }
     if (!kp) {
-      partner[pair_a[i]] = -1;
-      partner[pair_b[i]] = -1;
+      partner[pair_a[e]] = -1;
+      partner[pair_b[e]] = -1;
     }
   }
 }
 
-__global__ void k_store_npairs(const int* __restrict__ v, long long cap, long long* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    long long x = *v;
-    *out = x < cap ? x : cap;
-  }
+// segment of every pair (sort key) and the identity payload
+__global__ void k_pair_seg(const int* __restrict__ pair_a, const int* __restrict__ sg, int M,
+                           unsigned* __restrict__ key, int* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  key[i] = (unsigned)sg[pair_a[i]];
+  idx[i] = i;
+}
+
+// [pstart[s], pend[s]) = run of segment s in the sorted keys
+__global__ void k_seg_runs(const unsigned* __restrict__ key, int M, int* __restrict__ pstart,
+                           int* __restrict__ pend) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const unsigned s = key[i];
+  if (i == 0 || key[i - 1] != s) pstart[s] = i;
+  if (i == M - 1 || key[i + 1] != s) pend[s] = i + 1;
+}
+
+__global__ void k_store_npairs(const int* __restrict__ v, long long* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = (long long)*v;
 }
 
 unsigned grid_for(long long cnt) {
@@ -252,7 +292,7 @@ unsigned grid_for(long long cnt) {
 
 }  // namespace
 
-size_t select_temp_bytes(long long n, long long m) {
+size_t select_temp_bytes(long long n, long long m, int nseg) {
   Carver c(nullptr);
   c.take<int>(n);                 // pick
   c.take<unsigned>(n);            // pcost
@@ -261,9 +301,15 @@ size_t select_temp_bytes(long long n, long long m) {
   c.take<int>(n / 2 + 1);         // pair_a
   c.take<int>(n / 2 + 1);         // pair_b
   c.take<unsigned>(n / 2 + 1);    // pair_c
+  c.take<unsigned>(n / 2 + 1);    // pair segment keys
+  c.take<int>(n / 2 + 1);         // pair order
+  c.take<int>(nseg);              // pstart
+  c.take<int>(nseg);              // pend
+  c.take<long long>(nseg);        // budgets
+  c.take<int>(nseg);              // pairs kept
   c.take<int>(64);                // counters
   (void)m;
-  return c.bytes();
+  return c.bytes() + sort_temp_bytes(n / 2 + 1);
 }
 
 size_t select_adj_bytes(long long n, long long m) {
@@ -302,8 +348,9 @@ void build_adjacency(const int* ea, const int* eb, const float* cost, long long 
   }
 }
 
-SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long max_pairs,
-                          int* partner, void* temp, hipStream_t st, long long* d_npairs) {
+SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
+                          const long long* hP, int* partner, void* temp, hipStream_t st,
+                          long long* d_npairs, long long* hM) {
   Carver c(temp);
   int* pick = c.take<int>(n);
   unsigned* pcost = c.take<unsigned>(n);
@@ -311,7 +358,14 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long 
   int* pair_a = c.take<int>(n / 2 + 1);
   int* pair_b = c.take<int>(n / 2 + 1);
   unsigned* pair_c = c.take<unsigned>(n / 2 + 1);
+  unsigned* pkey = c.take<unsigned>(n / 2 + 1);
+  int* pidx = c.take<int>(n / 2 + 1);
+  int* pstart = c.take<int>(nseg);
+  int* pend = c.take<int>(nseg);
+  long long* Pdev = c.take<long long>(nseg);
+  int* mseg = c.take<int>(nseg);
   int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs
+  void* stemp = (char*)temp + c.bytes();
   long long* host = pinned_host();
 
   fill_i32(partner, -1, n, st);
@@ -343,17 +397,49 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, long long 
     if (known == 0) break;
   }
   r.iters = it;
-  long long M = ((const int*)host)[2];
-  if (M > max_pairs) {
-    k_topp<<<1, 1024, 0, st>>>(pair_a, pair_b, pair_c, counters + 2, lg, max_pairs, partner);
-    NG_LAUNCH_CHECK();
-    M = max_pairs;
+  const long long M = ((const int*)host)[2];
+  // per-segment budgets (the matching of each segment, then its P smallest)
+  NG_HIP(hipMemcpyAsync(Pdev, hP, nseg * sizeof(long long), hipMemcpyHostToDevice, st));
+  const int* idx = nullptr;
+  if (nseg > 1) {
+    fill_i32(pstart, 0, nseg, st);
+    fill_i32(pend, 0, nseg, st);
+    if (M > 0) {
+      k_pair_seg<<<blocks_for(M, 256), 256, 0, st>>>(pair_a, sg, (int)M, pkey, pidx);
+      NG_LAUNCH_CHECK();
+      int bits = 1;
+      while ((1 << bits) < nseg) ++bits;
+      sort_pairs_u32(pkey, pidx, M, bits, stemp, st);
+      k_seg_runs<<<blocks_for(M, 256), 256, 0, st>>>(pkey, (int)M, pstart, pend);
+      NG_LAUNCH_CHECK();
+    }
+    idx = pidx;
   }
+  k_topp_seg<<<nseg, 1024, 0, st>>>(pair_a, pair_b, pair_c, idx, pstart, pend, counters + 2, Pdev,
+                                     lg, partner, mseg);
+  NG_LAUNCH_CHECK();
   if (d_npairs) {
-    k_store_npairs<<<1, 64, 0, st>>>(counters + 2, max_pairs, d_npairs);
+    k_store_npairs<<<1, 64, 0, st>>>(mseg, d_npairs);
     NG_LAUNCH_CHECK();
   }
-  r.pairs = M;
+  long long total = 0;
+  if (hM) {
+    int* hm = (int*)(host + 8);
+    for (int s0 = 0; s0 < nseg; s0 += 96) {
+      const int cnt = nseg - s0 < 96 ? nseg - s0 : 96;
+      NG_HIP(hipMemcpyAsync(hm, mseg + s0, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+      NG_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < cnt; ++i) {
+        hM[s0 + i] = hm[i];
+        total += hm[i];
+      }
+    }
+  } else {
+    NG_HIP(hipStreamSynchronize(st));  // hP may be a stack value of the caller
+    total = M;
+    for (int i = 0; i < nseg; ++i) total = total < hP[i] ? total : hP[i];
+  }
+  r.pairs = total;
   return r;
 }
 
