@@ -246,6 +246,63 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,
                            int64_t* d_nout, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 
+/* ---- batched and served form: many scenes per pass ---------------------- */
+
+/* A batch keeps several simplification jobs (scenes) in one working set and
+ * runs one pass of Algorithm 1 for all of them with one launch per stage;
+ * every job gets the same result as nanogs_simplify with the same options
+ * and seed (its draws are keyed by its own seed and pass).  Jobs join at pass
+ * boundaries as rows free up and leave when they reach their target, so a
+ * serving loop can keep the device busy with requests that arrive at any
+ * time.  A batch is a host object bound to one stream; it is not
+ * thread-safe. */
+typedef struct nanogs_batch nanogs_batch;
+
+/* Workspace of a batch holding at most max_rows splats of at most max_jobs
+ * jobs at a time, with kNN sizes up to max_k (1..NANOGS_MAX_K). */
+size_t nanogs_batch_workspace_bytes(int64_t max_rows, int32_t max_k,
+                                    int32_t max_jobs);
+
+/* Creates a batch over the caller's device workspace ws (ws_bytes from
+ * nanogs_batch_workspace_bytes, 256-byte aligned), which must outlive it.
+ * opt (nullable) applies to every job except its seed, which is per job.
+ * Errors: EINVAL, EWORKSPACE. */
+nanogs_status nanogs_batch_create(int64_t max_rows, int32_t max_k,
+                                  int32_t max_jobs, const nanogs_options* opt,
+                                  void* ws, size_t ws_bytes, hipStream_t stream,
+                                  nanogs_batch** out);
+void nanogs_batch_destroy(nanogs_batch* b);
+
+/* Queues a job: simplify the n splats of `in` (device, stored form) to
+ * target_n with kNN size k and draw seed `seed`, writing the result to
+ * `out` (device, capacity n) and, if d_origin is non-null, each output
+ * splat's provenance (smallest input index it absorbed) to d_origin[n].  The
+ * buffers must stay valid until the job is done; `in` is read when the job
+ * joins a pass.  *job_id (host) receives the job's handle.  Errors: EINVAL
+ * (n < 1, n > max_rows, target_n < 1, k outside 1..max_k). */
+nanogs_status nanogs_batch_submit(nanogs_batch* b, const nanogs_gaussians* in,
+                                  int64_t n, int64_t target_n, int32_t k,
+                                  uint64_t seed, nanogs_gaussians* out,
+                                  int32_t* d_origin, int32_t* job_id);
+
+/* One pass for every job in the working set; queued jobs join first, in
+ * submission order, while their rows fit.  *n_done (nullable) receives the
+ * number of jobs that completed (or failed) in this call.  Synchronises the
+ * stream. */
+nanogs_status nanogs_batch_step(nanogs_batch* b, int32_t* n_done);
+
+/* Steps until every submitted job is done. */
+nanogs_status nanogs_batch_run(nanogs_batch* b);
+
+/* Job state: 0 queued, 1 running, 2 done (output written), or minus the
+ * nanogs_status it failed with.  n_out and stats are nullable (host). */
+nanogs_status nanogs_batch_job(const nanogs_batch* b, int32_t job_id,
+                               int32_t* state, int64_t* n_out,
+                               nanogs_stats* stats);
+
+/* Splats currently held in the working set (admission control). */
+int64_t nanogs_batch_rows_in_use(const nanogs_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -225,6 +225,12 @@ size_t merge_ws_bytes(long long n) {
 
 using namespace ng;
 
+struct nanogs_batch {
+  Engine* eng;
+  Opts opts;
+  int kmax;
+};
+
 extern "C" {
 
 void nanogs_default_options(nanogs_options* opt) {
@@ -488,5 +494,132 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* pa
     return NANOGS_OK;
   });
 }
+
+// ---- batched and served form ----------------------------------------------
+
+size_t nanogs_batch_workspace_bytes(int64_t max_rows, int32_t max_k, int32_t max_jobs) {
+  if (max_rows < 1 || max_k < 1 || max_k > NANOGS_MAX_K || max_jobs < 1) return 0;
+  return Engine::workspace_bytes(max_rows, max_k, max_jobs);
+}
+
+nanogs_status nanogs_batch_create(int64_t max_rows, int32_t max_k, int32_t max_jobs,
+                                  const nanogs_options* opt, void* ws, size_t ws_bytes,
+                                  hipStream_t stream, nanogs_batch** out) {
+  return guarded([&]() -> nanogs_status {
+    if (!out) {
+      set_error("out is null");
+      return NANOGS_EINVAL;
+    }
+    *out = nullptr;
+    if (max_rows < 1 || max_jobs < 1 || max_jobs > 4096) {
+      set_error("max_rows must be >= 1 and max_jobs in [1, 4096]");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_n(max_rows, max_k));
+    Opts o;
+    NG_CHECK(read_opts(opt, &o));
+    if (o.d_trace || o.d_origin) {
+      set_error("batch options take no trace/origin buffers (origin is per job)");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_ws(ws, ws_bytes, Engine::workspace_bytes(max_rows, max_k, max_jobs)));
+    nanogs_batch* b = new nanogs_batch;
+    b->eng = new Engine(max_rows, max_k, max_jobs, o, ws, stream);
+    b->opts = o;
+    b->kmax = max_k;
+    *out = b;
+    return NANOGS_OK;
+  });
+}
+
+void nanogs_batch_destroy(nanogs_batch* b) {
+  if (!b) return;
+  delete b->eng;
+  delete b;
+}
+
+nanogs_status nanogs_batch_submit(nanogs_batch* b, const nanogs_gaussians* in, int64_t n,
+                                  int64_t target_n, int32_t k, uint64_t seed,
+                                  nanogs_gaussians* out, int32_t* d_origin, int32_t* job_id) {
+  return guarded([&]() -> nanogs_status {
+    if (!b || !job_id) {
+      set_error("batch or job_id is null");
+      return NANOGS_EINVAL;
+    }
+    if (n < 1 || n > b->eng->capacity()) {
+      set_error("n must be in [1, max_rows]");
+      return NANOGS_EINVAL;
+    }
+    if (target_n < 1) {
+      set_error("target_n must be >= 1");
+      return NANOGS_EINVAL;
+    }
+    if (k < 1 || k > b->kmax) {
+      set_error("k must be in [1, max_k]");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_gaussians(in, "in"));
+    NG_CHECK(check_gaussians(out, "out"));
+    if (in->pos == out->pos || in->sh == out->sh) {
+      set_error("in and out may not alias");
+      return NANOGS_EINVAL;
+    }
+    if (d_origin) NG_CHECK(check_ptr(d_origin, 4, "d_origin"));
+    JobSpec js;
+    js.in = *in;
+    js.out = *out;
+    js.n = n;
+    js.target = target_n;
+    js.k = k;
+    js.seed = seed;
+    js.d_origin = d_origin;
+    *job_id = b->eng->submit(js);
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_batch_step(nanogs_batch* b, int32_t* n_done) {
+  return guarded([&]() -> nanogs_status {
+    if (!b) {
+      set_error("batch is null");
+      return NANOGS_EINVAL;
+    }
+    const int d = b->eng->step(nullptr);
+    if (n_done) *n_done = d;
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_batch_run(nanogs_batch* b) {
+  return guarded([&]() -> nanogs_status {
+    if (!b) {
+      set_error("batch is null");
+      return NANOGS_EINVAL;
+    }
+    b->eng->run(nullptr);
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_batch_job(const nanogs_batch* b, int32_t job_id, int32_t* state,
+                               int64_t* n_out, nanogs_stats* stats) {
+  if (!b || !state || job_id < 0 || job_id >= b->eng->num_jobs()) {
+    set_error("bad batch, job id or state pointer");
+    return NANOGS_EINVAL;
+  }
+  const Job& j = b->eng->job(job_id);
+  switch (j.state) {
+    case JOB_QUEUED: *state = 0; break;
+    case JOB_RUNNING: *state = 1; break;
+    case JOB_DRAINING:
+    case JOB_DONE: *state = 2; break;
+    default: *state = -j.status; break;
+  }
+  if (n_out) *n_out = (j.state == JOB_DRAINING || j.state == JOB_DONE) ? j.stats.n_out : 0;
+  if (stats) *stats = j.stats;
+  return NANOGS_OK;
+}
+
+int64_t nanogs_batch_rows_in_use(const nanogs_batch* b) { return b ? b->eng->rows_in_use() : 0; }
 
 }  // extern "C"

@@ -109,6 +109,18 @@ _SIGS = {
     "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
+    "nanogs_batch_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
+    "nanogs_batch_create": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(Options), _P, _SZ,
+                                           _P, ctypes.POINTER(_P)]),
+    "nanogs_batch_destroy": (None, [_P]),
+    "nanogs_batch_submit": (ctypes.c_int, [_P, ctypes.POINTER(Gaussians), _I64, _I64, _I32,
+                                           ctypes.c_uint64, ctypes.POINTER(Gaussians), _P,
+                                           ctypes.POINTER(_I32)]),
+    "nanogs_batch_step": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
+    "nanogs_batch_run": (ctypes.c_int, [_P]),
+    "nanogs_batch_job": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                                        ctypes.POINTER(Stats)]),
+    "nanogs_batch_rows_in_use": (_I64, [_P]),
     "nanogs_merge": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, ctypes.POINTER(Splats),
                                     _P, _P, _SZ, _P]),
 }
@@ -408,3 +420,92 @@ def merge(s: SplatTensors, partner):
     k = int(dn.item())
     return SplatTensors(out.mu[:k], out.scale[:k], out.quat[:k], out.alpha[:k], out.sh[:k],
                         out.origin[:k] if out.origin is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# batched / served form
+# ---------------------------------------------------------------------------
+JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
+
+
+def batch_workspace_bytes(max_rows: int, max_k: int, max_jobs: int) -> int:
+    return int(load().nanogs_batch_workspace_bytes(max_rows, max_k, max_jobs))
+
+
+class Batch:
+    """Many simplification jobs in one working set (nanogs_batch_*).
+
+    Jobs are submitted with their own device input/output tensors, join at
+    pass boundaries while rows are free, and leave when done.  step() runs
+    one pass for every job in the working set; run() steps until all jobs
+    are done.  Bound to the stream current at construction."""
+
+    def __init__(self, max_rows: int, max_k: int = 32, max_jobs: int = 64,
+                 opts: Options | None = None):
+        lib = load()
+        self.opts = opts if opts is not None else options()
+        self.ws_bytes = batch_workspace_bytes(max_rows, max_k, max_jobs)
+        if self.ws_bytes == 0:
+            raise ValueError("bad batch sizes")
+        self.ws = _workspace(self.ws_bytes)
+        self._h = ctypes.c_void_p()
+        self._stream = _stream()
+        _check(lib.nanogs_batch_create(max_rows, max_k, max_jobs, ctypes.byref(self.opts),
+                                       _ptr(self.ws), self.ws_bytes, self._stream,
+                                       ctypes.byref(self._h)))
+        self._keep = {}  # job id -> tensors that must stay alive
+        self.max_rows = max_rows
+
+    def close(self):
+        if self._h:
+            load().nanogs_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
+
+    def submit(self, g: GaussianTensors, target_n: int, k: int = 16, seed: int = 0,
+               out: GaussianTensors | None = None, origin=None) -> int:
+        out = out if out is not None else GaussianTensors.empty(g.n)
+        gs, os_ = g.struct(), out.struct()
+        jid = ctypes.c_int32(-1)
+        _check(load().nanogs_batch_submit(self._h, ctypes.byref(gs), g.n, target_n, k,
+                                          ctypes.c_uint64(seed & ((1 << 64) - 1)),
+                                          ctypes.byref(os_), _ptr(origin), ctypes.byref(jid)))
+        self._keep[jid.value] = (g, out, origin)
+        return jid.value
+
+    def step(self) -> int:
+        d = ctypes.c_int32(0)
+        _check(load().nanogs_batch_step(self._h, ctypes.byref(d)))
+        return d.value
+
+    def run(self):
+        _check(load().nanogs_batch_run(self._h))
+
+    def job(self, jid: int):
+        """(state, n_out, stats dict); state 0 queued, 1 running, 2 done,
+        negative: failed with that status."""
+        st = ctypes.c_int32(0)
+        n = ctypes.c_int64(0)
+        stats = Stats()
+        _check(load().nanogs_batch_job(self._h, jid, ctypes.byref(st), ctypes.byref(n),
+                                       ctypes.byref(stats)))
+        return st.value, int(n.value), stats.as_dict()
+
+    def result(self, jid: int) -> GaussianTensors:
+        state, n, _ = self.job(jid)
+        if state != JOB_DONE:
+            raise NanoGSError(-state if state < 0 else 5, f"job {jid} is not done")
+        return self._keep[jid][1].slice(n)
+
+    def release(self, jid: int):
+        """Drops the binding's references to a finished job's tensors."""
+        self._keep.pop(jid, None)
+
+    def rows_in_use(self) -> int:
+        return int(load().nanogs_batch_rows_in_use(self._h))
+

@@ -1,0 +1,119 @@
+"""Batched form: several scenes in one working set must give, job by job,
+the same bytes as simplifying each scene alone (each job's draws are keyed by
+its own seed and pass), whether the jobs start together or join while others
+are running.  Failure handling: a job that cannot be admitted or carries a
+non-finite value fails alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2603_16103_amd.synth import gen_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SPECS = [  # (n, scene seed, planes, spheres, ratio, k, draw seed)
+    (3000, 11, 8, 4, 0.5, 16, 101),
+    (5200, 12, 4, 0, 0.1, 24, 102),
+    (1200, 13, 2, 2, 0.2, 8, 103),
+    (800, 14, 1, 1, 0.5, 16, 104),
+]
+
+
+def _scene(spec):
+    n, sd, pl, sp, ratio, k, seed = spec
+    return gen_scene(n, sd, n_planes=pl, n_spheres=sp), max(int(np.ceil(ratio * n)), 1), k, seed
+
+
+def _alone(ng, sc, target, k, seed):
+    import torch
+    g = ng.GaussianTensors.from_scene(sc)
+    origin = torch.full((sc.n,), -1, dtype=torch.int32, device="cuda")
+    res = ng.simplify(g, target, k=k, opts=ng.options(seed=seed, d_origin=origin))
+    return [x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)], \
+        origin[:res.n].cpu().numpy()
+
+
+def _same(got, ref):
+    for a, b in zip(got, ref):
+        assert a.shape == b.shape
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_batch_equals_alone(gpu_lib):
+    import torch
+    ng = gpu_lib
+    scenes = [_scene(s) for s in SPECS]
+    b = ng.Batch(max_rows=sum(sc.n for sc, *_ in scenes), max_k=24, max_jobs=8)
+    jobs = []
+    for sc, target, k, seed in scenes:
+        origin = torch.full((sc.n,), -1, dtype=torch.int32, device="cuda")
+        jid = b.submit(ng.GaussianTensors.from_scene(sc), target, k=k, seed=seed, origin=origin)
+        jobs.append((jid, origin))
+    log("batch run", len(jobs), "jobs")
+    b.run()
+    for (jid, origin), (sc, target, k, seed) in zip(jobs, scenes):
+        state, n_out, _ = b.job(jid)
+        assert state == ng.JOB_DONE
+        res = b.result(jid)
+        ref, ref_org = _alone(ng, sc, target, k, seed)
+        log("job", jid, sc.n, "->", n_out)
+        assert n_out == ref[0].shape[0]
+        _same([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)],
+              ref)
+        assert np.array_equal(origin[:n_out].cpu().numpy(), ref_org)
+    b.close()
+
+
+def test_batch_jobs_join_and_leave(gpu_lib):
+    ng = gpu_lib
+    scenes = [_scene(s) for s in SPECS]
+    # room for about two scenes at a time: later jobs wait for rows, and one
+    # job is submitted while the others are mid-way
+    b = ng.Batch(max_rows=8500, max_k=24, max_jobs=3)
+    jobs = [(b.submit(ng.GaussianTensors.from_scene(sc), t, k=k, seed=sd), i)
+            for i, (sc, t, k, sd) in enumerate(scenes[:3])]
+    b.step()
+    b.step()
+    states = [b.job(j)[0] for j, _ in jobs]
+    log("states after two steps", states, "rows", b.rows_in_use())
+    assert ng.JOB_QUEUED in states or ng.JOB_DONE in states
+    sc, t, k, sd = scenes[3]
+    jobs.append((b.submit(ng.GaussianTensors.from_scene(sc), t, k=k, seed=sd), 3))
+    steps = 0
+    while any(b.job(j)[0] != ng.JOB_DONE for j, _ in jobs):
+        b.step()
+        steps += 1
+        assert steps < 200
+    for jid, i in jobs:
+        sc, t, k, sd = scenes[i]
+        res = b.result(jid)
+        ref, _ = _alone(ng, sc, t, k, sd)
+        _same([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)],
+              ref)
+    b.close()
+
+
+def test_batch_failures_are_isolated(gpu_lib):
+    ng = gpu_lib
+    good, t, k, sd = _scene(SPECS[2])
+    bad = good.copy()
+    bad.opacity[7] = np.nan
+    b = ng.Batch(max_rows=4000, max_k=16, max_jobs=4)
+    with pytest.raises(ng.NanoGSError):
+        b.submit(ng.GaussianTensors.from_scene(gen_scene(5000, 3)), 100, k=16)
+    j_bad = b.submit(ng.GaussianTensors.from_scene(bad), t, k=k, seed=sd)
+    j_good = b.submit(ng.GaussianTensors.from_scene(good), t, k=k, seed=sd)
+    b.run()
+    assert b.job(j_bad)[0] == -3  # ENONFINITE
+    assert b.job(j_good)[0] == ng.JOB_DONE
+    res = b.result(j_good)
+    ref, _ = _alone(ng, good, t, k, sd)
+    _same([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)], ref)
+    b.close()
