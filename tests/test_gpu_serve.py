@@ -1,0 +1,76 @@
+"""Continuous batching: requests replayed in real time through the batched
+server must each get the same bytes as the same request simplified alone,
+also when a small HBM budget makes later requests wait for admission and
+join while earlier ones are running; the plain one-at-a-time server gives
+the same results."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2603_16103_amd.synth import gen_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    from paper_2603_16103_amd import serve
+    rng = np.random.default_rng(9)
+    reqs = []
+    for rid in range(10):
+        n = int(rng.integers(2000, 30000))
+        sc = gen_scene(n, 500 + rid, n_planes=int(rng.integers(1, 6)),
+                       n_spheres=int(rng.integers(0, 3)))
+        ratio = float(rng.choice([0.5, 0.1, 0.01]))
+        k = int(rng.choice([16, 24]))
+        reqs.append(serve.Request(rid, 0.02 * rid, sc, max(int(np.ceil(ratio * n)), 1), k,
+                                  seed=77 + rid))
+    return reqs
+
+
+def _alone(ng, req):
+    res = ng.simplify(ng.GaussianTensors.from_scene(req.scene), req.target, k=req.k,
+                      opts=ng.options(seed=req.seed))
+    return [x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)]
+
+
+def _check_same(reqs, ng):
+    for r in reqs:
+        ref = _alone(ng, r)
+        assert r.result is not None, r.rid
+        assert r.n_out == ref[0].shape[0], (r.rid, r.n_out, ref[0].shape)
+        for a, b in zip(r.result, ref):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), r.rid
+
+
+@pytest.mark.parametrize("budget_mb", [4096, 80])
+def test_served_results_equal_alone(gpu_lib, budget_mb):
+    from paper_2603_16103_amd import serve
+    ng = gpu_lib
+    reqs = _requests()
+    hosts = [serve._HostScene(r.scene) for r in reqs]
+    srv = serve.BatchServer(budget_mb * 2**20, max_k=24, max_jobs=8, keep_results=True)
+    log("rows", srv.rows, "budget MB", budget_mb)
+    rep = srv.serve(reqs, hosts)
+    log(rep)
+    assert rep["requests"] == len(reqs) and rep["served"] == len(reqs)
+    assert rep["latency_p99_s"] is not None
+    if budget_mb == 80:
+        assert srv.rows < sum(r.n for r in reqs)  # admission had to wait
+    srv.batch.close()
+    _check_same(reqs, ng)
+
+
+def test_plain_server_matches(gpu_lib):
+    from paper_2603_16103_amd import serve
+    ng = gpu_lib
+    reqs = _requests()[:4]
+    hosts = [serve._HostScene(r.scene) for r in reqs]
+    rep = serve.PlainServer(max(r.n for r in reqs), keep_results=True).serve(reqs, hosts)
+    log(rep)
+    _check_same(reqs, ng)
