@@ -246,6 +246,33 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,
                            int64_t* d_nout, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 
+/* ---- launch shapes (autotuned) ------------------------------------------ */
+
+/* Launch parameters of the stage kernels.  Every choice gives bit-identical
+ * results (the arithmetic of each output does not depend on it); only the
+ * speed changes.  Values apply per size bucket of the pass's splat count N:
+ * bucket 0: N < 65536, 1: N < 524288, 2: larger. */
+typedef struct {
+  int32_t cost_block;     /* threads per workgroup, edge-cost kernel: 64, 128
+                             or 256 (256) */
+  int32_t knn_block;      /* threads per workgroup, one-lane-per-query kNN
+                             kernel: 64, 128 or 256 (64) */
+  int32_t knn_wave_grid;  /* workgroups striding over the sparse kNN queries
+                             (one wave each): 256..65536 (16384) */
+  int32_t knn_level_bias; /* finest cell-table level relative to the default
+                             (about log8 N): -2..1 (0) */
+  int32_t select_check;   /* matching iterations between host reads of the
+                             active count: 1..16 (4) */
+} nanogs_tuning;
+
+#define NANOGS_TUNE_BUCKETS 3
+
+/* Sets (or reads) the launch parameters of one bucket; bucket -1 sets all.
+ * Process-wide; not thread-safe with concurrent calls.  Errors: EINVAL for a
+ * bad bucket or value. */
+nanogs_status nanogs_set_tuning(int32_t bucket, const nanogs_tuning* t);
+nanogs_status nanogs_get_tuning(int32_t bucket, nanogs_tuning* t);
+
 /* ---- batched and served form: many scenes per pass ---------------------- */
 
 /* A batch keeps several simplification jobs (scenes) in one working set and

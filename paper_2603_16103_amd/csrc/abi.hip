@@ -622,4 +622,47 @@ nanogs_status nanogs_batch_job(const nanogs_batch* b, int32_t job_id, int32_t* s
 
 int64_t nanogs_batch_rows_in_use(const nanogs_batch* b) { return b ? b->eng->rows_in_use() : 0; }
 
+// ---- launch shapes ---------------------------------------------------------
+
+nanogs_status nanogs_set_tuning(int32_t bucket, const nanogs_tuning* t) {
+  if (!t || bucket < -1 || bucket >= NANOGS_TUNE_BUCKETS) {
+    set_error("bad bucket or null tuning");
+    return NANOGS_EINVAL;
+  }
+  const bool ok = (t->cost_block == 64 || t->cost_block == 128 || t->cost_block == 256) &&
+                  (t->knn_block == 64 || t->knn_block == 128 || t->knn_block == 256) &&
+                  t->knn_wave_grid >= 256 && t->knn_wave_grid <= 65536 &&
+                  t->knn_level_bias >= -2 && t->knn_level_bias <= 1 && t->select_check >= 1 &&
+                  t->select_check <= 16;
+  if (!ok) {
+    set_error("tuning value out of range");
+    return NANOGS_EINVAL;
+  }
+  Tuning v;
+  v.cost_block = t->cost_block;
+  v.knn_block = t->knn_block;
+  v.knn_wave_grid = t->knn_wave_grid;
+  v.knn_level_bias = t->knn_level_bias;
+  v.select_check = t->select_check;
+  for (int b = 0; b < NANOGS_TUNE_BUCKETS; ++b)
+    if (bucket < 0 || bucket == b) set_tuning(b, v);
+  return NANOGS_OK;
+}
+
+nanogs_status nanogs_get_tuning(int32_t bucket, nanogs_tuning* t) {
+  if (!t || bucket < 0 || bucket >= NANOGS_TUNE_BUCKETS) {
+    set_error("bad bucket or null tuning");
+    return NANOGS_EINVAL;
+  }
+  const long long rep = bucket == 0 ? 1 : bucket == 1 ? 65536 : 524288;
+  const Tuning& v = tuning_for(rep);
+  t->cost_block = v.cost_block;
+  t->knn_block = v.knn_block;
+  t->knn_wave_grid = v.knn_wave_grid;
+  t->knn_level_bias = v.knn_level_bias;
+  t->select_check = v.select_check;
+  return NANOGS_OK;
+}
+
 }  // extern "C"
+

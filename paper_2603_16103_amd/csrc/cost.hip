@@ -352,7 +352,8 @@ void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int
                       float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
                       AdjOut adj, hipStream_t st) {
   if (m <= 0) return;
-  k_edge_cost<<<blocks_for(m, 256), 256, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n,
+  const int bs = tuning_for(n).cost_block;
+  k_edge_cost<<<blocks_for(m, bs), bs, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n,
                                                   orient ? 1 : 0, crn.tab, crn.S, crn.sg, crn.seg,
                                                   fb_ratio, cost, dgeo, fb_list, fb_count, adj);
   NG_LAUNCH_CHECK();

@@ -49,9 +49,11 @@ Work take_work_e(Carver& c, long long n) {
 }
 
 long long table_bound(long long rows, int jobs) {
-  // per segment: 8^LT + 1 < 8 n + 1 (LT is the smallest level with 8^LT >= n,
-  // at least 1, so also <= 9 for tiny n)
-  return 8 * rows + 10ll * jobs + 16;
+  // per segment: 8^LT + 1 entries with LT at most one level above the
+  // smallest level with 8^L >= n (8^L < 8n), and LT <= 7
+  const long long by_rows = 64 * rows + 72ll * jobs;
+  const long long by_cap = (long long)jobs * ((1ll << 21) + 1);
+  return std::min(by_rows, by_cap) + 16ll * jobs + 16;
 }
 
 }  // namespace

@@ -124,6 +124,19 @@ struct SegInfo {
   int next;    // its position after this pass's compaction, -1: its rows are dropped
 };
 
+// Launch parameters per size bucket (see nanogs_tuning); util.hip.
+struct Tuning {
+  int cost_block = 256;
+  int knn_block = 64;
+  int knn_wave_grid = 16384;
+  int knn_level_bias = 0;
+  int select_check = 4;
+};
+constexpr int TUNE_BUCKETS = 3;
+int tune_bucket(long long n);
+const Tuning& tuning_for(long long n);
+void set_tuning(int bucket, const Tuning& t);
+
 // ---------------------------------------------------------------------------
 // host-side launchers (each defined in the .hip file named in the comment)
 // ---------------------------------------------------------------------------
@@ -183,6 +196,7 @@ void launch_deactivate_plain(const float* mu, const float* scale, const float* q
 void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsigned* keys,
                         void* temp, hipStream_t st);
 int table_level(long long n);
+int table_level_max(long long n);
 int kclass_of(int keff);
 unsigned class_bit(int kclass);
 long long table_entries(int LT);

@@ -255,7 +255,7 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
 // every row outside the block is then farther.  Cells are disjoint, so no row
 // is seen twice.
 template <int K>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_knn_grid(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
            const SegInfo* __restrict__ seg, const int* __restrict__ table,
            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
@@ -613,11 +613,20 @@ __global__ void k_gather_cen(const float* __restrict__ xyz3, const int* __restri
 
 }  // namespace
 
-// Finest table level of a segment of n rows: about 8^L >= n, at most 7.
+// Finest table level of a segment of n rows: about 8^L >= n (moved by the
+// tuned bias), between 1 and 7.
 int table_level(long long n) {
   int L = 1;
   while (L < 7 && (1ll << (3 * L)) < n) ++L;
-  return L;
+  L += tuning_for(n).knn_level_bias;
+  return L < 1 ? 1 : (L > 7 ? 7 : L);
+}
+
+// Upper bound of table_level(n) over every allowed bias (workspace sizing).
+int table_level_max(long long n) {
+  int L = 1;
+  while (L < 7 && (1ll << (3 * L)) < n) ++L;
+  return L + 1 > 7 ? 7 : L + 1;
 }
 
 int kclass_of(int keff) {
@@ -659,7 +668,8 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
 template <int K>
 void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
              const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
-  k_knn_grid<K><<<blocks_for(n, 64), 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
+  const int bs = tuning_for(n).knn_block;
+  k_knn_grid<K><<<blocks_for(n, bs), bs, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
                                                   rows_logical, nbr, m.sflag);
   NG_LAUNCH_CHECK();
 }
@@ -668,7 +678,8 @@ template <int K>
 void query_wave_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
                   const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
   // the sparse count stays on the device: a grid of fixed size strides over it
-  unsigned g = (unsigned)(n < 16384 ? n : 16384);
+  const int cap = tuning_for(n).knn_wave_grid;
+  unsigned g = (unsigned)(n < cap ? n : cap);
   if (g < 1) g = 1;
   k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr,
                                   m.sparse, m.counters + 1);
@@ -724,7 +735,7 @@ size_t knn_plain_bytes(long long n) {
   c.take<float4>(n);
   c.take<SegInfo>(1);
   size_t kb = 0;
-  carve_knn(nullptr, n, table_entries(table_level(n)), &kb);
+  carve_knn(nullptr, n, table_entries(table_level_max(n)), &kb);
   return c.bytes() + std::max(kb, sort_temp_bytes(n));
 }
 

@@ -375,7 +375,7 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   int it = 0;
   // Iterations run without a host round trip; the host reads the active
   // count every `batch` iterations (an empty iteration is two tiny launches).
-  const int batch = 4;
+  const int batch = tuning_for(n).select_check;
   while (true) {
     for (int b = 0; b < batch; ++b, ++it) {
       const int* in_list = it == 0 ? nullptr : act[(it + 1) & 1];

@@ -85,6 +85,14 @@ __global__ void k_set_i64(long long* d, long long v) {
 
 }  // namespace
 
+namespace {
+Tuning g_tuning[TUNE_BUCKETS];
+}
+
+int tune_bucket(long long n) { return n < 65536 ? 0 : n < 524288 ? 1 : 2; }
+const Tuning& tuning_for(long long n) { return g_tuning[tune_bucket(n)]; }
+void set_tuning(int bucket, const Tuning& t) { g_tuning[bucket] = t; }
+
 void set_i64(long long* d, long long v, hipStream_t st) {
   k_set_i64<<<1, 64, 0, st>>>(d, v);
   NG_LAUNCH_CHECK();

@@ -80,6 +80,19 @@ class Stats(ctypes.Structure):
                 "stage_launches": dict(zip(STAGES, self.stage_launches))}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("cost_block", ctypes.c_int32), ("knn_block", ctypes.c_int32),
+                ("knn_wave_grid", ctypes.c_int32), ("knn_level_bias", ctypes.c_int32),
+                ("select_check", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+TUNE_BUCKETS = 3
+TUNE_BUCKET_LIMITS = (65536, 524288, None)  # N below the limit -> bucket
+TUNING_FILE = os.path.join(HERE, "tuning_gfx950.json")
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -109,6 +122,8 @@ _SIGS = {
     "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
+    "nanogs_set_tuning": (ctypes.c_int, [_I32, ctypes.POINTER(Tuning)]),
+    "nanogs_get_tuning": (ctypes.c_int, [_I32, ctypes.POINTER(Tuning)]),
     "nanogs_batch_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
     "nanogs_batch_create": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(Options), _P, _SZ,
                                            _P, ctypes.POINTER(_P)]),
@@ -140,6 +155,7 @@ def load():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    apply_tuning_file(TUNING_FILE)
     return lib
 
 
@@ -508,4 +524,40 @@ class Batch:
 
     def rows_in_use(self) -> int:
         return int(load().nanogs_batch_rows_in_use(self._h))
+
+
+# ---------------------------------------------------------------------------
+# launch shapes
+# ---------------------------------------------------------------------------
+def get_tuning(bucket: int) -> dict:
+    t = Tuning()
+    _check(load().nanogs_get_tuning(bucket, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(bucket: int, **values):
+    """Sets launch parameters of one bucket (-1: all); unspecified fields keep
+    their current values.  Results do not depend on these values."""
+    lib = load()
+    cur = get_tuning(0 if bucket < 0 else bucket)
+    cur.update(values)
+    t = Tuning(**cur)
+    _check(lib.nanogs_set_tuning(bucket, ctypes.byref(t)))
+
+
+def apply_tuning_file(path: str) -> bool:
+    """Applies a tuning table written by paper_2603_16103_amd.tune (if the
+    file exists and was tuned for this architecture)."""
+    import json
+    try:
+        with open(path) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        return False
+    if tab.get("arch") != "gfx950":
+        return False
+    for b, vals in enumerate(tab.get("buckets", [])[:TUNE_BUCKETS]):
+        t = Tuning(**{f: int(vals[f]) for f, _ in Tuning._fields_})
+        _check(_lib.nanogs_set_tuning(b, ctypes.byref(t)))
+    return True
 
