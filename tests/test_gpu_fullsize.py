@@ -1,0 +1,191 @@
+"""Parity at the benchmarked size: 1,000,000 splats (seed 2), k = 16, in the
+launch configuration the benchmark uses (tuned launch shapes), checked on
+outputs the FP64 oracle can compute one by one and on properties that hold
+at any size:
+
+* kNN: 256 sampled rows equal the oracle's exact rows (key (d2, index));
+* union edges: the full set equals the oracle's union of the GPU lists;
+* edge costs: 20,000 sampled edges within 1e-4 |C| + 1e-5 of the oracle
+  (draws whose u sits within float rounding of pi may flip: counted);
+* selection: the pairs satisfy the characterisation of the greedy scan under
+  the strict order (cost, i, j) over all 9M edges: disjoint, and every edge
+  not taken has an end taken by an earlier edge;
+* merge: 20,000 sampled merged splats equal the oracle's MPMM;
+* whole loop: the final count is exactly the target and provenance is a
+  partition of the input.
+Also the precision-stress shape (flat and needle splats on 64 planes, k=24,
+to 1%) end to end against the oracle at 40,000 splats.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2603_16103_amd.synth import gen_scene, scene_plain_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda().contiguous()
+
+
+@pytest.fixture(scope="module")
+def big():
+    sc, k, target = scene_plain_gpu(1_000_000)
+    st = O.activate(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh)
+    f32 = np.float32
+    act = (st.mu.astype(f32), st.s.astype(f32), st.q.astype(f32), st.alpha.astype(f32),
+           st.f.astype(f32))
+    return sc, k, target, act
+
+
+def _state64(mu, s, q, al, f):
+    q = q.astype(np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    return O.State(mu.astype(np.float64), s.astype(np.float64), q, al.astype(np.float64),
+                   f.astype(np.float64), np.arange(mu.shape[0]))
+
+
+def test_fullsize_stages(gpu_lib, big):
+    ng = gpu_lib
+    sc, k, target, act = big
+    n = sc.n
+    rng = np.random.default_rng(123)
+    # kNN
+    log("knn 1M")
+    nbr = ng.knn(_t(act[0]), k)
+    nb = nbr.cpu().numpy()
+    rows = rng.choice(n, 256, replace=False)
+    ref_rows = O.knn(act[0], k, queries=rows)
+    np.testing.assert_array_equal(nb[rows], ref_rows)
+    # union edges
+    log("edges")
+    ei, ej = ng.edges(nbr)
+    a, b = ei.cpu().numpy(), ej.cpu().numpy()
+    ra, rb = O.union_edges(nb)
+    assert a.size == ra.size
+    key = a.astype(np.int64) * (n + 1) + b
+    np.testing.assert_array_equal(np.sort(key), ra.astype(np.int64) * (n + 1) + rb)
+    m = a.size
+    log("edges", m)
+    # costs on a sample
+    crn = O.crn_block(0, 0, 1)
+    splats = ng.SplatTensors(*(_t(x) for x in act))
+    cost = ng.edge_cost(splats, ei, ej, crn)
+    c = cost.cpu().numpy()
+    smp = rng.choice(m, 20000, replace=False)
+    st = _state64(*act)
+    ref = O.edge_costs(st, a[smp], b[smp], crn)[0]
+    err = np.abs(c[smp].astype(np.float64) - ref)
+    bad = err > 1e-4 * np.abs(ref) + 1e-5
+    wa = O.mass(st.s[a[smp]], st.alpha[a[smp]])
+    wb = O.mass(st.s[b[smp]], st.alpha[b[smp]])
+    near = np.abs(wa / (wa + wb) - float(crn[0, 0])) < 1e-6
+    assert not np.any(bad & ~near), (np.sum(bad & ~near), err[bad & ~near][:5])
+    log("cost flips", int(np.sum(bad)))
+    # selection: greedy characterisation over every edge
+    P = n - target
+    partner, npairs = ng.select(ei, ej, cost, n, P)
+    pt = partner.cpu().numpy()
+    ok = np.isfinite(c)
+    order = np.lexsort((b, a, np.where(ok, c, np.inf)))
+    rank = np.empty(m, np.int64)
+    rank[order] = np.arange(m)
+    rank[~ok] = np.iinfo(np.int64).max
+    taken = (pt[a] == b) & (pt[b] == a)
+    assert taken.sum() == npairs <= P
+    matched = pt >= 0
+    assert np.all(pt[pt[matched]] == np.nonzero(matched)[0])  # partner is an involution
+    big_rank = np.iinfo(np.int64).max
+    vrank = np.full(n, big_rank, np.int64)
+    vrank[a[taken]] = rank[taken]
+    vrank[b[taken]] = rank[taken]
+    free_edges = ok & ~taken
+    blocked = np.minimum(vrank[a], vrank[b]) < rank
+    assert np.all(blocked[free_edges]), int(np.sum(~blocked[free_edges]))
+    log("pairs", npairs)
+    # merge on a sample of pairs
+    origin = np.arange(n, dtype=np.int32)
+    out = ng.merge(ng.SplatTensors(*(_t(x) for x in act), _t(origin, None)), partner)
+    assert out.n == n - npairs
+    org = out.origin.cpu().numpy()
+    pairs = np.stack([a[taken], b[taken]], 1)
+    pairs = np.sort(pairs, 1)
+    sel = pairs[rng.choice(len(pairs), min(20000, len(pairs)), replace=False)]
+    pos_of = np.full(n, -1, np.int64)
+    pos_of[org] = np.arange(out.n)
+    rows_out = pos_of[sel[:, 0]]
+    assert np.all(rows_out >= 0)
+    i, j = sel[:, 0], sel[:, 1]
+    mu_r, Sr, al_r, f_r = O.mpmm(st.mu[i], st.s[i], st.q[i], st.alpha[i], st.f[i],
+                                 st.mu[j], st.s[j], st.q[j], st.alpha[j], st.f[j])
+    mu = out.mu.cpu().numpy()[rows_out].astype(np.float64)
+    s = out.scale.cpu().numpy()[rows_out].astype(np.float64)
+    q = out.quat.cpu().numpy()[rows_out].astype(np.float64)
+    al = out.alpha.cpu().numpy()[rows_out].astype(np.float64)
+    f = out.sh.cpu().numpy()[rows_out].astype(np.float64)
+    assert np.max(np.abs(mu - mu_r) / np.maximum(np.abs(mu_r).max(1, keepdims=True), 1)) < 1.01e-5
+    Sg = O.covariance(s, q)
+    fro = np.linalg.norm(Sg - Sr, axis=(1, 2)) / np.linalg.norm(Sr, axis=(1, 2))
+    assert fro.max() < 1e-5, fro.max()
+    assert np.max(np.abs(al - al_r)) < 1e-5
+    df = np.linalg.norm(f - f_r, axis=1) / np.maximum(np.linalg.norm(f_r, axis=1), 1e-3)
+    assert df.max() < 1e-5
+
+
+def test_fullsize_loop(gpu_lib, big):
+    import torch
+    ng = gpu_lib
+    sc, k, target, _ = big
+    origin = torch.full((sc.n,), -1, dtype=torch.int32, device="cuda")
+    res, stats = ng.simplify(ng.GaussianTensors.from_scene(sc), target, k=k,
+                             opts=ng.options(d_origin=origin), return_stats=True)
+    log("1M ->", res.n, stats["n_per_round"], stats["pairs_per_round"])
+    assert res.n == target
+    org = origin.cpu().numpy()[:res.n]
+    assert len(np.unique(org)) == res.n and org.min() >= 0 and org.max() < sc.n
+    assert stats["rounds"] >= math.ceil(math.log2(sc.n / target))
+    for nr, pr in zip(stats["n_per_round"], stats["pairs_per_round"]):
+        assert pr <= min(nr - target, nr // 2)
+
+
+def test_precision_stress_end_to_end(gpu_lib):
+    """Flat and needle splats (one or two log-scales ~ N(-7, 0.5)), 64 planes,
+    k = 24, to 1%: exact count, >= 99% of merged pairs identical to the
+    oracle's by provenance, FP64 fallback counted."""
+    import torch
+    ng = gpu_lib
+    n = 40_000
+    sc = gen_scene(n, 3, n_planes=64, n_spheres=0, stress=True)
+    target = max(int(math.ceil(0.01 * n)), 1)
+    trace = torch.full((n, 2), -1, dtype=torch.int32, device="cuda")
+    res, stats = ng.simplify(ng.GaussianTensors.from_scene(sc), target, k=24,
+                             opts=ng.options(d_trace=trace), return_stats=True)
+    log("stress", stats["n_per_round"], "fp64 edges", stats["fallback_per_round"])
+    ref_trace = []
+    ref = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, 24,
+                     trace=ref_trace)
+    assert res.n == ref.n == target
+    tr = trace.cpu().numpy()
+    off = same = total = 0
+    for r, cnt in enumerate(stats["pairs_per_round"][:stats["rounds"]]):
+        got = {tuple(x) for x in tr[off:off + cnt].tolist()}
+        off += cnt
+        exp = {tuple(x) for x in ref_trace[r].tolist()} if r < len(ref_trace) else set()
+        same += len(got & exp)
+        total += len(exp)
+    frac = same / max(total, 1)
+    log("identical pairs", frac)
+    assert frac >= 0.99
