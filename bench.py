@@ -178,7 +178,8 @@ def main():
                    "n": args.n, "target_n": target, "k": k, "S": 1,
                    "passes": last["rounds"], "n_per_pass": last["n_per_round"],
                    "edges_per_pass": last["edges_per_round"],
-                   "fp64_edges_per_pass": last["fallback_per_round"]},
+                   "fp64_edges_per_pass": last["fallback_per_round"],
+                   "knn_wave_retries_per_pass": last["knn_retry_per_round"]},
         "edge_costs_per_s": round(edges_total / (stage_ms["cost"] * 1e-3), 1)
         if stage_ms["cost"] > 0 else None,
         "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 4) for s in ng.STAGES},

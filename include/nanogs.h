@@ -116,6 +116,8 @@ typedef struct {
   int64_t pairs_per_round[NANOGS_MAX_ROUNDS];
   int64_t fallback_per_round[NANOGS_MAX_ROUNDS]; /* edges costed in FP64 */
   int32_t ld_iters_per_round[NANOGS_MAX_ROUNDS]; /* matching iterations */
+  int64_t knn_retry_per_round[NANOGS_MAX_ROUNDS]; /* kNN queries finished by
+                                                     the wave search */
   double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
   int32_t stage_launches[NANOGS_NTIMED];
 } nanogs_stats;
@@ -256,13 +258,20 @@ typedef struct {
   int32_t cost_block;     /* threads per workgroup, edge-cost kernel: 64, 128
                              or 256 (256) */
   int32_t knn_block;      /* threads per workgroup, one-lane-per-query kNN
-                             kernel: 64, 128 or 256 (64) */
-  int32_t knn_wave_grid;  /* workgroups striding over the sparse kNN queries
-                             (one wave each): 256..65536 (16384) */
+                             block search: 64, 128 or 256 (128) */
+  int32_t knn_wave_grid;  /* workgroups striding over the kNN queries that the
+                             wave search finishes (one wave each):
+                             256..65536 (16384) */
   int32_t knn_level_bias; /* finest cell-table level relative to the default
-                             (about log8 N): -2..1 (0) */
+                             (one above the smallest L with 8^L >= N, at most
+                             8): -2..1, positive values add nothing (0) */
   int32_t select_check;   /* matching iterations between host reads of the
                              active count: 1..16 (4) */
+  int32_t knn_block_min;  /* rows the 3x3x3 block of cells around a query
+                             must hold for the block search to use that
+                             cell level: 17..1024 (32) */
+  int32_t knn_lane_rows;  /* largest block a lane searches alone; larger
+                             ones go to the wave search: 64..4096 (256) */
 } nanogs_tuning;
 
 #define NANOGS_TUNE_BUCKETS 3

@@ -633,7 +633,8 @@ nanogs_status nanogs_set_tuning(int32_t bucket, const nanogs_tuning* t) {
                   (t->knn_block == 64 || t->knn_block == 128 || t->knn_block == 256) &&
                   t->knn_wave_grid >= 256 && t->knn_wave_grid <= 65536 &&
                   t->knn_level_bias >= -2 && t->knn_level_bias <= 1 && t->select_check >= 1 &&
-                  t->select_check <= 16;
+                  t->select_check <= 16 && t->knn_block_min >= 17 && t->knn_block_min <= 1024 &&
+                  t->knn_lane_rows >= 64 && t->knn_lane_rows <= 4096;
   if (!ok) {
     set_error("tuning value out of range");
     return NANOGS_EINVAL;
@@ -644,6 +645,8 @@ nanogs_status nanogs_set_tuning(int32_t bucket, const nanogs_tuning* t) {
   v.knn_wave_grid = t->knn_wave_grid;
   v.knn_level_bias = t->knn_level_bias;
   v.select_check = t->select_check;
+  v.knn_block_min = t->knn_block_min;
+  v.knn_lane_rows = t->knn_lane_rows;
   for (int b = 0; b < NANOGS_TUNE_BUCKETS; ++b)
     if (bucket < 0 || bucket == b) set_tuning(b, v);
   return NANOGS_OK;
@@ -661,6 +664,8 @@ nanogs_status nanogs_get_tuning(int32_t bucket, nanogs_tuning* t) {
   t->knn_wave_grid = v.knn_wave_grid;
   t->knn_level_bias = v.knn_level_bias;
   t->select_check = v.select_check;
+  t->knn_block_min = v.knn_block_min;
+  t->knn_lane_rows = v.knn_lane_rows;
   return NANOGS_OK;
 }
 

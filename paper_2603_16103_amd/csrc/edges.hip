@@ -62,24 +62,25 @@ k_edge_count(const unsigned char* __restrict__ flag, int n, int k, int* __restri
   cnt[p] = c;  // cnt[n] = 0, so the scan's entry n is the total
 }
 
+// thread per directed slot: an emitting slot writes its edge at eoff[p] +
+// (emitting slots before it in row p); its rank among the edges into its
+// target comes from an atomic counter per target (each slot's atomic is
+// independent of the others, so none waits for another's result)
 __global__ void __launch_bounds__(256)
 k_edge_emit(const int* __restrict__ nbr, int n, int k, const unsigned char* __restrict__ flag,
             const int* __restrict__ eoff, int* __restrict__ src, int* __restrict__ tgt,
             int* __restrict__ indeg, int* __restrict__ islot) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int* row = nbr + (long long)p * k;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (long long)n * k || !flag[s]) return;
+  const int p = (int)(s / k);
+  const int t = (int)(s - (long long)p * k);
   const unsigned char* f = flag + (long long)p * k;
   int o = eoff[p];
-  for (int t = 0; t < k; ++t) {
-    if (f[t]) {
-      const int j = row[t];
-      src[o] = p;
-      tgt[o] = j;
-      if (islot) islot[o] = atomicAdd(&indeg[j], 1);
-      ++o;
-    }
-  }
+  for (int u = 0; u < t; ++u) o += f[u];
+  const int j = nbr[s];
+  src[o] = p;
+  tgt[o] = j;
+  if (islot) islot[o] = atomicAdd(&indeg[j], 1);
 }
 
 __global__ void k_to_i64(const int* __restrict__ v, long long* __restrict__ out) {
@@ -140,7 +141,7 @@ void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es,
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(cnt, es.eoff, n + 1, tot, stemp, st);
   if (es.ioff) fill_i32(ideg, 0, n + 1, st);
-  k_edge_emit<<<blocks_for(n, 256), 256, 0, st>>>(nbr, n, k, flag, es.eoff, es.src, es.tgt,
+  k_edge_emit<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, n, k, flag, es.eoff, es.src, es.tgt,
                                                   ideg, es.ioff ? es.islot : nullptr);
   NG_LAUNCH_CHECK();
   if (es.ioff) {

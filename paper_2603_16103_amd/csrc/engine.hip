@@ -50,9 +50,9 @@ Work take_work_e(Carver& c, long long n) {
 
 long long table_bound(long long rows, int jobs) {
   // per segment: 8^LT + 1 entries with LT at most one level above the
-  // smallest level with 8^L >= n (8^L < 8n), and LT <= 7
+  // smallest level with 8^L >= n (8^L < 8n), and LT <= 8
   const long long by_rows = 64 * rows + 72ll * jobs;
-  const long long by_cap = (long long)jobs * ((1ll << 21) + 1);
+  const long long by_cap = (long long)jobs * ((1ll << 24) + 1);
   return std::min(by_rows, by_cap) + 16ll * jobs + 16;
 }
 
@@ -291,7 +291,7 @@ int Engine::step(StageTimer* T) {
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_TREE) : -1;
   fill_i32(W.counters + 2, 0, 1, st_);
-  knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, true, st_);
+  knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, st_);
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
   knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, st_);
@@ -302,8 +302,11 @@ int Engine::step(StageTimer* T) {
   if (T) T->stop(tk);
   NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(host + 2, carve_knn(W.temp, N, entries, nullptr).counters + 1,
+                        sizeof(int), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipStreamSynchronize(st_));
   const long long m = host[0];
+  const long long knn_retries = *(int*)(host + 2);
   if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
 
   const CrnTab ct{W.crn, o_.S, sg, W.seg};
@@ -350,6 +353,7 @@ int Engine::step(StageTimer* T) {
       j.stats.pairs_per_round[r] = hM[i];
       j.stats.fallback_per_round[r] = searching == 1 ? fb : 0;
       j.stats.ld_iters_per_round[r] = sel.iters;
+      j.stats.knn_retry_per_round[r] = searching == 1 ? knn_retries : 0;
     }
   }
 

@@ -127,10 +127,12 @@ struct SegInfo {
 // Launch parameters per size bucket (see nanogs_tuning); util.hip.
 struct Tuning {
   int cost_block = 256;
-  int knn_block = 64;
+  int knn_block = 128;
   int knn_wave_grid = 16384;
   int knn_level_bias = 0;
   int select_check = 4;
+  int knn_block_min = 32;
+  int knn_lane_rows = 256;
 };
 constexpr int TUNE_BUCKETS = 3;
 int tune_bucket(long long n);
@@ -205,19 +207,17 @@ long long table_entries(int LT);
 struct KnnMem {
   int* hist;
   int* table;
-  int* inv;
-  int* sflag;
-  int* spos;
-  int* sparse;
-  int* counters;  // [1]: sparse count
+  int* inv;      // logical index -> working row
+  int2* retry;   // (row, level) of the queries the wave search finishes
+  int* counters;  // [1]: retry count
   void* scan_temp;
 };
 KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes);
 // Cell tables of every segment with LT > 0 (rows sorted by Morton key within
-// each segment; *d_unsorted or-ed with 1 if not).  invert: also the logical
-// -> working inverse (rows carry their logical index in cen[].w).
+// each segment; *d_unsorted or-ed with 1 if not), and the logical -> working
+// inverse (rows carry their logical index in cen[].w).
 void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
-               void* mem, int* d_unsorted, bool invert, hipStream_t st);
+               void* mem, int* d_unsorted, hipStream_t st);
 // Exact kNN of every row of a segment with kclass > 0 among the rows of its
 // segment: nbr[p][t], t < keff of the segment, key (d2, logical); rows of
 // other segments get -1.  Entries are working rows (use_inv) or logical

@@ -141,13 +141,11 @@ __global__ void k_cell_runs(const float4* __restrict__ cen, int n, const int* __
   if (last || next_cell != cell) atomicAdd(&hist[S.toff + cell], i - S.row0 + 1);
 }
 
-// Rows of segments without a search (inert): empty lists.  Every row starts
-// as not sparse.
+// Rows of segments without a search (inert): empty lists.
 __global__ void k_knn_prefill(int n, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
-                              int k_out, int* __restrict__ nbr, int* __restrict__ sparse_flag) {
+                              int k_out, int* __restrict__ nbr) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  sparse_flag[p] = 0;
   if (seg[sg ? sg[p] : 0].kclass == 0)
     for (int t = 0; t < k_out; ++t) nbr[(long long)p * k_out + t] = -1;
 }
@@ -206,6 +204,15 @@ struct Best {
   NG_DEV void consider(double dc, int lc) {
     if (less(dc, lc, d[K - 1], l[K - 1])) insert(dc, lc);
   }
+  // the kk-th smallest distance (kk <= K): the entries are sorted, so it is
+  // the largest of the first kk (written as a reduction, which keeps the
+  // entries in registers; an indexed read would move them to memory)
+  NG_DEV double kth(int kk) const {
+    double v = d[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) v = q < kk ? fmax(v, d[q]) : v;
+    return v;
+  }
 };
 
 // Geometry of the quantisation grid shared with morton_key: a point v lies in
@@ -241,127 +248,277 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
   return (unsigned)t;
 }
 
-// Exact k-NN of one query over the cell table at the finest level LT, for
-// queries whose own cell holds at least K + 1 rows (so the own cell alone
-// fills the list and the k-th distance is at most the cell's diagonal: the
-// search never needs more than rings 1 and 2); the others are flagged in
-// sparse_flag for k_knn_wave.  Search:
-// the query's own cell, then rings R = 1, 2, ... of level-L cells (the cells
-// at Chebyshev distance R), skipping cells whose box (widened by the
-// quantisation margin) is beyond the current k-th key.  After ring R the
-// block of (2R+1)^3 cells around the query's cell has been searched; the
-// search stops once the k-th key is closer than the block's boundary (faces
-// on the grid's outer boundary do not count: no row lies beyond them), since
-// every row outside the block is then farther.  Cells are disjoint, so no row
-// is seen twice.
+// ---- block search, one lane per query ----------------------------------------
+// A query takes the finest level L whose 3x3x3 block of level-L cells around
+// its own cell holds at least `block_min` rows (or the segment's rows, if
+// fewer), and selects its k best within that block in three passes over the
+// block's rows, none of which inserts into a sorted list per candidate:
+//   A. a per-lane histogram of the float squared distances, 32 bins of a
+//      quarter octave each from (side/8)^2 to (2 side)^2 (side = cell side),
+//      giving tau = the upper edge of the bin holding the keff-th distance;
+//   B. the rows whose float distance is within tau (widened for rounding) go
+//      to a per-lane buffer (about keff of them);
+//   C. the buffered rows get the exact key (d2 in double, logical index) and
+//      a sorted insertion.
+// Cells whose box is beyond the current tau are skipped in A and B (their
+// rows fall in bins above tau, so neither tau nor the buffer changes).  The
+// own cell and the six faces come first, so tau is usually known early.
+// Every row outside the block is at least rho away (rho = distance to the
+// block's faces, faces on the grid's outer boundary open).  If the exact k-th
+// key is closer than rho the list is the exact kNN; otherwise the query goes
+// to the retry list with its level (the wave search continues with ring 2
+// from this list); a block over the scan cap or a buffer overflow retries
+// from scratch.
+
+// the 3x3x3 block: own cell, 6 faces, 12 edges, 8 corners; the offsets are
+// packed two bits per cell and axis (offset + 1), so a lane decodes cell c
+// without a memory access
+constexpr signed char kBlk[27][3] = {
+    {0, 0, 0},    {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},   {0, 1, 0},    {0, 0, -1},  {0, 0, 1},
+    {-1, -1, 0},  {-1, 1, 0},  {1, -1, 0},  {1, 1, 0},    {-1, 0, -1},  {-1, 0, 1},  {1, 0, -1},
+    {1, 0, 1},    {0, -1, -1}, {0, -1, 1},  {0, 1, -1},   {0, 1, 1},    {-1, -1, -1}, {-1, -1, 1},
+    {-1, 1, -1},  {-1, 1, 1},  {1, -1, -1}, {1, -1, 1},   {1, 1, -1},   {1, 1, 1}};
+constexpr unsigned long long pack_blk_axis(int a) {
+  unsigned long long v = 0;
+  for (int c = 0; c < 27; ++c) v |= (unsigned long long)(kBlk[c][a] + 1) << (2 * c);
+  return v;
+}
+constexpr unsigned long long kBlkX = pack_blk_axis(0), kBlkY = pack_blk_axis(1),
+                             kBlkZ = pack_blk_axis(2);
+NG_DEV int blk(unsigned long long packed, int c) { return (int)((packed >> (2 * c)) & 3ull) - 1; }
+
+constexpr int kExtCells = 80;   // cells of the k-th ball's range scanned by the lane itself
+// float screen: a point whose exact d2 is <= B has float d2 <= B * kScreen
+// (the float evaluation rounds at most five times, about 3e-7 relative)
+constexpr float kScreen = 1.000005f;
+constexpr float kPrune = 1.00001f;  // same, for the float box distance of a cell
+
+NG_DEV float d2_screen(float qx, float qy, float qz, float4 c) {
+  const float dx = qx - c.x, dy = qy - c.y, dz = qz - c.z;
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+// Result of one lane query: -1 done, 0 retry from scratch, L > 0 retry from
+// the block list at level L (already written to nbr).
 template <int K>
-__global__ void __launch_bounds__(256)
-k_knn_grid(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
-           const SegInfo* __restrict__ seg, const int* __restrict__ table,
-           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
-           int* __restrict__ sparse_flag) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const SegInfo& S = seg[sg ? sg[p] : 0];
-  if (S.kclass != K) return;  // another launch (or none: inert) serves it
+NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const SegInfo& S,
+                      const int* __restrict__ table, const int* __restrict__ inv, int rows_logical,
+                      int* __restrict__ nbr, int block_min, int lane_rows,
+                      unsigned* __restrict__ hist,
+                      int* __restrict__ buf, int bs) {
+  constexpr int CAP = 2 * K;
   const int keff = S.keff;
   const int LT = S.LT;
-  const unsigned* box = S.box;
   const int* cstart = table + S.toff;
   const int rb = S.row0 - cstart[0];  // table values -> rows
   const float4 cq = cen[p];
-  const double qx = cq.x, qy = cq.y, qz = cq.z;
   const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
-  const Grid g = grid_from_box(box);
   float lof[3], hif[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lof[a] = ord2f(box[a]);
-    hif[a] = ord2f(box[3 + a]);
+    lof[a] = ord2f(S.box[a]);
+    hif[a] = ord2f(S.box[3 + a]);
   }
   const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
   const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
   const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc), quant(qzf, lof[2], sc)};
 
-  // Queries whose own finest-level cell holds fewer than K + 1 rows (sparse
-  // surroundings) are flagged for k_knn_wave instead.
-  const int L = LT;
-  {
-    const unsigned mc = (spread10(qi[0] >> (10 - L)) << 2) | (spread10(qi[1] >> (10 - L)) << 1) |
-                        spread10(qi[2] >> (10 - L));
-    const int cnt = cstart[mc + 1] - cstart[mc];
-    const bool sparse = cnt < K + 1 && sc > 0.f;
-    sparse_flag[p] = sparse ? 1 : 0;
-    if (sparse) return;
-  }
-  const int s = 10 - L;
-  const int G = 1 << L;
-  const int sub = 3 * (LT - L);
-  const double side = (double)(1 << s) * g.inv_sc;
-  const int cx = (int)(qi[0] >> s), cy = (int)(qi[1] >> s), cz = (int)(qi[2] >> s);
-
-  Best<K> best;
-  best.init();
-  float thr = INFINITY;
-  auto scan = [&](int a, int b) {
-    for (int j = a; j < b; ++j) {
-      const float4 c = cen[j];
-      const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
-      if (dx * dx + dy * dy + dz * dz <= thr && j != p)
-        best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
+  // level: finest L whose block holds >= bmin rows (level 1's block is the
+  // whole segment); bmin > keff, so the block holds keff rows besides p.
+  // mask: the block's non-empty cells (bit c: cell c of the block order)
+  int bmin = block_min > keff + 1 ? block_min : keff + 1;
+  if (bmin > S.nrows) bmin = S.nrows;
+  int L = LT;
+  int rows = 0;
+  unsigned mask = 0u;
+  for (;; --L) {
+    const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
+    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+    rows = 0;
+    mask = 0u;
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+      const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
+      if (x < 0 || x >= G || y < 0 || y >= G || z < 0 || z >= G) continue;
+      const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                          spread10((unsigned)z)) << sub;
+      const int cnt = cstart[f + (1u << sub)] - cstart[f];
+      rows += cnt;
+      if (cnt > 0) mask |= 1u << c;
     }
-    thr = admit_bound(best.d[K - 1]);
+    if (rows >= bmin || L <= 1) break;
+  }
+  if (rows > lane_rows) return 0;
+
+  const int sl = 10 - L, sub = 3 * (LT - L);
+  const int G = 1 << L;
+  const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+  const float side = sc > 0.f ? (float)(1 << sl) / sc : 0.f;
+  const float marg = 1e-5f * ext;
+  int base = (int)(__float_as_uint(side * side) >> 21) - 24;
+  if (base < 0) base = 0;
+
+  // float distance from the query to the box of block cell c (widened by
+  // the quantisation margin)
+  auto box_d2 = [&](int c) {
+    const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
+    const float gx = fmaxf(fmaxf(lof[0] + x * side - marg - qxf, qxf - (lof[0] + (x + 1) * side + marg)), 0.f);
+    const float gy = fmaxf(fmaxf(lof[1] + y * side - marg - qyf, qyf - (lof[1] + (y + 1) * side + marg)), 0.f);
+    const float gz = fmaxf(fmaxf(lof[2] + z * side - marg - qzf, qzf - (lof[2] + (z + 1) * side + marg)), 0.f);
+    return fmaf(gz, gz, fmaf(gy, gy, gx * gx));
   };
-  auto cell_range = [&](int x, int y, int z, int& a, int& b) {
-    const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                        spread10((unsigned)z);
-    const unsigned f = mc << sub;
+  auto range = [&](int c, int& a, int& b) {
+    const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
+    const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                        spread10((unsigned)z)) << sub;
     a = cstart[f] + rb;
     b = cstart[f + (1u << sub)] + rb;
   };
-  {
-    int a, b;
-    cell_range(cx, cy, cz, a, b);
-    scan(a, b);
-  }
-  // a zero-extent grid has every row in one cell: the own cell was all
-  for (int R = 1; sc > 0.f; ++R) {
-    for (int dx = -R; dx <= R; ++dx) {
-      const int x = cx + dx;
-      if (x < 0 || x >= G) continue;
-      for (int dy = -R; dy <= R; ++dy) {
-        const int y = cy + dy;
-        if (y < 0 || y >= G) continue;
-        const bool edge_xy = dx == -R || dx == R || dy == -R || dy == R;
-        for (int dz = -R; dz <= R; dz += (edge_xy ? 1 : 2 * R)) {
-          const int z = cz + dz;
-          if (z < 0 || z >= G) continue;
-          // distance from the query to the cell's widened box, in double
-          const double bx0 = g.lo[0] + x * side - g.margin, bx1 = g.lo[0] + (x + 1) * side + g.margin;
-          const double by0 = g.lo[1] + y * side - g.margin, by1 = g.lo[1] + (y + 1) * side + g.margin;
-          const double bz0 = g.lo[2] + z * side - g.margin, bz1 = g.lo[2] + (z + 1) * side + g.margin;
-          const double gx = fmax(fmax(bx0 - qx, qx - bx1), 0.0);
-          const double gy = fmax(fmax(by0 - qy, qy - by1), 0.0);
-          const double gz = fmax(fmax(bz0 - qz, qz - bz1), 0.0);
-          const double bd = (gx * gx + gy * gy) + gz * gz;
-          if (bd > best.d[K - 1] * (1.0 + 1e-12)) continue;
-          int a, b;
-          cell_range(x, y, z, a, b);
-          if (b > a) scan(a, b);
-        }
-      }
+  // upper edge of the bin that holds the keff-th distance (+inf if unknown)
+  auto kth_edge = [&]() {
+    int cum = 0, bstar = -1;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const unsigned v = hist[w * bs];
+      cum += (int)(v & 0xffffu);
+      if (bstar < 0 && cum >= keff) bstar = 2 * w;
+      cum += (int)(v >> 16);
+      if (bstar < 0 && cum >= keff) bstar = 2 * w + 1;
     }
-    // distance from the query to the boundary of the searched block (shrunk
-    // by the margin); faces on the grid boundary are open
-    double rho = INFINITY;
-    if (cx - R > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - R) * side + g.margin));
-    if (cx + R + 1 < G) rho = fmin(rho, (g.lo[0] + (cx + R + 1) * side - g.margin) - qx);
-    if (cy - R > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - R) * side + g.margin));
-    if (cy + R + 1 < G) rho = fmin(rho, (g.lo[1] + (cy + R + 1) * side - g.margin) - qy);
-    if (cz - R > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - R) * side + g.margin));
-    if (cz + R + 1 < G) rho = fmin(rho, (g.lo[2] + (cz + R + 1) * side - g.margin) - qz);
-    if (!(rho < INFINITY)) break;  // the block covers the whole grid
-    if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.d[K - 1]) break;
+    if (bstar < 0 || bstar == 31 || base + bstar + 1 >= 1020) return INFINITY;
+    return __uint_as_float((unsigned)(base + bstar + 1) << 21);
+  };
+  // visits the non-empty cells in block order, the range of the next cell
+  // loaded before the current one is scanned; f(c, a, b) scans one cell
+  auto for_cells = [&](auto&& f) {
+    unsigned rem = mask;
+    int c = rem ? __ffs(rem) - 1 : -1;
+    int a = 0, b = 0;
+    if (c >= 0) range(c, a, b);
+    while (c >= 0) {
+      rem &= rem - 1u;
+      const int cn = rem ? __ffs(rem) - 1 : -1;
+      int an = 0, bn = 0;
+      if (cn >= 0) range(cn, an, bn);
+      f(c, a, b, cn);
+      c = cn;
+      a = an;
+      b = bn;
+    }
+  };
+
+  // pass A (p itself is counted in bin 0 with the own cell, then removed)
+#pragma unroll
+  for (int w = 0; w < 16; ++w) hist[w * bs] = 0u;
+  auto count = [&](const float4& cj) {
+    const float d2 = d2_screen(qxf, qyf, qzf, cj);
+    int bin = (int)(__float_as_uint(d2) >> 21) - base;
+    bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
+    atomicAdd(&hist[(bin >> 1) * bs], 1u << ((bin & 1) << 4));
+  };
+  float tau = INFINITY;
+  for_cells([&](int c, int a, int b, int cn) {
+    if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * kPrune)) {
+      int j = a;
+      for (; j + 4 <= b; j += 4) {
+        const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
+        count(c0);
+        count(c1);
+        count(c2);
+        count(c3);
+      }
+      for (; j < b; ++j) count(cen[j]);
+    }
+    if (c == 0) hist[0] -= 1u;  // p, at distance 0
+    // refresh the bound after the own cell and after the faces
+    if (c == 0 || (c <= 6 && (cn < 0 || cn > 6))) tau = kth_edge();
+  });
+  tau = kth_edge();
+
+  // pass B: rows within tau into the buffer (slot CAP takes the overflow);
+  // p itself (distance 0, own cell) is buffered too and skipped in pass C
+  const float adm = tau * kScreen;
+  int nb = 0;
+  auto keep = [&](const float4& cj, int j) {
+    const bool in = d2_screen(qxf, qyf, qzf, cj) <= adm;
+    buf[(nb < CAP ? nb : CAP) * bs] = j;
+    nb += in ? 1 : 0;
+  };
+  for_cells([&](int c, int a, int b, int) {
+    if (c > 0 && box_d2(c) > tau * kPrune) return;
+    int j = a;
+    for (; j + 4 <= b; j += 4) {
+      const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
+      keep(c0, j);
+      keep(c1, j + 1);
+      keep(c2, j + 2);
+      keep(c3, j + 3);
+    }
+    for (; j < b; ++j) keep(cen[j], j);
+  });
+  if (nb > CAP || nb < keff + 1) return 0;  // (nb >= keff + 1 by construction)
+
+  // pass C: exact keys of the buffered rows.  Then every row within the
+  // k-th distance lies in a level-L cell whose box (widened by the margin)
+  // meets the ball; if all such cells belong to the block the list is exact.
+  // Otherwise the rows of the few cells outside the block that pass the
+  // screen are buffered and given exact keys in a second round (the ball
+  // only shrinks meanwhile), unless the ball spans more than kExtCells cells
+  // (the wave search then goes on from ring 2) or they overflow the buffer.
+  const double qx = qxf, qy = qyf, qz = qzf;
+  Best<K> best;
+  best.init();
+  int res = -1;
+  for (int round = 0;; ++round) {
+    for (int i = 0; i < nb; ++i) {
+      const int j = buf[i * bs];
+      const float4 c = cen[j];
+      if (j != p) best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
+    }
+    if (round > 0 || !(sc > 0.f)) break;  // (a zero-extent grid: one cell holds every row)
+    const Grid g = grid_from_box(S.box);
+    const double sd = (double)(1 << sl) * g.inv_sc;
+    const double kd = best.kth(keff);
+    const double r = sqrt(kd) + 2.0 * g.margin;
+    const double q3[3] = {qx, qy, qz};
+    const int c3[3] = {cx, cy, cz};
+    int lo3[3], hi3[3];
+    bool inside = true;
+    int vol = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double f0 = floor((q3[a] - r - g.lo[a]) / sd);
+      const double f1 = floor((q3[a] + r - g.lo[a]) / sd);
+      lo3[a] = f0 < 0.0 ? 0 : (f0 > G - 1 ? G - 1 : (int)f0);
+      hi3[a] = f1 < 0.0 ? 0 : (f1 > G - 1 ? G - 1 : (int)f1);
+      inside = inside && lo3[a] >= c3[a] - 1 && hi3[a] <= c3[a] + 1;
+      vol *= hi3[a] - lo3[a] + 1;
+    }
+    if (inside) break;
+    if (vol > kExtCells) {
+      res = L;
+      break;
+    }
+    const float thr = admit_bound(kd);
+    nb = 0;
+    for (int z = lo3[2]; z <= hi3[2]; ++z)
+      for (int y = lo3[1]; y <= hi3[1]; ++y)
+        for (int x = lo3[0]; x <= hi3[0]; ++x) {
+          if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
+          const double gx = fmax(fmax(g.lo[0] + x * sd - g.margin - qx, qx - (g.lo[0] + (x + 1) * sd + g.margin)), 0.0);
+          const double gy = fmax(fmax(g.lo[1] + y * sd - g.margin - qy, qy - (g.lo[1] + (y + 1) * sd + g.margin)), 0.0);
+          const double gz = fmax(fmax(g.lo[2] + z * sd - g.margin - qz, qz - (g.lo[2] + (z + 1) * sd + g.margin)), 0.0);
+          if ((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12)) continue;
+          const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                              spread10((unsigned)z)) << sub;
+          const int a = cstart[f] + rb, b = cstart[f + (1u << sub)] + rb;
+          for (int j = a; j < b; ++j) {
+            const bool in = d2_screen(qxf, qyf, qzf, cen[j]) <= thr;
+            buf[(nb < CAP ? nb : CAP) * bs] = j;
+            nb += in ? 1 : 0;
+          }
+        }
+    if (nb > CAP) return 0;
   }
 
   const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
@@ -375,16 +532,52 @@ k_knn_grid(const float4* __restrict__ cen, int n, int k_out, const int* __restri
     }
   }
   for (int t = K; t < k_out; ++t) out[t] = -1;
+  return res;
 }
 
-// ---- sparse queries ------------------------------------------------------------
-// Exact k-NN of the sparse queries, one wave per query.  Level: the finest
-// L < LT whose cell around the query holds at least K + 1 rows (or level 1),
-// so rings 1 and 2 suffice as in k_knn_grid.  The lanes share the work: the
-// cells of a ring are tested one per lane (box against the current k-th
-// distance), the rows of the cells that pass are dealt out 64 at a time, and
-// the k best live one entry per lane (lanes 0..K-1, sorted), so an insertion
-// is a ballot and a shift.  The own cell is scanned first.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_knn_lane(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
+           const SegInfo* __restrict__ seg, const int* __restrict__ table,
+           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr, int block_min,
+           int lane_rows, int2* __restrict__ retry, int* __restrict__ n_retry) {
+  extern __shared__ unsigned s_lane[];  // [16][bs] histogram words, then [2K + 1][bs] buffer
+  const int bs = blockDim.x, tid = threadIdx.x;
+  const int p = blockIdx.x * bs + tid;
+  int res = -1;
+  if (p < n) {
+    const SegInfo& S = seg[sg ? sg[p] : 0];
+    if (S.kclass == K)
+      res = lane_query<K>(cen, p, k_out, S, table, inv, rows_logical, nbr, block_min, lane_rows,
+                          s_lane + tid, (int*)(s_lane + 16 * bs) + tid, bs);
+  }
+  // retries, appended with one atomic per wave
+  const bool need = res >= 0;
+  const unsigned long long m = __ballot(need);
+  if (m) {
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int at = 0;
+    if (lane == leader) at = atomicAdd(n_retry, __popcll(m));
+    at = __shfl(at, leader, 64);
+    if (need) {
+      const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+      retry[at + __popcll(below)] = make_int2(p, res);
+    }
+  }
+}
+
+// ---- retries: one wave per query ---------------------------------------------
+// Queries whose block search could not prove its list exact, one wave each.
+// An entry (p, L > 0) holds the exact k best of the 3x3x3 block at level L
+// (written to nbr): the search goes on with rings R = 2, 3, ... of level-L
+// cells.  An entry (p, 0) starts from scratch at the finest level whose own
+// cell holds at least K + 1 rows (or level 1), with the own cell, then rings
+// R = 1, 2, ...  The lanes share the work: the cells of a ring are tested one
+// per lane (box against the current k-th distance), the rows of the cells
+// that pass are dealt out 64 at a time, and the k best live one entry per
+// lane (lanes 0..K-1, sorted), so an insertion is a ballot and a shift.  The
+// search stops once the k-th key is closer than the searched block's faces.
 template <int K>
 struct WaveBest {
   double d;  // entry of this lane (lanes >= K hold +inf)
@@ -394,9 +587,10 @@ struct WaveBest {
     d = INFINITY;
     l = INT_MAX;
   }
-  NG_DEV double kth() const {
-    const int lo = __shfl(__double2loint(d), K - 1, 64);
-    const int hi = __shfl(__double2hiint(d), K - 1, 64);
+  // entry kk - 1 (kk = the segment's k_eff, wave-uniform)
+  NG_DEV double kth(int kk) const {
+    const int lo = __shfl(__double2loint(d), kk - 1, 64);
+    const int hi = __shfl(__double2hiint(d), kk - 1, 64);
     return __hiloint2double(hi, lo);
   }
   // insert (dc, lc) (wave-uniform); no-op if it does not beat entry K-1
@@ -426,14 +620,19 @@ template <int K>
 __global__ void __launch_bounds__(64)
 k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
            const SegInfo* __restrict__ seg, const int* __restrict__ table,
-           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
-           const int* __restrict__ list, const int* __restrict__ d_count) {
+           const int* __restrict__ inv, const int* __restrict__ l2p, int rows_logical,
+           int block_min, int* __restrict__ nbr, const int2* __restrict__ list,
+           const int* __restrict__ d_count) {
+  constexpr int CAPW = 256;  // rows the block search may buffer for exact keys
   __shared__ int s_start[128];
   __shared__ int s_pref[129];
+  __shared__ int s_hist[32];
+  __shared__ int s_buf[CAPW];
   const int lane = threadIdx.x;
   const int count = *d_count;
   for (int qidx = blockIdx.x; qidx < count; qidx += gridDim.x) {
-    const int p = list[qidx];
+    const int2 ent = list[qidx];
+    const int p = ent.x;
     const SegInfo& S = seg[sg ? sg[p] : 0];
     if (S.kclass != K) continue;  // wave-uniform: one query per wave
     const int keff = S.keff;
@@ -455,32 +654,18 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
     const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
     const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc),
                             quant(qzf, lof[2], sc)};
-    int L = LT - 1 >= 1 ? LT - 1 : 1;
-    while (L > 1) {
-      const int sl = 10 - L;
-      const unsigned mc = (spread10(qi[0] >> sl) << 2) | (spread10(qi[1] >> sl) << 1) |
-                          spread10(qi[2] >> sl);
-      const unsigned f = mc << (3 * (LT - L));
-      if (cstart[f + (1u << (3 * (LT - L)))] - cstart[f] >= K + 1) break;
-      --L;
-    }
-    const int sl = 10 - L;
-    const int G = 1 << L;
-    const int sub = 3 * (LT - L);
-    const double side = (double)(1 << sl) * g.inv_sc;
-    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+    const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
+    int* out = nbr + row * k_out;
     WaveBest<K> best;
     best.init();
 
-    // scans the rows of the cells listed in s_start / s_pref (ncell cells)
-    auto scan_cells = [&](int ncell) {
+    // rows of the cells listed in s_start / s_pref (ncell cells), 64 per
+    // step: f(j) for lane's row j (j = -1: no row)
+    auto for_rows = [&](int ncell, auto&& f) {
       const int total = s_pref[ncell];
       for (int t0 = 0; t0 < total; t0 += 64) {
         const int t = t0 + lane;
-        bool pass = false;
         int j = -1;
-        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-        const float thr = admit_bound(best.kth());
         if (t < total) {
           int lo = 0, hi = ncell - 1;  // last cell with s_pref <= t
           while (lo < hi) {
@@ -488,44 +673,194 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
             if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
           }
           j = s_start[lo] + (t - s_pref[lo]);
-          c = cen[j];
-          const float dx = qxf - c.x, dy = qyf - c.y, dz = qzf - c.z;
-          pass = dx * dx + dy * dy + dz * dz <= thr && j != p;
         }
-        unsigned long long m = __ballot(pass);
-        const double dme = pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0;
-        const int lme = __float_as_int(c.w);
-        while (m) {
-          const int src = __ffsll((long long)m) - 1;
-          m &= m - 1;
-          const int dlo = __shfl(__double2loint(dme), src, 64);
-          const int dhi = __shfl(__double2hiint(dme), src, 64);
-          const int ls = __shfl(lme, src, 64);
-          best.insert(__hiloint2double(dhi, dlo), ls);
-        }
+        f(j);
       }
     };
-    // own cell
-    {
-      const unsigned mc = (spread10((unsigned)cx) << 2) | (spread10((unsigned)cy) << 1) |
-                          spread10((unsigned)cz);
-      const unsigned f = mc << sub;
-      if (lane == 0) {
-        s_start[0] = cstart[f] + rb;
-        s_pref[0] = 0;
-        s_pref[1] = cstart[f + (1u << sub)] - cstart[f];
+    // lanes holding a candidate (pass) insert it, one after another
+    auto insert_passing = [&](bool pass, double dme, int lme) {
+      unsigned long long m = __ballot(pass);
+      while (m) {
+        const int src = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int dlo = __shfl(__double2loint(dme), src, 64);
+        const int dhi = __shfl(__double2hiint(dme), src, 64);
+        const int ls = __shfl(lme, src, 64);
+        best.insert(__hiloint2double(dhi, dlo), ls);
       }
+    };
+    // the non-empty cells (lane's range [a, b)) into s_start / s_pref;
+    // returns their number
+    auto list_cells = [&](int a, int b) {
+      const bool has = b > a;
+      const unsigned long long hm = __ballot(has);
+      const int rank = __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+      const int cnt = has ? b - a : 0;
+      int incl = cnt;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+      }
+      if (has) {
+        s_start[rank] = a;
+        s_pref[rank] = incl - cnt;
+      }
+      const int ncell = __popcll(hm);
+      if (lane == 63) s_pref[ncell] = incl;
       __syncthreads();
-      scan_cells(1);
+      return ncell;
+    };
+
+    int L = ent.y;
+    int R0 = 2;
+    if (L > 0) {
+      // the exact k best of the 3x3x3 block, as written by the block search
+      if (lane < keff) {
+        const int e = out[lane];
+        const float4 c = cen[inv ? e : l2p[e]];
+        best.d = dist2(qx, qy, qz, c.x, c.y, c.z);
+        best.l = __float_as_int(c.w);
+      }
+    } else {
+      // block search as in the lane kernel, the lanes sharing the rows: the
+      // finest level whose 3x3x3 block holds bmin rows, a histogram of the
+      // float distances for tau, the rows within tau buffered, exact keys
+      int bmin = block_min > keff + 1 ? block_min : keff + 1;
+      if (bmin > S.nrows) bmin = S.nrows;
+      int a = 0, b = 0;
+      for (L = LT;; --L) {
+        const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
+        const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+        a = b = 0;
+        if (lane < 27) {
+          const int x = cx + blk(kBlkX, lane), y = cy + blk(kBlkY, lane), z = cz + blk(kBlkZ, lane);
+          if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
+            const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                                spread10((unsigned)z)) << sub;
+            a = cstart[f] + rb;
+            b = cstart[f + (1u << sub)] + rb;
+          }
+        }
+        int rows = b - a;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) rows += __shfl_xor(rows, d, 64);
+        if (rows >= bmin || L <= 1) break;
+      }
+      const int ncell = list_cells(a, b);
+      const int sl = 10 - L;
+      const float side = sc > 0.f ? (float)(1 << sl) / sc : 0.f;
+      int base = (int)(__float_as_uint(side * side) >> 21) - 24;
+      if (base < 0) base = 0;
+      // pass A
+      if (lane < 32) s_hist[lane] = 0;
       __syncthreads();
+      for_rows(ncell, [&](int j) {
+        if (j >= 0 && j != p) {
+          const float d2 = d2_screen(qxf, qyf, qzf, cen[j]);
+          int bin = (int)(__float_as_uint(d2) >> 21) - base;
+          bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
+          atomicAdd(&s_hist[bin], 1);
+        }
+      });
+      __syncthreads();
+      int cum = lane < 32 ? s_hist[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        const int y = __shfl_up(cum, d, 64);
+        if (lane >= d) cum += y;
+      }
+      const unsigned long long reach = __ballot(lane < 32 && cum >= keff);
+      const int bstar = reach ? __ffsll((long long)reach) - 1 : -1;
+      float tau = INFINITY;
+      if (bstar >= 0 && bstar < 31 && base + bstar + 1 < 1020)
+        tau = __uint_as_float((unsigned)(base + bstar + 1) << 21);
+      // pass B
+      const float adm = tau * kScreen;
+      int nb = 0;
+      for_rows(ncell, [&](int j) {
+        bool keep = false;
+        if (j >= 0 && j != p) keep = d2_screen(qxf, qyf, qzf, cen[j]) <= adm;
+        const unsigned long long m = __ballot(keep);
+        const int rank = __popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+        if (keep && nb + rank < CAPW) s_buf[nb + rank] = j;
+        nb += __popcll(m);
+      });
+      __syncthreads();
+      if (nb <= CAPW) {
+        // pass C
+        for (int i0 = 0; i0 < nb; i0 += 64) {
+          const int i = i0 + lane;
+          bool pass = false;
+          double dme = 0.0;
+          int lme = 0;
+          if (i < nb) {
+            const float4 c = cen[s_buf[i]];
+            dme = dist2(qx, qy, qz, c.x, c.y, c.z);
+            lme = __float_as_int(c.w);
+            pass = true;
+          }
+          insert_passing(pass, dme, lme);
+        }
+        // the block holds the exact list if the k-th key is closer than
+        // its faces
+        const int G = 1 << L;
+        const double sd = (double)(1 << sl) * g.inv_sc;
+        const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+        double rho = INFINITY;
+        if (cx - 1 > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - 1) * sd + g.margin));
+        if (cx + 2 < G) rho = fmin(rho, (g.lo[0] + (cx + 2) * sd - g.margin) - qx);
+        if (cy - 1 > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - 1) * sd + g.margin));
+        if (cy + 2 < G) rho = fmin(rho, (g.lo[1] + (cy + 2) * sd - g.margin) - qy);
+        if (cz - 1 > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - 1) * sd + g.margin));
+        if (cz + 2 < G) rho = fmin(rho, (g.lo[2] + (cz + 2) * sd - g.margin) - qz);
+        const double kd = best.kth(keff);
+        if (!(sc > 0.f) || !(rho < INFINITY) || (rho > 0.0 && rho * rho * (1.0 - 1e-9) > kd))
+          R0 = -1;  // done
+      } else {
+        // too many rows within tau (crowded or tied distances): the k best
+        // by insertion from the finest level whose own cell holds K + 1 rows
+        best.init();
+        for (L = LT; L > 1; --L) {
+          const int sl2 = 10 - L;
+          const unsigned mc = (spread10(qi[0] >> sl2) << 2) | (spread10(qi[1] >> sl2) << 1) |
+                              spread10(qi[2] >> sl2);
+          const unsigned f = mc << (3 * (LT - L));
+          if (cstart[f + (1u << (3 * (LT - L)))] - cstart[f] >= K + 1) break;
+        }
+        const int sl2 = 10 - L, sub2 = 3 * (LT - L);
+        const unsigned mc = (spread10(qi[0] >> sl2) << 2) | (spread10(qi[1] >> sl2) << 1) |
+                            spread10(qi[2] >> sl2);
+        const unsigned f = mc << sub2;
+        const int ncell1 = list_cells(lane == 0 ? cstart[f] + rb : 0,
+                                      lane == 0 ? cstart[f + (1u << sub2)] + rb : 0);
+        for_rows(ncell1, [&](int j) {
+          bool pass = false;
+          float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+          const float thr = admit_bound(best.kth(keff));
+          if (j >= 0) {
+            c = cen[j];
+            pass = d2_screen(qxf, qyf, qzf, c) <= thr && j != p;
+          }
+          insert_passing(pass, pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0, __float_as_int(c.w));
+        });
+        __syncthreads();
+        R0 = 1;
+      }
     }
-    for (int R = 1; sc > 0.f; ++R) {
+
+    const int sl = 10 - L;
+    const int G = 1 << L;
+    const int sub = 3 * (LT - L);
+    const double side = (double)(1 << sl) * g.inv_sc;
+    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+    for (int R = R0; R > 0 && sc > 0.f; ++R) {
       // cells of ring R, enumerated over the (2R+1)^3 cube, 64 per step
       const int side_n = 2 * R + 1;
       const int ncube = side_n * side_n * side_n;
       for (int c0 = 0; c0 < ncube; c0 += 64) {
         const int ci = c0 + lane;
-        const double kd = best.kth();  // wave-uniform, read before any branch
+        const double kd = best.kth(keff);  // wave-uniform, read before any branch
         int a = 0, b = 0;
         if (ci < ncube) {
           const int dx = ci % side_n - R, dy = (ci / side_n) % side_n - R, dz = ci / (side_n * side_n) - R;
@@ -548,25 +883,20 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
             }
           }
         }
-        // compact the non-empty cells of this step into s_start / s_pref
-        const bool has = b > a;
-        const unsigned long long hm = __ballot(has);
-        const int rank = __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-        int cnt = has ? b - a : 0;
-        int incl = cnt;  // inclusive prefix of counts over the non-empty cells
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const int y = __shfl_up(incl, d, 64);
-          if (lane >= d) incl += y;
+        const int ncell = list_cells(a, b);
+        if (ncell > 0) {
+          for_rows(ncell, [&](int j) {
+            bool pass = false;
+            float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float thr = admit_bound(best.kth(keff));
+            if (j >= 0) {
+              c = cen[j];
+              pass = d2_screen(qxf, qyf, qzf, c) <= thr && j != p;
+            }
+            insert_passing(pass, pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0,
+                           __float_as_int(c.w));
+          });
         }
-        if (has) {
-          s_start[rank] = a;
-          s_pref[rank] = incl - cnt;
-        }
-        const int ncell = __popcll(hm);
-        if (lane == 63) s_pref[ncell] = incl;
-        __syncthreads();
-        if (ncell > 0) scan_cells(ncell);
         __syncthreads();
       }
       double rho = INFINITY;
@@ -577,11 +907,9 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       if (cz - R > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - R) * side + g.margin));
       if (cz + R + 1 < G) rho = fmin(rho, (g.lo[2] + (cz + R + 1) * side - g.margin) - qz);
       if (!(rho < INFINITY)) break;
-      if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.kth()) break;
+      if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.kth(keff)) break;
     }
     // row out: lane t < keff holds entry t
-    const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
-    int* out = nbr + row * k_out;
     if (lane < k_out) {
       int o = -1;
       if (lane < keff) o = inv ? inv[best.l] : best.l;
@@ -589,12 +917,6 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
     }
     __syncthreads();
   }
-}
-
-__global__ void k_scatter_flagged(const int* __restrict__ flag, const int* __restrict__ pos, int n,
-                                  int* __restrict__ list) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n && flag[p]) list[pos[p]] = p;
 }
 
 __global__ void k_invert(const float4* __restrict__ cen, int n, int* __restrict__ inv) {
@@ -613,20 +935,23 @@ __global__ void k_gather_cen(const float* __restrict__ xyz3, const int* __restri
 
 }  // namespace
 
-// Finest table level of a segment of n rows: about 8^L >= n (moved by the
-// tuned bias), between 1 and 7.
+// Finest table level of a segment of n rows: one above the smallest level L
+// with 8^L >= n (about 1/8 row per cell: surfaces crowd their cells, and a
+// query takes coarser levels where it needs them), moved down by the tuned
+// bias, between 1 and 8.  8^LT < 64 n bounds the table.
 int table_level(long long n) {
   int L = 1;
-  while (L < 7 && (1ll << (3 * L)) < n) ++L;
-  L += tuning_for(n).knn_level_bias;
-  return L < 1 ? 1 : (L > 7 ? 7 : L);
+  while (L < 8 && (1ll << (3 * L)) < n) ++L;
+  int LT = L + 1 + tuning_for(n).knn_level_bias;
+  if (LT > L + 1) LT = L + 1;
+  return LT < 1 ? 1 : (LT > 8 ? 8 : LT);
 }
 
 // Upper bound of table_level(n) over every allowed bias (workspace sizing).
 int table_level_max(long long n) {
   int L = 1;
-  while (L < 7 && (1ll << (3 * L)) < n) ++L;
-  return L + 1 > 7 ? 7 : L + 1;
+  while (L < 8 && (1ll << (3 * L)) < n) ++L;
+  return L + 1 > 8 ? 8 : L + 1;
 }
 
 int kclass_of(int keff) {
@@ -642,9 +967,7 @@ KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes) {
   m.hist = c.take<int>(entries + 1);
   m.table = c.take<int>(entries + 1);
   m.inv = c.take<int>(n);
-  m.sflag = c.take<int>(n);
-  m.spos = c.take<int>(n);
-  m.sparse = c.take<int>(n);
+  m.retry = c.take<int2>(n);
   m.counters = c.take<int>(64);
   const size_t scan = std::max(scan_temp_bytes(entries + 1), scan_temp_bytes(n));
   m.scan_temp = base ? (char*)base + c.bytes() : nullptr;
@@ -653,36 +976,38 @@ KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes) {
 }
 
 void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
-               void* mem, int* d_unsorted, bool invert, hipStream_t st) {
+               void* mem, int* d_unsorted, hipStream_t st) {
   KnnMem m = carve_knn(mem, n, entries, nullptr);
   fill_i32(m.hist, 0, entries + 1, st);
   k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, m.hist, d_unsorted);
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(m.hist, m.table, entries + 1, nullptr, m.scan_temp, st);
-  if (invert) {
-    k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, m.inv);
-    NG_LAUNCH_CHECK();
-  }
+  k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, m.inv);
+  NG_LAUNCH_CHECK();
 }
 
 template <int K>
 void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
              const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
-  const int bs = tuning_for(n).knn_block;
-  k_knn_grid<K><<<blocks_for(n, bs), bs, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
-                                                  rows_logical, nbr, m.sflag);
+  const Tuning& t = tuning_for(n);
+  int bs = t.knn_block;
+  while (bs > 64 && (size_t)(17 + 2 * K) * bs * sizeof(unsigned) > 65536) bs >>= 1;
+  const size_t lds = (size_t)(17 + 2 * K) * bs * sizeof(unsigned);
+  k_knn_lane<K><<<blocks_for(n, bs), bs, lds, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
+                                                    rows_logical, nbr, t.knn_block_min,
+                                                    t.knn_lane_rows, m.retry, m.counters + 1);
   NG_LAUNCH_CHECK();
 }
 
 template <int K>
 void query_wave_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
                   const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
-  // the sparse count stays on the device: a grid of fixed size strides over it
+  // the retry count stays on the device: a grid of fixed size strides over it
   const int cap = tuning_for(n).knn_wave_grid;
   unsigned g = (unsigned)(n < cap ? n : cap);
   if (g < 1) g = 1;
-  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr,
-                                  m.sparse, m.counters + 1);
+  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, m.inv, rows_logical,
+                                  tuning_for(n).knn_block_min, nbr, m.retry, m.counters + 1);
   NG_LAUNCH_CHECK();
 }
 
@@ -691,16 +1016,14 @@ void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo
                int* nbr, hipStream_t st) {
   KnnMem m = carve_knn(mem, n, entries, nullptr);
   const int* inv = use_inv ? m.inv : nullptr;
-  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr, m.sflag);
+  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr);
   NG_LAUNCH_CHECK();
+  fill_i32(m.counters + 1, 0, 1, st);
   if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
   if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
   if (class_mask & 4u) query_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
   if (class_mask & 8u) query_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  // sparse queries, compacted in working (Morton) order
-  scan_exclusive_i32(m.sflag, m.spos, n, m.counters + 1, m.scan_temp, st);
-  k_scatter_flagged<<<blocks_for(n, 256), 256, 0, st>>>(m.sflag, m.spos, n, m.sparse);
-  NG_LAUNCH_CHECK();
+  // retries (unordered: each query's result does not depend on the order)
   if (class_mask & 1u) query_wave_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
   if (class_mask & 2u) query_wave_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
   if (class_mask & 4u) query_wave_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
@@ -766,7 +1089,7 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   const long long entries = table_entries(h.LT);
   KnnMem m = carve_knn(rest, n, entries, nullptr);
   fill_i32(m.counters, 0, 1, st);  // order check: sorted above by the same keys
-  knn_build(cen, n, nullptr, dseg, entries, rest, m.counters, false, st);
+  knn_build(cen, n, nullptr, dseg, entries, rest, m.counters, st);
   knn_query(cen, n, k, nullptr, dseg, class_bit(h.kclass), entries, rest, false, 1, nbr, st);
   // the host copy of h must outlive the async copy
   NG_HIP(hipStreamSynchronize(st));

@@ -29,21 +29,6 @@ constexpr unsigned long long KEY_MAX = ~0ull;
 
 NG_DEV int logical(const int* lg, int p) { return lg ? lg[p] : p; }
 
-// Appends `value` for every lane with `flag`, one atomic per wave.
-NG_DEV void append_wave(bool flag, int value, int* list, int* count) {
-  const unsigned long long m = __ballot(flag);
-  if (m == 0) return;
-  const int lane = lane_id();
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(count, __popcll(m));
-  base = __shfl(base, leader, 64);
-  if (flag) {
-    const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-    list[base + __popcll(below)] = value;
-  }
-}
-
 // ---- generic incidence from an arbitrary edge list (stage entry point) ----
 NG_DEV bool edge_ok(int a, int b, int n) { return a >= 0 && a < n && b >= 0 && b < n && a != b; }
 
@@ -80,7 +65,12 @@ __global__ void k_adj_fill(const int* __restrict__ ea, const int* __restrict__ e
 }
 
 // ---- matching iterations ----------------------------------------------------
-// act == nullptr: every vertex [0, n) is active.
+// act == nullptr: every vertex [0, n) is active, and (first iteration) every
+// vertex is free.
+//
+// pick: each active vertex takes its smallest entry whose other end is free.
+// The entries are read four at a time (keys, other ends, then the other
+// ends' partner slots), so a lane waits on two loads per four entries.
 __global__ void __launch_bounds__(256)
 k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
           const int* __restrict__ au, const int* __restrict__ partner,
@@ -88,19 +78,37 @@ k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
           int* __restrict__ pick, unsigned* __restrict__ pcost, int* __restrict__ next_count) {
   const int cnt = act ? *act_count : n;
   if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  const bool all_free = act == nullptr;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
     const int v = act ? act[i] : i;
     unsigned long long best = KEY_MAX;
     int bu = -1;
+    int t = aoff[v];
     const int t1 = aoff[v + 1];
-    for (int t = aoff[v]; t < t1; ++t) {
-      const unsigned long long key = akey[t];
-      if (key < best) {
-        const int u = au[t];
-        if (partner[u] < 0) {
-          best = key;
-          bu = u;
+    for (; t + 4 <= t1; t += 4) {
+      unsigned long long k[4];
+      int u[4];
+      bool f[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        k[q] = akey[t + q];
+        u[q] = au[t + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f[q] = all_free || partner[u[q]] < 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (f[q] && k[q] < best) {
+          best = k[q];
+          bu = u[q];
         }
+    }
+    for (; t < t1; ++t) {
+      const unsigned long long key = akey[t];
+      const int u = au[t];
+      if (key < best && (all_free || partner[u] < 0)) {
+        best = key;
+        bu = u;
       }
     }
     pick[v] = bu;
@@ -108,15 +116,48 @@ k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
   }
 }
 
-__global__ void __launch_bounds__(256)
+// Block-wide append: every thread with `flag` gets a distinct slot of
+// `list`, with one atomic on *count per block.  Every thread of the block
+// must call it (it synchronises the block).
+template <int NW>
+NG_DEV int block_append(bool flag, int* s_cnt, int* count) {
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  if (lane == 0) s_cnt[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int q = 0; q < NW; ++q) {
+      const int c = s_cnt[q];
+      s_cnt[q] = tot;
+      tot += c;
+    }
+    s_cnt[NW] = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+  const int slot = s_cnt[NW] + s_cnt[w] + __popcll(below);
+  __syncthreads();  // s_cnt is reused by the next call
+  return slot;
+}
+
+// match: mutual picks are matched (each end writes only its own partner
+// slot, the lower logical end records the pair); vertices whose pick was not
+// returned stay active.  Appends use one atomic per block and list.
+constexpr int kMatchBlock = 1024;
+__global__ void __launch_bounds__(kMatchBlock)
 k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n,
            const int* __restrict__ pick, const unsigned* __restrict__ pcost,
            const int* __restrict__ lg, int* __restrict__ partner, int* __restrict__ next_act,
            int* __restrict__ next_count, int* __restrict__ pair_a, int* __restrict__ pair_b,
            unsigned* __restrict__ pair_c, int* __restrict__ npairs) {
+  constexpr int NW = kMatchBlock / 64;
+  __shared__ int s_cnt[NW + 1];
   const int cnt = act ? *act_count : n;
-  const int span = (cnt + 255) & ~255;  // whole waves stay in the loop for the ballots
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < span; i += gridDim.x * blockDim.x) {
+  // whole blocks stay in the loop for the block-wide appends
+  const int span = (cnt + kMatchBlock - 1) / kMatchBlock * kMatchBlock;
+  for (int i0 = blockIdx.x * kMatchBlock; i0 < span; i0 += gridDim.x * kMatchBlock) {
+    const int i = i0 + (int)threadIdx.x;
     bool keep = false, rec = false;
     int v = 0, u = -1;
     if (i < cnt) {
@@ -131,22 +172,13 @@ k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n
         }
       }
     }
-    append_wave(keep, v, next_act, next_count);
-    // the lower logical end records the pair
-    const unsigned long long m = __ballot(rec);
-    if (m) {
-      const int lane = lane_id();
-      const int leader = __ffsll((long long)m) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(npairs, __popcll(m));
-      base = __shfl(base, leader, 64);
-      if (rec) {
-        const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-        const int s = base + __popcll(below);
-        pair_a[s] = v;
-        pair_b[s] = u;
-        pair_c[s] = pcost[v];
-      }
+    const int ks = block_append<NW>(keep, s_cnt, next_count);
+    if (keep) next_act[ks] = v;
+    const int ps = block_append<NW>(rec, s_cnt, npairs);
+    if (rec) {
+      pair_a[ps] = v;
+      pair_b[ps] = u;
+      pair_c[ps] = pcost[v];
     }
   }
 }
@@ -386,8 +418,11 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
       k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n,
                                    pick, pcost, out_cnt);
       NG_LAUNCH_CHECK();
-      k_ld_match<<<g, 256, 0, st>>>(in_list, in_cnt, n, pick, pcost, lg, partner, out_list,
-                                    out_cnt, pair_a, pair_b, pair_c, counters + 2);
+      unsigned gm = (unsigned)((known + kMatchBlock - 1) / kMatchBlock);
+      gm = gm < 1 ? 1 : (gm > 1024 ? 1024 : gm);
+      k_ld_match<<<gm, kMatchBlock, 0, st>>>(in_list, in_cnt, n, pick, pcost, lg, partner,
+                                             out_list, out_cnt, pair_a, pair_b, pair_c,
+                                             counters + 2);
       NG_LAUNCH_CHECK();
     }
     NG_HIP(hipMemcpyAsync(host, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, st));

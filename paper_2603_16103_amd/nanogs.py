@@ -63,6 +63,7 @@ class Stats(ctypes.Structure):
                 ("pairs_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("fallback_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("ld_iters_per_round", ctypes.c_int32 * MAX_ROUNDS),
+                ("knn_retry_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("stage_ms", ctypes.c_double * NTIMED),
                 ("stage_launches", ctypes.c_int32 * NTIMED)]
 
@@ -76,6 +77,7 @@ class Stats(ctypes.Structure):
                 "pairs_per_round": list(self.pairs_per_round[:r]),
                 "fallback_per_round": list(self.fallback_per_round[:r]),
                 "ld_iters_per_round": list(self.ld_iters_per_round[:r]),
+                "knn_retry_per_round": list(self.knn_retry_per_round[:r]),
                 "stage_ms": dict(zip(STAGES, self.stage_ms)),
                 "stage_launches": dict(zip(STAGES, self.stage_launches))}
 
@@ -83,7 +85,8 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("cost_block", ctypes.c_int32), ("knn_block", ctypes.c_int32),
                 ("knn_wave_grid", ctypes.c_int32), ("knn_level_bias", ctypes.c_int32),
-                ("select_check", ctypes.c_int32)]
+                ("select_check", ctypes.c_int32), ("knn_block_min", ctypes.c_int32),
+                ("knn_lane_rows", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -557,7 +560,11 @@ def apply_tuning_file(path: str) -> bool:
     if tab.get("arch") != "gfx950":
         return False
     for b, vals in enumerate(tab.get("buckets", [])[:TUNE_BUCKETS]):
-        t = Tuning(**{f: int(vals[f]) for f, _ in Tuning._fields_})
+        t = Tuning()
+        _check(_lib.nanogs_get_tuning(b, ctypes.byref(t)))  # fields the table lacks keep theirs
+        for f, _ in Tuning._fields_:
+            if f in vals:
+                setattr(t, f, int(vals[f]))
         _check(_lib.nanogs_set_tuning(b, ctypes.byref(t)))
     return True
 
