@@ -35,29 +35,31 @@ def src_hash(name):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-# Algorithmic bytes per launch of the single-kernel stages (each input and
-# output element counted once): n = splats in the pass, e = edges, k = kNN size.
-def algo_bytes(stage, n, e, k):
-    if stage == "cost":        # cen 16 + factors 32 + SH 192 per splat; ends 8 + cost 4 per edge
-        return 240 * n + 12 * e
-    if stage == "knn_query":   # centres 16 per splat in, k neighbour ids out
-        return 16 * n + 4 * k * n
+# Roofline terms of the single-kernel stages, per pass: (bound, algorithmic
+# work, unit).  n = splats in the pass, e = edges, k = kNN size, screens =
+# float distance screens the kNN block gather made (library statistics).
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+FLOPS_PER_SCREEN = 8      # 3 sub, 1 mul, 2 fma
+
+
+def stage_work(stage, n, e, k, screens):
+    if stage == "knn_query":   # block gather: distance screens (FP32 ALU)
+        return "alu", FLOPS_PER_SCREEN * screens
+    if stage == "cost":        # cen 16 + factors 32 + SH 192 per splat; ends 8 + cost 4 +
+        return "hbm", 240 * n + 36 * e  # two adjacency entries 24 per edge
     if stage == "precompute":  # shape 32 in, factors 32 out
-        return 64 * n
-    if stage == "knn_tree":    # centres in, boxes out (16 per splat, 2 x 16 per leaf pair)
-        return 16 * n + 4 * n
-    return None
+        return "hbm", 64 * n
+    return None, None
 
 
-KERNEL_OF = {"cost": "k_edge_cost", "knn_query": "k_knn_query", "precompute": "k_precompute",
-             "knn_tree": "k_tree_levels"}
-SOURCE_OF = {"cost": "cost.hip", "knn_query": "knn.hip", "precompute": "cost.hip",
-             "knn_tree": "knn.hip"}
+KERNEL_OF = {"knn_query": "k_knn_block<16>", "cost": "k_edge_cost", "precompute": "k_precompute"}
+SOURCE_OF = {"knn_query": "knn.hip", "cost": "cost.hip", "precompute": "cost.hip"}
 
 
-def traffic_for(stage, launches_bytes):
-    """HBM bytes per launch from the committed counter summary, scaled by the
-    copy-kernel calibration; None when absent or the kernel source changed."""
+def traffic_for(stage):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration); None when absent or
+    when the kernel's source changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -66,8 +68,7 @@ def traffic_for(stage, launches_bytes):
     ent = t.get("kernels", {}).get(KERNEL_OF[stage])
     if not ent or ent.get("source_sha") != src_hash(SOURCE_OF[stage]):
         return None
-    scale = t.get("copy_calibration", 1.0)
-    return (ent["fetch_kib"] + ent["write_kib"]) * 1024.0 * scale
+    return ent["bytes_per_launch"]
 
 
 def cpu_baseline(sample_n):
@@ -125,7 +126,7 @@ def main():
 
     stage_ms = {s: 0.0 for s in ng.STAGES}
     launches = {s: 0 for s in ng.STAGES}
-    bytes_by_stage = {s: 0.0 for s in ng.STAGES}
+    work_by_stage = {s: 0.0 for s in ng.STAGES}
     edges_total = 0
     last = None
     t0 = time.perf_counter()
@@ -136,12 +137,13 @@ def main():
         for s in ng.STAGES:
             stage_ms[s] += d["stage_ms"][s]
             launches[s] += d["stage_launches"][s]
-        for n_r, e_r in zip(d["n_per_round"], d["edges_per_round"]):
+        for n_r, e_r, sc_r in zip(d["n_per_round"], d["edges_per_round"],
+                                  d["knn_screens_per_round"]):
             edges_total += e_r
             for s in ng.STAGES:
-                b = algo_bytes(s, n_r, e_r, k)
-                if b is not None:
-                    bytes_by_stage[s] += b
+                _, w = stage_work(s, n_r, e_r, k, sc_r)
+                if w is not None:
+                    work_by_stage[s] += w
         last = d
         eprint(f"step {i + 1}/{args.steps}: {n_out} splats, {d['rounds']} passes")
     torch.cuda.synchronize()
@@ -150,16 +152,24 @@ def main():
 
     ms_step = 1000.0 * dt / args.steps
     value = args.n * args.steps / dt
-    single = [s for s in ("cost", "knn_query", "precompute") if launches[s] > 0]
-    dom = max(single, key=lambda s: stage_ms[s])
-    avg_ms = stage_ms[dom] / launches[dom]
-    bytes_per_launch = bytes_by_stage[dom] / launches[dom]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(dom, bytes_per_launch),
-            "kernel": KERNEL_OF[dom], "avg_launch_us": round(1000 * avg_ms, 2),
-            "algo_bytes_per_launch": int(bytes_per_launch)}
+    def roof(stage):
+        bound, _ = stage_work(stage, 1, 1, k, 1)
+        avg_ms = stage_ms[stage] / launches[stage]
+        per_launch = work_by_stage[stage] / launches[stage]
+        if bound == "hbm":
+            achieved, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            achieved, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+        return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 5), "traffic": traffic_for(stage),
+                "kernel": KERNEL_OF[stage], "avg_launch_us": round(1000 * avg_ms, 2),
+                ("algo_bytes_per_launch" if bound == "hbm" else "algo_flops_per_launch"):
+                    int(per_launch)}
+
+    single = [s for s in KERNEL_OF if launches[s] > 0]
+    dom = max(single, key=lambda s: stage_ms[s])  # the single-kernel stage with most time
+    roof_dom = roof(dom)
+    others = {s: roof(s) for s in single if s != dom}
     res = {
         "metric": "Gaussians simplified/s (1M→10%)",
         "value": round(value, 1),
@@ -179,11 +189,13 @@ def main():
                    "passes": last["rounds"], "n_per_pass": last["n_per_round"],
                    "edges_per_pass": last["edges_per_round"],
                    "fp64_edges_per_pass": last["fallback_per_round"],
-                   "knn_wave_retries_per_pass": last["knn_retry_per_round"]},
+                   "knn_wave_retries_per_pass": last["knn_retry_per_round"],
+                   "knn_screens_per_pass": last["knn_screens_per_round"]},
         "edge_costs_per_s": round(edges_total / (stage_ms["cost"] * 1e-3), 1)
         if stage_ms["cost"] > 0 else None,
         "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 4) for s in ng.STAGES},
-        "roofline": roof,
+        "roofline": roof_dom,
+        "roofline_other_kernels": others,
     }
     if not args.no_cpu_baseline:
         eprint("cpu baseline (oracle) on", args.cpu_sample, "splats")

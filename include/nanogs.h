@@ -97,7 +97,8 @@ typedef struct {
 /* Stages timed into nanogs_stats.stage_ms when options.timing is set. */
 #define NANOGS_T_PRECOMPUTE 0 /* per-splat Cholesky factors and weights */
 #define NANOGS_T_KNN_TREE 1   /* cell table of the Morton-sorted centres */
-#define NANOGS_T_KNN_QUERY 2  /* exact kNN query kernel */
+#define NANOGS_T_KNN_QUERY 2  /* kNN block gather kernel (level, histogram,
+                                 buffered rows) */
 #define NANOGS_T_EDGES 3      /* union edges (flags, scan, emit) */
 #define NANOGS_T_COST 4       /* FP32 edge-cost kernel */
 #define NANOGS_T_COST_FP64 5  /* FP64 recomputation of flagged edges */
@@ -105,7 +106,9 @@ typedef struct {
 #define NANOGS_T_MERGE 7      /* merge and compaction */
 #define NANOGS_T_SETUP 8      /* spatial order and activation */
 #define NANOGS_T_OUTPUT 9     /* deactivation into the caller's order */
-#define NANOGS_NTIMED 10
+#define NANOGS_T_KNN_EXACT 10 /* kNN exact keys of the buffered rows */
+#define NANOGS_T_KNN_WAVE 11  /* kNN queries finished one wave each */
+#define NANOGS_NTIMED 12
 
 typedef struct {
   int32_t rounds;                          /* passes that merged >= 1 pair */
@@ -118,6 +121,8 @@ typedef struct {
   int32_t ld_iters_per_round[NANOGS_MAX_ROUNDS]; /* matching iterations */
   int64_t knn_retry_per_round[NANOGS_MAX_ROUNDS]; /* kNN queries finished by
                                                      the wave search */
+  int64_t knn_screens_per_round[NANOGS_MAX_ROUNDS]; /* float distance screens
+                                                       of the block gather */
   double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
   int32_t stage_launches[NANOGS_NTIMED];
 } nanogs_stats;

@@ -323,8 +323,7 @@ nanogs_status nanogs_deactivate(const nanogs_splats* s, int64_t n, nanogs_gaussi
 }
 
 size_t nanogs_knn_workspace_bytes(int64_t n, int32_t k) {
-  (void)k;
-  return knn_plain_bytes(n < 1 ? 1 : n);
+  return knn_plain_bytes(n < 1 ? 1 : n, k < 1 ? 1 : (k > NANOGS_MAX_K ? NANOGS_MAX_K : k));
 }
 
 nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr, void* ws,
@@ -334,7 +333,7 @@ nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr, vo
     if (n == 0) return NANOGS_OK;
     NG_CHECK(check_ptr(mu, 4, "mu"));
     NG_CHECK(check_ptr(nbr, 4, "nbr"));
-    NG_CHECK(check_ws(ws, ws_bytes, knn_plain_bytes(n)));
+    NG_CHECK(check_ws(ws, ws_bytes, knn_plain_bytes(n, k)));
     if (n == 1) {
       fill_i32(nbr, -1, k, stream);
       return NANOGS_OK;

@@ -111,7 +111,7 @@ static EngineWs carve_engine(void* base, long long R, int K, int J) {
   s.boxes = c.take<unsigned>((size_t)J * 8);
   s.temp = base ? (char*)base + c.bytes() : nullptr;
   size_t kb = 0;
-  carve_knn(nullptr, R, table_bound(R, J), &kb);
+  carve_knn(nullptr, R, table_bound(R, J), K, &kb);
   size_t t = sort_temp_bytes(R);
   t = std::max(t, kb);
   t = std::max(t, edges_temp_bytes(R, K));
@@ -293,20 +293,20 @@ int Engine::step(StageTimer* T) {
   fill_i32(W.counters + 2, 0, 1, st_);
   knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, st_);
   if (T) T->stop(tk);
-  tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
-  knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, st_);
-  if (T) T->stop(tk);
+  knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, T, st_);
   tk = T ? T->start(NANOGS_T_EDGES) : -1;
   const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
   launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
   if (T) T->stop(tk);
   NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(host + 2, carve_knn(W.temp, N, entries, nullptr).counters + 1,
-                        sizeof(int), hipMemcpyDeviceToHost, st_));
+  const int* kc = carve_knn(W.temp, N, entries, K_, nullptr).counters;
+  NG_HIP(hipMemcpyAsync(host + 2, kc + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(host + 3, kc + 8, sizeof(long long), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipStreamSynchronize(st_));
   const long long m = host[0];
   const long long knn_retries = *(int*)(host + 2);
+  const long long knn_screens = host[3];
   if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
 
   const CrnTab ct{W.crn, o_.S, sg, W.seg};
@@ -354,6 +354,7 @@ int Engine::step(StageTimer* T) {
       j.stats.fallback_per_round[r] = searching == 1 ? fb : 0;
       j.stats.ld_iters_per_round[r] = sel.iters;
       j.stats.knn_retry_per_round[r] = searching == 1 ? knn_retries : 0;
+      j.stats.knn_screens_per_round[r] = searching == 1 ? knn_screens : 0;
     }
   }
 

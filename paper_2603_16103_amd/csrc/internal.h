@@ -204,15 +204,18 @@ unsigned class_bit(int kclass);
 long long table_entries(int LT);
 // kNN scratch: concatenated per-segment cell tables, logical -> working
 // inverse, sparse-query list.
+struct StageTimer;
 struct KnnMem {
   int* hist;
   int* table;
   int* inv;      // logical index -> working row
-  int2* retry;   // (row, level) of the queries the wave search finishes
+  int2* retry;   // (row, 0) of the queries the wave search finishes
+  int2* ginfo;   // per query: (rows buffered by the block gather or -1, level)
   int* counters;  // [1]: retry count
+  int* gbuf;     // [slot][n] rows buffered by the block gather
   void* scan_temp;
 };
-KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes);
+KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* bytes);
 // Cell tables of every segment with LT > 0 (rows sorted by Morton key within
 // each segment; *d_unsorted or-ed with 1 if not), and the logical -> working
 // inverse (rows carry their logical index in cen[].w).
@@ -225,9 +228,9 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
 // the kernel classes present (class_bit).
 void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
                unsigned class_mask, long long entries, void* mem, bool use_inv, int rows_logical,
-               int* nbr, hipStream_t st);
+               int* nbr, StageTimer* T, hipStream_t st);
 // Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
-size_t knn_plain_bytes(long long n);
+size_t knn_plain_bytes(long long n, int k);
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);
 
 // edges.hip -- union edges and the incidence structure of the selection

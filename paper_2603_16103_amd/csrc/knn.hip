@@ -22,6 +22,7 @@
 #include <cstring>
 #include <climits>
 
+#include "../../include/nanogs.h"
 #include "internal.h"
 
 namespace ng {
@@ -287,7 +288,7 @@ constexpr unsigned long long kBlkX = pack_blk_axis(0), kBlkY = pack_blk_axis(1),
                              kBlkZ = pack_blk_axis(2);
 NG_DEV int blk(unsigned long long packed, int c) { return (int)((packed >> (2 * c)) & 3ull) - 1; }
 
-constexpr int kExtCells = 80;   // cells of the k-th ball's range scanned by the lane itself
+constexpr int kExtCells = 64;   // cells of the k-th ball's range a lane may screen itself
 // float screen: a point whose exact d2 is <= B has float d2 <= B * kScreen
 // (the float evaluation rounds at most five times, about 3e-7 relative)
 constexpr float kScreen = 1.000005f;
@@ -298,30 +299,49 @@ NG_DEV float d2_screen(float qx, float qy, float qz, float4 c) {
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-// Result of one lane query: -1 done, 0 retry from scratch, L > 0 retry from
-// the block list at level L (already written to nbr).
+// Query geometry shared by the block gather and the exact pass.
+struct QueryGeo {
+  float qxf, qyf, qzf;
+  float lof[3];
+  float ext, sc;
+  unsigned qi[3];
+};
+
+NG_DEV QueryGeo query_geo(const float4& cq, const SegInfo& S) {
+  QueryGeo q;
+  q.qxf = cq.x;
+  q.qyf = cq.y;
+  q.qzf = cq.z;
+  float hif[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.lof[a] = ord2f(S.box[a]);
+    hif[a] = ord2f(S.box[3 + a]);
+  }
+  q.ext = fmaxf(fmaxf(hif[0] - q.lof[0], hif[1] - q.lof[1]), hif[2] - q.lof[2]);
+  q.sc = q.ext > 0.f ? 1023.0f / q.ext : 0.f;
+  q.qi[0] = quant(q.qxf, q.lof[0], q.sc);
+  q.qi[1] = quant(q.qyf, q.lof[1], q.sc);
+  q.qi[2] = quant(q.qzf, q.lof[2], q.sc);
+  return q;
+}
+
+// Passes A and B of the block search for query p (see above).  Returns the
+// number of buffered rows (p itself included), written to gbuf[i * n + p],
+// or -1 when the block exceeds lane_rows or the buffer overflows (the wave
+// search starts from scratch); *level = the block's level.
 template <int K>
-NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const SegInfo& S,
-                      const int* __restrict__ table, const int* __restrict__ inv, int rows_logical,
-                      int* __restrict__ nbr, int block_min, int lane_rows,
-                      unsigned* __restrict__ hist,
-                      int* __restrict__ buf, int bs) {
+NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegInfo& S,
+                        const int* __restrict__ table, int block_min, int lane_rows,
+                        unsigned* __restrict__ hist, int bs, int* __restrict__ gbuf, int* level,
+                        int* screens) {
   constexpr int CAP = 2 * K;
   const int keff = S.keff;
   const int LT = S.LT;
   const int* cstart = table + S.toff;
   const int rb = S.row0 - cstart[0];  // table values -> rows
-  const float4 cq = cen[p];
-  const float qxf = cq.x, qyf = cq.y, qzf = cq.z;
-  float lof[3], hif[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lof[a] = ord2f(S.box[a]);
-    hif[a] = ord2f(S.box[3 + a]);
-  }
-  const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
-  const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
-  const unsigned qi[3] = {quant(qxf, lof[0], sc), quant(qyf, lof[1], sc), quant(qzf, lof[2], sc)};
+  const QueryGeo q = query_geo(cen[p], S);
+  const float qxf = q.qxf, qyf = q.qyf, qzf = q.qzf;
 
   // level: finest L whose block holds >= bmin rows (level 1's block is the
   // whole segment); bmin > keff, so the block holds keff rows besides p.
@@ -333,7 +353,7 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
   unsigned mask = 0u;
   for (;; --L) {
     const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
-    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+    const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
     rows = 0;
     mask = 0u;
 #pragma unroll
@@ -348,13 +368,15 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
     }
     if (rows >= bmin || L <= 1) break;
   }
-  if (rows > lane_rows) return 0;
+  *level = L;
+  *screens = 0;
+  if (rows > lane_rows) return -1;
+  int nscreen = 0;  // float distance screens (passes A and B)
 
   const int sl = 10 - L, sub = 3 * (LT - L);
-  const int G = 1 << L;
-  const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
-  const float side = sc > 0.f ? (float)(1 << sl) / sc : 0.f;
-  const float marg = 1e-5f * ext;
+  const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
+  const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;
+  const float marg = 1e-5f * q.ext;
   int base = (int)(__float_as_uint(side * side) >> 21) - 24;
   if (base < 0) base = 0;
 
@@ -362,9 +384,9 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
   // the quantisation margin)
   auto box_d2 = [&](int c) {
     const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
-    const float gx = fmaxf(fmaxf(lof[0] + x * side - marg - qxf, qxf - (lof[0] + (x + 1) * side + marg)), 0.f);
-    const float gy = fmaxf(fmaxf(lof[1] + y * side - marg - qyf, qyf - (lof[1] + (y + 1) * side + marg)), 0.f);
-    const float gz = fmaxf(fmaxf(lof[2] + z * side - marg - qzf, qzf - (lof[2] + (z + 1) * side + marg)), 0.f);
+    const float gx = fmaxf(fmaxf(q.lof[0] + x * side - marg - qxf, qxf - (q.lof[0] + (x + 1) * side + marg)), 0.f);
+    const float gy = fmaxf(fmaxf(q.lof[1] + y * side - marg - qyf, qyf - (q.lof[1] + (y + 1) * side + marg)), 0.f);
+    const float gz = fmaxf(fmaxf(q.lof[2] + z * side - marg - qzf, qzf - (q.lof[2] + (z + 1) * side + marg)), 0.f);
     return fmaf(gz, gz, fmaf(gy, gy, gx * gx));
   };
   auto range = [&](int c, int& a, int& b) {
@@ -389,7 +411,7 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
     return __uint_as_float((unsigned)(base + bstar + 1) << 21);
   };
   // visits the non-empty cells in block order, the range of the next cell
-  // loaded before the current one is scanned; f(c, a, b) scans one cell
+  // loaded before the current one is scanned; f(c, a, b, next) scans one
   auto for_cells = [&](auto&& f) {
     unsigned rem = mask;
     int c = rem ? __ffs(rem) - 1 : -1;
@@ -419,6 +441,7 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
   float tau = INFINITY;
   for_cells([&](int c, int a, int b, int cn) {
     if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * kPrune)) {
+      nscreen += b - a;
       int j = a;
       for (; j + 4 <= b; j += 4) {
         const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
@@ -436,16 +459,17 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
   tau = kth_edge();
 
   // pass B: rows within tau into the buffer (slot CAP takes the overflow);
-  // p itself (distance 0, own cell) is buffered too and skipped in pass C
+  // p itself (distance 0, own cell) is buffered too and skipped later
   const float adm = tau * kScreen;
   int nb = 0;
   auto keep = [&](const float4& cj, int j) {
     const bool in = d2_screen(qxf, qyf, qzf, cj) <= adm;
-    buf[(nb < CAP ? nb : CAP) * bs] = j;
+    gbuf[(long long)(nb < CAP ? nb : CAP) * n + p] = j;
     nb += in ? 1 : 0;
   };
   for_cells([&](int c, int a, int b, int) {
     if (c > 0 && box_d2(c) > tau * kPrune) return;
+    nscreen += b - a;
     int j = a;
     for (; j + 4 <= b; j += 4) {
       const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
@@ -456,71 +480,130 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
     }
     for (; j < b; ++j) keep(cen[j], j);
   });
-  if (nb > CAP || nb < keff + 1) return 0;  // (nb >= keff + 1 by construction)
 
-  // pass C: exact keys of the buffered rows.  Then every row within the
-  // k-th distance lies in a level-L cell whose box (widened by the margin)
-  // meets the ball; if all such cells belong to the block the list is exact.
-  // Otherwise the rows of the few cells outside the block that pass the
-  // screen are buffered and given exact keys in a second round (the ball
-  // only shrinks meanwhile), unless the ball spans more than kExtCells cells
-  // (the wave search then goes on from ring 2) or they overflow the buffer.
-  const double qx = qxf, qy = qyf, qz = qzf;
-  Best<K> best;
-  best.init();
-  int res = -1;
-  for (int round = 0;; ++round) {
-    for (int i = 0; i < nb; ++i) {
-      const int j = buf[i * bs];
-      const float4 c = cen[j];
-      if (j != p) best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
-    }
-    if (round > 0 || !(sc > 0.f)) break;  // (a zero-extent grid: one cell holds every row)
-    const Grid g = grid_from_box(S.box);
-    const double sd = (double)(1 << sl) * g.inv_sc;
-    const double kd = best.kth(keff);
-    const double r = sqrt(kd) + 2.0 * g.margin;
-    const double q3[3] = {qx, qy, qz};
+  // Rows outside the block: the block's keff-th float distance bounds the
+  // true k-th one (times the rounding factor), so every row that may enter
+  // the list lies within r of the query, in a level-L cell whose box
+  // (widened by the margin) meets that ball.  The cells of that range
+  // outside the block are screened here too, unless the range spans more
+  // than kExtCells cells (then the wave search takes the query).
+  if (q.sc > 0.f) {  // (a zero-extent grid has every row in the own cell)
+    const int G = 1 << L;
+    const float r = sqrtf(adm) * 1.000001f + 2.f * marg;
+    const float qq[3] = {qxf, qyf, qzf};
     const int c3[3] = {cx, cy, cz};
     int lo3[3], hi3[3];
     bool inside = true;
     int vol = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double f0 = floor((q3[a] - r - g.lo[a]) / sd);
-      const double f1 = floor((q3[a] + r - g.lo[a]) / sd);
-      lo3[a] = f0 < 0.0 ? 0 : (f0 > G - 1 ? G - 1 : (int)f0);
-      hi3[a] = f1 < 0.0 ? 0 : (f1 > G - 1 ? G - 1 : (int)f1);
+      const float f0 = floorf((qq[a] - r - q.lof[a]) / side);
+      const float f1 = floorf((qq[a] + r - q.lof[a]) / side);
+      lo3[a] = f0 < 0.f ? 0 : (f0 > (float)(G - 1) ? G - 1 : (int)f0);
+      hi3[a] = f1 < 0.f ? 0 : (f1 > (float)(G - 1) ? G - 1 : (int)f1);
       inside = inside && lo3[a] >= c3[a] - 1 && hi3[a] <= c3[a] + 1;
       vol *= hi3[a] - lo3[a] + 1;
     }
-    if (inside) break;
-    if (vol > kExtCells) {
-      res = L;
-      break;
-    }
-    const float thr = admit_bound(kd);
-    nb = 0;
-    for (int z = lo3[2]; z <= hi3[2]; ++z)
-      for (int y = lo3[1]; y <= hi3[1]; ++y)
-        for (int x = lo3[0]; x <= hi3[0]; ++x) {
-          if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
-          const double gx = fmax(fmax(g.lo[0] + x * sd - g.margin - qx, qx - (g.lo[0] + (x + 1) * sd + g.margin)), 0.0);
-          const double gy = fmax(fmax(g.lo[1] + y * sd - g.margin - qy, qy - (g.lo[1] + (y + 1) * sd + g.margin)), 0.0);
-          const double gz = fmax(fmax(g.lo[2] + z * sd - g.margin - qz, qz - (g.lo[2] + (z + 1) * sd + g.margin)), 0.0);
-          if ((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12)) continue;
-          const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                              spread10((unsigned)z)) << sub;
-          const int a = cstart[f] + rb, b = cstart[f + (1u << sub)] + rb;
-          for (int j = a; j < b; ++j) {
-            const bool in = d2_screen(qxf, qyf, qzf, cen[j]) <= thr;
-            buf[(nb < CAP ? nb : CAP) * bs] = j;
-            nb += in ? 1 : 0;
-          }
+    if (!inside) {
+      if (!(tau < INFINITY) || vol > kExtCells) return -1;
+      // the range's cells outside the block whose box is within the bound
+      // (bit i: cell i of the range in x-fastest order)
+      const int nx = hi3[0] - lo3[0] + 1, ny = hi3[1] - lo3[1] + 1;
+      unsigned long long emask = 0ull;
+      for (int i = 0; i < vol; ++i) {
+        const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
+        if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
+        const float gx = fmaxf(fmaxf(q.lof[0] + x * side - marg - qxf, qxf - (q.lof[0] + (x + 1) * side + marg)), 0.f);
+        const float gy = fmaxf(fmaxf(q.lof[1] + y * side - marg - qyf, qyf - (q.lof[1] + (y + 1) * side + marg)), 0.f);
+        const float gz = fmaxf(fmaxf(q.lof[2] + z * side - marg - qzf, qzf - (q.lof[2] + (z + 1) * side + marg)), 0.f);
+        if (!(fmaf(gz, gz, fmaf(gy, gy, gx * gx)) > tau * kPrune)) emask |= 1ull << i;
+      }
+      auto erange = [&](int i, int& a, int& b) {
+        const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
+        const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                            spread10((unsigned)z)) << sub;
+        a = cstart[f] + rb;
+        b = cstart[f + (1u << sub)] + rb;
+      };
+      // as in for_cells: the next cell's range is loaded before a cell is scanned
+      int i = emask ? __ffsll((long long)emask) - 1 : -1;
+      int a = 0, b = 0;
+      if (i >= 0) erange(i, a, b);
+      while (i >= 0) {
+        emask &= emask - 1ull;
+        const int in_ = emask ? __ffsll((long long)emask) - 1 : -1;
+        int an = 0, bn = 0;
+        if (in_ >= 0) erange(in_, an, bn);
+        nscreen += b - a;
+        int j = a;
+        for (; j + 4 <= b; j += 4) {
+          const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
+          keep(c0, j);
+          keep(c1, j + 1);
+          keep(c2, j + 2);
+          keep(c3, j + 3);
         }
-    if (nb > CAP) return 0;
+        for (; j < b; ++j) keep(cen[j], j);
+        i = in_;
+        a = an;
+        b = bn;
+      }
+    }
   }
+  *screens = nscreen;
+  if (nb > CAP || nb < keff + 1) return -1;  // (nb >= keff + 1 by construction)
+  return nb;
+}
 
+template <int K>
+__global__ void __launch_bounds__(256)
+k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
+            const SegInfo* __restrict__ seg, const int* __restrict__ table, int block_min,
+            int lane_rows, int* __restrict__ gbuf, int2* __restrict__ ginfo,
+            unsigned long long* __restrict__ screens) {
+  extern __shared__ unsigned s_hist[];  // [16][bs]: two 16-bit bin counts per word
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int ns = 0;
+  if (p < n) {
+    const SegInfo& S = seg[sg ? sg[p] : 0];
+    if (S.kclass == K) {
+      int L = 0;
+      const int nb = block_gather<K>(cen, p, n, S, table, block_min, lane_rows,
+                                     s_hist + threadIdx.x, blockDim.x, gbuf, &L, &ns);
+      ginfo[p] = make_int2(nb, L);
+    }
+  }
+  // the screens of the wave, one atomic
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) ns += __shfl_xor(ns, d, 64);
+  if (lane_id() == 0 && ns) atomicAdd(screens, (unsigned long long)ns);
+}
+
+// Pass C: the buffered rows get the exact key (d2 in double, logical index)
+// and a sorted insertion; the buffer holds every row that may enter the list,
+// so its keff best are the exact list.  Returns 0 (retry from scratch) when
+// the gather gave up, else -1.
+template <int K>
+NG_DEV int exact_query(const float4* __restrict__ cen, int p, int n, int k_out,
+                       const SegInfo& S, const int* __restrict__ inv, int rows_logical,
+                       int* __restrict__ nbr, const int* __restrict__ gbuf, int2 info) {
+  const int nb = info.x;
+  if (nb < 0) return 0;
+  const int keff = S.keff;
+  const float4 cq = cen[p];
+  const double qx = cq.x, qy = cq.y, qz = cq.z;
+  Best<K> best;
+  best.init();
+  // software pipeline: the next row's centre is loaded while one is inserted
+  int j = gbuf[p];
+  float4 c = cen[j];
+  for (int i = 0; i < nb; ++i) {
+    const int jn = i + 1 < nb ? gbuf[(long long)(i + 1) * n + p] : p;
+    const float4 cn = cen[jn];
+    if (j != p) best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
+    j = jn;
+    c = cn;
+  }
   const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
   int* out = nbr + row * k_out;
 #pragma unroll
@@ -532,24 +615,22 @@ NG_DEV int lane_query(const float4* __restrict__ cen, int p, int k_out, const Se
     }
   }
   for (int t = K; t < k_out; ++t) out[t] = -1;
-  return res;
+  return -1;
 }
 
 template <int K>
 __global__ void __launch_bounds__(256)
-k_knn_lane(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
-           const SegInfo* __restrict__ seg, const int* __restrict__ table,
-           const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr, int block_min,
-           int lane_rows, int2* __restrict__ retry, int* __restrict__ n_retry) {
-  extern __shared__ unsigned s_lane[];  // [16][bs] histogram words, then [2K + 1][bs] buffer
-  const int bs = blockDim.x, tid = threadIdx.x;
-  const int p = blockIdx.x * bs + tid;
+k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
+            const SegInfo* __restrict__ seg, const int* __restrict__ table,
+            const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
+            const int* __restrict__ gbuf, const int2* __restrict__ ginfo,
+            int2* __restrict__ retry, int* __restrict__ n_retry) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   int res = -1;
   if (p < n) {
     const SegInfo& S = seg[sg ? sg[p] : 0];
     if (S.kclass == K)
-      res = lane_query<K>(cen, p, k_out, S, table, inv, rows_logical, nbr, block_min, lane_rows,
-                          s_lane + tid, (int*)(s_lane + 16 * bs) + tid, bs);
+      res = exact_query<K>(cen, p, n, k_out, S, inv, rows_logical, nbr, gbuf, ginfo[p]);
   }
   // retries, appended with one atomic per wave
   const bool need = res >= 0;
@@ -568,16 +649,15 @@ k_knn_lane(const float4* __restrict__ cen, int n, int k_out, const int* __restri
 }
 
 // ---- retries: one wave per query ---------------------------------------------
-// Queries whose block search could not prove its list exact, one wave each.
-// An entry (p, L > 0) holds the exact k best of the 3x3x3 block at level L
-// (written to nbr): the search goes on with rings R = 2, 3, ... of level-L
-// cells.  An entry (p, 0) starts from scratch at the finest level whose own
-// cell holds at least K + 1 rows (or level 1), with the own cell, then rings
-// R = 1, 2, ...  The lanes share the work: the cells of a ring are tested one
-// per lane (box against the current k-th distance), the rows of the cells
-// that pass are dealt out 64 at a time, and the k best live one entry per
-// lane (lanes 0..K-1, sorted), so an insertion is a ballot and a shift.  The
-// search stops once the k-th key is closer than the searched block's faces.
+// Queries the block gather gave up on (a block over knn_lane_rows rows, a
+// buffer overflow, or a k-th ball spanning too many cells), one wave each.
+// The lanes share the work: cells are looked up one per lane, their rows are
+// dealt out 64 at a time, and the k best live one entry per lane (lanes
+// 0..K-1, sorted), so an insertion is a ballot and a shift.  First the block
+// search at the finest level whose 3x3x3 block holds bmin rows; if its k-th
+// key reaches beyond the block, a ball search over the cells of the range
+// [q - r, q + r] (r: that k-th distance) at the finest level where it spans at
+// most 8 cells per axis.
 template <int K>
 struct WaveBest {
   double d;  // entry of this lane (lanes >= K hold +inf)
@@ -620,32 +700,29 @@ template <int K>
 __global__ void __launch_bounds__(64)
 k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
            const SegInfo* __restrict__ seg, const int* __restrict__ table,
-           const int* __restrict__ inv, const int* __restrict__ l2p, int rows_logical,
-           int block_min, int* __restrict__ nbr, const int2* __restrict__ list,
+           const int* __restrict__ inv, int rows_logical, int block_min,
+           int* __restrict__ nbr, const int2* __restrict__ list,
            const int* __restrict__ d_count) {
-  constexpr int CAPW = 256;  // rows the block search may buffer for exact keys
-  __shared__ int s_start[128];
-  __shared__ int s_pref[129];
+  constexpr int MAXC = 512;  // cells one search may list
+  __shared__ int s_start[MAXC];
+  __shared__ int s_pref[MAXC + 1];
   __shared__ int s_hist[32];
-  __shared__ int s_buf[CAPW];
   const int lane = threadIdx.x;
   const int count = *d_count;
   for (int qidx = blockIdx.x; qidx < count; qidx += gridDim.x) {
-    const int2 ent = list[qidx];
-    const int p = ent.x;
+    const int p = list[qidx].x;
     const SegInfo& S = seg[sg ? sg[p] : 0];
     if (S.kclass != K) continue;  // wave-uniform: one query per wave
     const int keff = S.keff;
     const int LT = S.LT;
-    const unsigned* box = S.box;
     const int* cstart = table + S.toff;
     const int rb = S.row0 - cstart[0];
-    const Grid g = grid_from_box(box);
+    const Grid g = grid_from_box(S.box);
     float lof[3], hif[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lof[a] = ord2f(box[a]);
-      hif[a] = ord2f(box[3 + a]);
+      lof[a] = ord2f(S.box[a]);
+      hif[a] = ord2f(S.box[3 + a]);
     }
     const float ext = fmaxf(fmaxf(hif[0] - lof[0], hif[1] - lof[1]), hif[2] - lof[2]);
     const float sc = ext > 0.f ? 1023.0f / ext : 0.f;
@@ -657,41 +734,11 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
     const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
     int* out = nbr + row * k_out;
     WaveBest<K> best;
-    best.init();
 
-    // rows of the cells listed in s_start / s_pref (ncell cells), 64 per
-    // step: f(j) for lane's row j (j = -1: no row)
-    auto for_rows = [&](int ncell, auto&& f) {
-      const int total = s_pref[ncell];
-      for (int t0 = 0; t0 < total; t0 += 64) {
-        const int t = t0 + lane;
-        int j = -1;
-        if (t < total) {
-          int lo = 0, hi = ncell - 1;  // last cell with s_pref <= t
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
-          }
-          j = s_start[lo] + (t - s_pref[lo]);
-        }
-        f(j);
-      }
-    };
-    // lanes holding a candidate (pass) insert it, one after another
-    auto insert_passing = [&](bool pass, double dme, int lme) {
-      unsigned long long m = __ballot(pass);
-      while (m) {
-        const int src = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const int dlo = __shfl(__double2loint(dme), src, 64);
-        const int dhi = __shfl(__double2hiint(dme), src, 64);
-        const int ls = __shfl(lme, src, 64);
-        best.insert(__hiloint2double(dhi, dlo), ls);
-      }
-    };
-    // the non-empty cells (lane's range [a, b)) into s_start / s_pref;
-    // returns their number
-    auto list_cells = [&](int a, int b) {
+    // appends the lanes' non-empty ranges [a, b) to the cell list (ncell
+    // cells so far, prefix sums of their rows in s_pref)
+    int ncell = 0;
+    auto add_cells = [&](int a, int b) {
       const bool has = b > a;
       const unsigned long long hm = __ballot(has);
       const int rank = __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
@@ -702,33 +749,108 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         const int y = __shfl_up(incl, d, 64);
         if (lane >= d) incl += y;
       }
+      const int base = s_pref[ncell];
       if (has) {
-        s_start[rank] = a;
-        s_pref[rank] = incl - cnt;
+        s_start[ncell + rank] = a;
+        s_pref[ncell + rank] = base + incl - cnt;
       }
-      const int ncell = __popcll(hm);
-      if (lane == 63) s_pref[ncell] = incl;
+      const int added = __popcll(hm);
       __syncthreads();
-      return ncell;
+      if (lane == 63) s_pref[ncell + added] = base + incl;
+      ncell += added;
+      __syncthreads();
+    };
+    // f(j) for the lanes' rows j of the listed cells, 64 per step (j = -1:
+    // no row)
+    // f(j, c) for the lanes' rows j (centre c) of the listed cells, 256 per
+    // step, four per lane with their loads issued together (j = -1: no row)
+    auto for_rows = [&](auto&& f) {
+      const int total = s_pref[ncell];
+      for (int t0 = 0; t0 < total; t0 += 256) {
+        int jj[4];
+        float4 cc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + 64 * u + lane;
+          jj[u] = -1;
+          if (t < total) {
+            int lo = 0, hi = ncell - 1;  // last cell with s_pref <= t
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            jj[u] = s_start[lo] + (t - s_pref[lo]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cc[u] = jj[u] >= 0 ? cen[jj[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f(jj[u], cc[u]);
+      }
+    };
+    // exact k best among the listed cells' rows: a histogram of the float
+    // distances (32 quarter-octave bins from 2^base) gives tau, then the rows
+    // within tau (widened for rounding) are inserted one after another
+    auto search = [&](int base) {
+      best.init();
+      if (lane < 32) s_hist[lane] = 0;
+      __syncthreads();
+      for_rows([&](int j, const float4& cj) {
+        if (j >= 0 && j != p) {
+          const float d2 = d2_screen(qxf, qyf, qzf, cj);
+          int bin = (int)(__float_as_uint(d2) >> 21) - base;
+          bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
+          atomicAdd(&s_hist[bin], 1);
+        }
+      });
+      __syncthreads();
+      int cum = lane < 32 ? s_hist[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        const int y = __shfl_up(cum, d, 64);
+        if (lane >= d) cum += y;
+      }
+      const unsigned long long reach = __ballot(lane < 32 && cum >= keff);
+      const int bstar = reach ? __ffsll((long long)reach) - 1 : -1;
+      float tau = INFINITY;
+      if (bstar >= 0 && bstar < 31 && base + bstar + 1 < 1020)
+        tau = __uint_as_float((unsigned)(base + bstar + 1) << 21);
+      const float adm = tau * kScreen;
+      for_rows([&](int j, const float4& c) {
+        bool pass = false;
+        double dme = 0.0;
+        int lme = 0;
+        if (j >= 0 && j != p) {
+          if (d2_screen(qxf, qyf, qzf, c) <= adm) {
+            pass = true;
+            dme = dist2(qx, qy, qz, c.x, c.y, c.z);
+            lme = __float_as_int(c.w);
+          }
+        }
+        unsigned long long m = __ballot(pass);
+        while (m) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int dlo = __shfl(__double2loint(dme), src, 64);
+          const int dhi = __shfl(__double2hiint(dme), src, 64);
+          const int ls = __shfl(lme, src, 64);
+          best.insert(__hiloint2double(dhi, dlo), ls);
+        }
+      });
+      __syncthreads();
+    };
+    auto bin_base = [](double len2) {
+      const int b = (int)(__float_as_uint((float)len2) >> 21);
+      return b > 0 ? b : 0;
     };
 
-    int L = ent.y;
-    int R0 = 2;
-    if (L > 0) {
-      // the exact k best of the 3x3x3 block, as written by the block search
-      if (lane < keff) {
-        const int e = out[lane];
-        const float4 c = cen[inv ? e : l2p[e]];
-        best.d = dist2(qx, qy, qz, c.x, c.y, c.z);
-        best.l = __float_as_int(c.w);
-      }
-    } else {
-      // block search as in the lane kernel, the lanes sharing the rows: the
-      // finest level whose 3x3x3 block holds bmin rows, a histogram of the
-      // float distances for tau, the rows within tau buffered, exact keys
+    double kd = INFINITY;  // an upper bound of the k-th key once known
+    bool done = false;
+    {
+      // block search: the finest level whose 3x3x3 block holds bmin rows
       int bmin = block_min > keff + 1 ? block_min : keff + 1;
       if (bmin > S.nrows) bmin = S.nrows;
-      int a = 0, b = 0;
+      int L, a = 0, b = 0;
       for (L = LT;; --L) {
         const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
         const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
@@ -747,167 +869,72 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         for (int d = 32; d > 0; d >>= 1) rows += __shfl_xor(rows, d, 64);
         if (rows >= bmin || L <= 1) break;
       }
-      const int ncell = list_cells(a, b);
-      const int sl = 10 - L;
-      const float side = sc > 0.f ? (float)(1 << sl) / sc : 0.f;
-      int base = (int)(__float_as_uint(side * side) >> 21) - 24;
-      if (base < 0) base = 0;
-      // pass A
-      if (lane < 32) s_hist[lane] = 0;
+      if (lane == 0) s_pref[0] = 0;
       __syncthreads();
-      for_rows(ncell, [&](int j) {
-        if (j >= 0 && j != p) {
-          const float d2 = d2_screen(qxf, qyf, qzf, cen[j]);
-          int bin = (int)(__float_as_uint(d2) >> 21) - base;
-          bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
-          atomicAdd(&s_hist[bin], 1);
-        }
-      });
-      __syncthreads();
-      int cum = lane < 32 ? s_hist[lane] : 0;
-#pragma unroll
-      for (int d = 1; d < 32; d <<= 1) {
-        const int y = __shfl_up(cum, d, 64);
-        if (lane >= d) cum += y;
-      }
-      const unsigned long long reach = __ballot(lane < 32 && cum >= keff);
-      const int bstar = reach ? __ffsll((long long)reach) - 1 : -1;
-      float tau = INFINITY;
-      if (bstar >= 0 && bstar < 31 && base + bstar + 1 < 1020)
-        tau = __uint_as_float((unsigned)(base + bstar + 1) << 21);
-      // pass B
-      const float adm = tau * kScreen;
-      int nb = 0;
-      for_rows(ncell, [&](int j) {
-        bool keep = false;
-        if (j >= 0 && j != p) keep = d2_screen(qxf, qyf, qzf, cen[j]) <= adm;
-        const unsigned long long m = __ballot(keep);
-        const int rank = __popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-        if (keep && nb + rank < CAPW) s_buf[nb + rank] = j;
-        nb += __popcll(m);
-      });
-      __syncthreads();
-      if (nb <= CAPW) {
-        // pass C
-        for (int i0 = 0; i0 < nb; i0 += 64) {
-          const int i = i0 + lane;
-          bool pass = false;
-          double dme = 0.0;
-          int lme = 0;
-          if (i < nb) {
-            const float4 c = cen[s_buf[i]];
-            dme = dist2(qx, qy, qz, c.x, c.y, c.z);
-            lme = __float_as_int(c.w);
-            pass = true;
-          }
-          insert_passing(pass, dme, lme);
-        }
-        // the block holds the exact list if the k-th key is closer than
-        // its faces
-        const int G = 1 << L;
-        const double sd = (double)(1 << sl) * g.inv_sc;
-        const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
-        double rho = INFINITY;
-        if (cx - 1 > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - 1) * sd + g.margin));
-        if (cx + 2 < G) rho = fmin(rho, (g.lo[0] + (cx + 2) * sd - g.margin) - qx);
-        if (cy - 1 > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - 1) * sd + g.margin));
-        if (cy + 2 < G) rho = fmin(rho, (g.lo[1] + (cy + 2) * sd - g.margin) - qy);
-        if (cz - 1 > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - 1) * sd + g.margin));
-        if (cz + 2 < G) rho = fmin(rho, (g.lo[2] + (cz + 2) * sd - g.margin) - qz);
-        const double kd = best.kth(keff);
-        if (!(sc > 0.f) || !(rho < INFINITY) || (rho > 0.0 && rho * rho * (1.0 - 1e-9) > kd))
-          R0 = -1;  // done
-      } else {
-        // too many rows within tau (crowded or tied distances): the k best
-        // by insertion from the finest level whose own cell holds K + 1 rows
-        best.init();
-        for (L = LT; L > 1; --L) {
-          const int sl2 = 10 - L;
-          const unsigned mc = (spread10(qi[0] >> sl2) << 2) | (spread10(qi[1] >> sl2) << 1) |
-                              spread10(qi[2] >> sl2);
-          const unsigned f = mc << (3 * (LT - L));
-          if (cstart[f + (1u << (3 * (LT - L)))] - cstart[f] >= K + 1) break;
-        }
-        const int sl2 = 10 - L, sub2 = 3 * (LT - L);
-        const unsigned mc = (spread10(qi[0] >> sl2) << 2) | (spread10(qi[1] >> sl2) << 1) |
-                            spread10(qi[2] >> sl2);
-        const unsigned f = mc << sub2;
-        const int ncell1 = list_cells(lane == 0 ? cstart[f] + rb : 0,
-                                      lane == 0 ? cstart[f + (1u << sub2)] + rb : 0);
-        for_rows(ncell1, [&](int j) {
-          bool pass = false;
-          float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-          const float thr = admit_bound(best.kth(keff));
-          if (j >= 0) {
-            c = cen[j];
-            pass = d2_screen(qxf, qyf, qzf, c) <= thr && j != p;
-          }
-          insert_passing(pass, pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0, __float_as_int(c.w));
-        });
-        __syncthreads();
-        R0 = 1;
-      }
+      ncell = 0;
+      add_cells(a, b);
+      const int sl = 10 - L, G = 1 << L;
+      const double sd = (double)(1 << sl) * g.inv_sc;
+      search(bin_base(sd * sd) - 24);
+      kd = best.kth(keff);
+      // exact if the k-th key is closer than the block's faces
+      const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+      double rho = INFINITY;
+      if (cx - 1 > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - 1) * sd + g.margin));
+      if (cx + 2 < G) rho = fmin(rho, (g.lo[0] + (cx + 2) * sd - g.margin) - qx);
+      if (cy - 1 > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - 1) * sd + g.margin));
+      if (cy + 2 < G) rho = fmin(rho, (g.lo[1] + (cy + 2) * sd - g.margin) - qy);
+      if (cz - 1 > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - 1) * sd + g.margin));
+      if (cz + 2 < G) rho = fmin(rho, (g.lo[2] + (cz + 2) * sd - g.margin) - qz);
+      done = !(sc > 0.f) || !(rho < INFINITY) || (rho > 0.0 && rho * rho * (1.0 - 1e-9) > kd);
     }
-
-    const int sl = 10 - L;
-    const int G = 1 << L;
-    const int sub = 3 * (LT - L);
-    const double side = (double)(1 << sl) * g.inv_sc;
-    const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
-    for (int R = R0; R > 0 && sc > 0.f; ++R) {
-      // cells of ring R, enumerated over the (2R+1)^3 cube, 64 per step
-      const int side_n = 2 * R + 1;
-      const int ncube = side_n * side_n * side_n;
+    if (!done) {
+      // ball search: every row within the bound lies in a cell of the
+      // range [q - r, q + r] (boxes widened by the margin); the range is
+      // taken at the finest level where it spans at most 8 cells per axis,
+      // and its cells whose box is beyond the bound are skipped
+      const double r = sqrt(kd) + 2.0 * g.margin;
+      const double q3[3] = {qx, qy, qz};
+      int L = LT, lo3[3], hi3[3];
+      for (;; --L) {
+        const double sd = (double)(1 << (10 - L)) * g.inv_sc;
+        const int G = 1 << L;
+        bool fits = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double f0 = floor((q3[a] - r - g.lo[a]) / sd);
+          const double f1 = floor((q3[a] + r - g.lo[a]) / sd);
+          lo3[a] = f0 < 0.0 ? 0 : (f0 > G - 1 ? G - 1 : (int)f0);
+          hi3[a] = f1 < 0.0 ? 0 : (f1 > G - 1 ? G - 1 : (int)f1);
+          fits = fits && hi3[a] - lo3[a] < 8;
+        }
+        if (fits || L <= 1) break;
+      }
+      const int sub = 3 * (LT - L);
+      const double sd = (double)(1 << (10 - L)) * g.inv_sc;
+      const int nx = hi3[0] - lo3[0] + 1, ny = hi3[1] - lo3[1] + 1;
+      const int ncube = nx * ny * (hi3[2] - lo3[2] + 1);
+      if (lane == 0) s_pref[0] = 0;
+      __syncthreads();
+      ncell = 0;
       for (int c0 = 0; c0 < ncube; c0 += 64) {
         const int ci = c0 + lane;
-        const double kd = best.kth(keff);  // wave-uniform, read before any branch
         int a = 0, b = 0;
         if (ci < ncube) {
-          const int dx = ci % side_n - R, dy = (ci / side_n) % side_n - R, dz = ci / (side_n * side_n) - R;
-          const int x = cx + dx, y = cy + dy, z = cz + dz;
-          const bool on_ring = max(max(abs(dx), abs(dy)), abs(dz)) == R;
-          if (on_ring && x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
-            const double bx0 = g.lo[0] + x * side - g.margin, bx1 = g.lo[0] + (x + 1) * side + g.margin;
-            const double by0 = g.lo[1] + y * side - g.margin, by1 = g.lo[1] + (y + 1) * side + g.margin;
-            const double bz0 = g.lo[2] + z * side - g.margin, bz1 = g.lo[2] + (z + 1) * side + g.margin;
-            const double gx = fmax(fmax(bx0 - qx, qx - bx1), 0.0);
-            const double gy = fmax(fmax(by0 - qy, qy - by1), 0.0);
-            const double gz = fmax(fmax(bz0 - qz, qz - bz1), 0.0);
-            const double bd = (gx * gx + gy * gy) + gz * gz;
-            if (!(bd > kd * (1.0 + 1e-12))) {
-              const unsigned mc = (spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                                  spread10((unsigned)z);
-              const unsigned f = mc << sub;
-              a = cstart[f] + rb;
-              b = cstart[f + (1u << sub)] + rb;
-            }
+          const int x = lo3[0] + ci % nx, y = lo3[1] + (ci / nx) % ny, z = lo3[2] + ci / (nx * ny);
+          const double gx = fmax(fmax(g.lo[0] + x * sd - g.margin - qx, qx - (g.lo[0] + (x + 1) * sd + g.margin)), 0.0);
+          const double gy = fmax(fmax(g.lo[1] + y * sd - g.margin - qy, qy - (g.lo[1] + (y + 1) * sd + g.margin)), 0.0);
+          const double gz = fmax(fmax(g.lo[2] + z * sd - g.margin - qz, qz - (g.lo[2] + (z + 1) * sd + g.margin)), 0.0);
+          if (!((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12))) {
+            const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                                spread10((unsigned)z)) << sub;
+            a = cstart[f] + rb;
+            b = cstart[f + (1u << sub)] + rb;
           }
         }
-        const int ncell = list_cells(a, b);
-        if (ncell > 0) {
-          for_rows(ncell, [&](int j) {
-            bool pass = false;
-            float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float thr = admit_bound(best.kth(keff));
-            if (j >= 0) {
-              c = cen[j];
-              pass = d2_screen(qxf, qyf, qzf, c) <= thr && j != p;
-            }
-            insert_passing(pass, pass ? dist2(qx, qy, qz, c.x, c.y, c.z) : 0.0,
-                           __float_as_int(c.w));
-          });
-        }
-        __syncthreads();
+        add_cells(a, b);
       }
-      double rho = INFINITY;
-      if (cx - R > 0) rho = fmin(rho, qx - (g.lo[0] + (cx - R) * side + g.margin));
-      if (cx + R + 1 < G) rho = fmin(rho, (g.lo[0] + (cx + R + 1) * side - g.margin) - qx);
-      if (cy - R > 0) rho = fmin(rho, qy - (g.lo[1] + (cy - R) * side + g.margin));
-      if (cy + R + 1 < G) rho = fmin(rho, (g.lo[1] + (cy + R + 1) * side - g.margin) - qy);
-      if (cz - R > 0) rho = fmin(rho, qz - (g.lo[2] + (cz - R) * side + g.margin));
-      if (cz + R + 1 < G) rho = fmin(rho, (g.lo[2] + (cz + R + 1) * side - g.margin) - qz);
-      if (!(rho < INFINITY)) break;
-      if (rho > 0.0 && rho * rho * (1.0 - 1e-9) > best.kth(keff)) break;
+      search(bin_base(kd) - 30);
     }
     // row out: lane t < keff holds entry t
     if (lane < k_out) {
@@ -961,14 +988,17 @@ int kclass_of(int keff) {
 
 long long table_entries(int LT) { return LT > 0 ? (1ll << (3 * LT)) + 1 : 0; }
 
-KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes) {
+KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* bytes) {
   Carver c(base);
   KnnMem m;
   m.hist = c.take<int>(entries + 1);
   m.table = c.take<int>(entries + 1);
   m.inv = c.take<int>(n);
   m.retry = c.take<int2>(n);
+  m.ginfo = c.take<int2>(n);
   m.counters = c.take<int>(64);
+  // last: its size depends on kmax (builds carve with kmax = 0)
+  m.gbuf = c.take<int>(n * (2 * (long long)kclass_of(kmax) + 1));
   const size_t scan = std::max(scan_temp_bytes(entries + 1), scan_temp_bytes(n));
   m.scan_temp = base ? (char*)base + c.bytes() : nullptr;
   if (bytes) *bytes = c.bytes() + scan;
@@ -977,7 +1007,7 @@ KnnMem carve_knn(void* base, long long n, long long entries, size_t* bytes) {
 
 void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
                void* mem, int* d_unsorted, hipStream_t st) {
-  KnnMem m = carve_knn(mem, n, entries, nullptr);
+  KnnMem m = carve_knn(mem, n, entries, 0, nullptr);
   fill_i32(m.hist, 0, entries + 1, st);
   k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, m.hist, d_unsorted);
   NG_LAUNCH_CHECK();
@@ -988,46 +1018,57 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
 
 template <int K>
 void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
-             const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
+             const KnnMem& m, const int* inv, int rows_logical, int* nbr, StageTimer* T,
+             hipStream_t st) {
   const Tuning& t = tuning_for(n);
-  int bs = t.knn_block;
-  while (bs > 64 && (size_t)(17 + 2 * K) * bs * sizeof(unsigned) > 65536) bs >>= 1;
-  const size_t lds = (size_t)(17 + 2 * K) * bs * sizeof(unsigned);
-  k_knn_lane<K><<<blocks_for(n, bs), bs, lds, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
-                                                    rows_logical, nbr, t.knn_block_min,
-                                                    t.knn_lane_rows, m.retry, m.counters + 1);
+  const int bs = t.knn_block;
+  int tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
+  k_knn_block<K><<<blocks_for(n, bs), bs, (size_t)16 * bs * sizeof(unsigned), st>>>(
+      cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf, m.ginfo,
+      (unsigned long long*)(m.counters + 8));
   NG_LAUNCH_CHECK();
+  if (T) T->stop(tk);
+  tk = T ? T->start(NANOGS_T_KNN_EXACT) : -1;
+  k_knn_exact<K><<<blocks_for(n, 256), 256, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
+                                                      rows_logical, nbr, m.gbuf, m.ginfo,
+                                                      m.retry, m.counters + 1);
+  NG_LAUNCH_CHECK();
+  if (T) T->stop(tk);
 }
 
 template <int K>
 void query_wave_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
-                  const KnnMem& m, const int* inv, int rows_logical, int* nbr, hipStream_t st) {
+                  const KnnMem& m, const int* inv, int rows_logical, int* nbr, StageTimer* T,
+                  hipStream_t st) {
+  const int tk = T ? T->start(NANOGS_T_KNN_WAVE) : -1;
   // the retry count stays on the device: a grid of fixed size strides over it
   const int cap = tuning_for(n).knn_wave_grid;
   unsigned g = (unsigned)(n < cap ? n : cap);
   if (g < 1) g = 1;
-  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, m.inv, rows_logical,
+  k_knn_wave<K><<<g, 64, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv, rows_logical,
                                   tuning_for(n).knn_block_min, nbr, m.retry, m.counters + 1);
   NG_LAUNCH_CHECK();
+  if (T) T->stop(tk);
 }
 
 void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
                unsigned class_mask, long long entries, void* mem, bool use_inv, int rows_logical,
-               int* nbr, hipStream_t st) {
-  KnnMem m = carve_knn(mem, n, entries, nullptr);
+               int* nbr, StageTimer* T, hipStream_t st) {
+  KnnMem m = carve_knn(mem, n, entries, k_out, nullptr);
   const int* inv = use_inv ? m.inv : nullptr;
   k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr);
   NG_LAUNCH_CHECK();
   fill_i32(m.counters + 1, 0, 1, st);
-  if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 4u) query_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 8u) query_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  fill_i32(m.counters + 8, 0, 2, st);  // screens (64-bit)
+  if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 4u) query_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 8u) query_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   // retries (unordered: each query's result does not depend on the order)
-  if (class_mask & 1u) query_wave_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 2u) query_wave_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 4u) query_wave_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
-  if (class_mask & 8u) query_wave_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, st);
+  if (class_mask & 1u) query_wave_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 2u) query_wave_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 4u) query_wave_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+  if (class_mask & 8u) query_wave_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
 }
 
 unsigned class_bit(int kclass) {
@@ -1050,7 +1091,7 @@ void launch_morton_keys(const float* pos_xyz3, const float4* cen4, int n, unsign
 
 // Plain entry: centres in caller order -> Morton-sorted copy -> one-segment
 // table -> rows by caller index.
-size_t knn_plain_bytes(long long n) {
+size_t knn_plain_bytes(long long n, int k) {
   Carver c(nullptr);
   c.take<unsigned>(64);
   c.take<unsigned>(n);
@@ -1058,7 +1099,7 @@ size_t knn_plain_bytes(long long n) {
   c.take<float4>(n);
   c.take<SegInfo>(1);
   size_t kb = 0;
-  carve_knn(nullptr, n, table_entries(table_level_max(n)), &kb);
+  carve_knn(nullptr, n, table_entries(table_level_max(n)), k, &kb);
   return c.bytes() + std::max(kb, sort_temp_bytes(n));
 }
 
@@ -1087,10 +1128,10 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   NG_HIP(hipMemcpyAsync(dseg, &h, sizeof(h), hipMemcpyHostToDevice, st));
   NG_HIP(hipMemcpyAsync(dseg->box, boxmem, 6 * sizeof(unsigned), hipMemcpyDeviceToDevice, st));
   const long long entries = table_entries(h.LT);
-  KnnMem m = carve_knn(rest, n, entries, nullptr);
+  KnnMem m = carve_knn(rest, n, entries, k, nullptr);
   fill_i32(m.counters, 0, 1, st);  // order check: sorted above by the same keys
   knn_build(cen, n, nullptr, dseg, entries, rest, m.counters, st);
-  knn_query(cen, n, k, nullptr, dseg, class_bit(h.kclass), entries, rest, false, 1, nbr, st);
+  knn_query(cen, n, k, nullptr, dseg, class_bit(h.kclass), entries, rest, false, 1, nbr, nullptr, st);
   // the host copy of h must outlive the async copy
   NG_HIP(hipStreamSynchronize(st));
 }

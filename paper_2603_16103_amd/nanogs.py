@@ -23,7 +23,7 @@ MAX_ROUNDS = 64
 PREC_FP32 = 0
 PREC_FP64 = 1
 STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "select",
-          "merge", "setup", "output")
+          "merge", "setup", "output", "knn_exact", "knn_wave")
 NTIMED = len(STAGES)
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY"}
@@ -64,6 +64,7 @@ class Stats(ctypes.Structure):
                 ("fallback_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("ld_iters_per_round", ctypes.c_int32 * MAX_ROUNDS),
                 ("knn_retry_per_round", ctypes.c_int64 * MAX_ROUNDS),
+                ("knn_screens_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("stage_ms", ctypes.c_double * NTIMED),
                 ("stage_launches", ctypes.c_int32 * NTIMED)]
 
@@ -78,6 +79,7 @@ class Stats(ctypes.Structure):
                 "fallback_per_round": list(self.fallback_per_round[:r]),
                 "ld_iters_per_round": list(self.ld_iters_per_round[:r]),
                 "knn_retry_per_round": list(self.knn_retry_per_round[:r]),
+                "knn_screens_per_round": list(self.knn_screens_per_round[:r]),
                 "stage_ms": dict(zip(STAGES, self.stage_ms)),
                 "stage_launches": dict(zip(STAGES, self.stage_launches))}
 

@@ -48,7 +48,7 @@ def _check_same(reqs, ng):
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), r.rid
 
 
-@pytest.mark.parametrize("budget_mb", [4096, 80])
+@pytest.mark.parametrize("budget_mb", [4096, 96])
 def test_served_results_equal_alone(gpu_lib, budget_mb):
     from paper_2603_16103_amd import serve
     ng = gpu_lib
@@ -60,7 +60,7 @@ def test_served_results_equal_alone(gpu_lib, budget_mb):
     log(rep)
     assert rep["requests"] == len(reqs) and rep["served"] == len(reqs)
     assert rep["latency_p99_s"] is not None
-    if budget_mb == 80:
+    if budget_mb == 96:
         assert srv.rows < sum(r.n for r in reqs)  # admission had to wait
     srv.batch.close()
     _check_same(reqs, ng)
