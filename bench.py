@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB three times (the "
+                         "reference kernel for scaling the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -112,6 +115,15 @@ def main():
     from paper_2603_16103_amd.synth import scene_plain_gpu
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nbytes, "copies": 3}), flush=True)
+        return
     ng.load()
     eprint("generating scene", args.n)
     sc, k, target = scene_plain_gpu(args.n)

@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+``python -m paper_2603_16103_amd.profsum stats KERNEL_STATS_CSV OUT_MD TITLE CMD``
+writes a markdown table of a ``--kernel-trace --stats`` run.
+
+``python -m paper_2603_16103_amd.profsum traffic OUT_JSON OUT_MD CMD
+FETCH_CSV WRITE_CSV CALIB_FETCH_CSV CALIB_WRITE_CSV CALIB_BYTES KERNEL[=SOURCE] ...``
+turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the benchmark
+and the same two counters on a plain copy of CALIB_BYTES into HBM bytes per
+launch of each named kernel: each counter (KiB per dispatch) is scaled by the
+ratio of the copy's known bytes to what that counter read for the copy.  The
+JSON records the hash of each kernel's source file, so a reader can tell when
+the kernel changed after the counters were taken.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def short(name: str) -> str:
+    m = re.search(r"(k_\w+|__amd\w+)(<\d+>)?", name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
+    m = re.search(r"(\w*[Cc]opy\w*)", name)
+    return m.group(1) if m else name[:48]
+
+
+def src_hash(fname: str) -> str:
+    with open(os.path.join(HERE, "csrc", fname), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def stats(csv_path, out_md, title, cmd):
+    rows = list(csv.DictReader(open(csv_path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    with open(out_md, "w") as f:
+        f.write(f"# rocprofv3 kernel statistics: {title}\n\n")
+        f.write("Command (from the repository root on one MI355X):\n\n```\n" + cmd + "\n```\n\n")
+        f.write("| kernel | calls | total ms | avg us | min us | max us | % |\n")
+        f.write("|---|---|---|---|---|---|---|\n")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            f.write(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} "
+                    f"| {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} "
+                    f"| {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+        f.write(f"\nTotal kernel time {tot / 1e6:.2f} ms.\n")
+
+
+def per_kernel(csv_path, counter):
+    """kernel -> list of per-dispatch counter values (KiB)."""
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter:
+            vals[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(out_json, out_md, cmd, fetch_csv, write_csv, cfetch_csv, cwrite_csv, calib_bytes,
+            kernels):
+    calib_bytes = float(calib_bytes)
+    cf = per_kernel(cfetch_csv, "FETCH_SIZE")
+    cw = per_kernel(cwrite_csv, "WRITE_SIZE")
+    # the copy kernel: the dispatch class with the largest counts
+    copy_f = max(cf.items(), key=lambda kv: max(kv[1]))
+    copy_w = max(cw.items(), key=lambda kv: max(kv[1]))
+    sf = calib_bytes / (max(copy_f[1]) * 1024.0)
+    sw = calib_bytes / (max(copy_w[1]) * 1024.0)
+    fe = per_kernel(fetch_csv, "FETCH_SIZE")
+    wr = per_kernel(write_csv, "WRITE_SIZE")
+    out = {"copy_kernel": copy_f[0], "calib_bytes": calib_bytes,
+           "fetch_scale": sf, "write_scale": sw, "kernels": {}}
+    for spec in kernels:
+        name, _, src = spec.partition("=")
+        f = fe.get(name, [])
+        w = wr.get(name, [])
+        if not f or not w:
+            continue
+        fk = sum(f) / len(f)
+        wk = sum(w) / len(w)
+        out["kernels"][name] = {"launches": len(f), "fetch_kib_avg": fk, "write_kib_avg": wk,
+                                "bytes_per_launch": fk * 1024.0 * sf + wk * 1024.0 * sw,
+                                "source": src or None,
+                                "source_sha": src_hash(src) if src else None}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(out_md, "w") as fh:
+        fh.write("# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n\n")
+        fh.write("Commands (from the repository root on one MI355X):\n\n```\n" + cmd + "\n```\n\n")
+        fh.write(f"Calibration: `{copy_f[0]}` copying {calib_bytes / 2**20:.0f} MiB reads "
+                 f"{max(copy_f[1]):.0f} KiB (FETCH_SIZE) and writes {max(copy_w[1]):.0f} KiB "
+                 f"(WRITE_SIZE) per dispatch; scale factors {sf:.4f} (fetch), {sw:.4f} (write).\n\n")
+        fh.write("| kernel | launches | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (scaled) |\n")
+        fh.write("|---|---|---|---|---|\n")
+        for name, e in out["kernels"].items():
+            fh.write(f"| {name} | {e['launches']} | {e['fetch_kib_avg']:.0f} | {e['write_kib_avg']:.0f} "
+                     f"| {e['bytes_per_launch']:.4g} |\n")
+
+
+def main(argv):
+    if argv[0] == "stats":
+        stats(*argv[1:5])
+    elif argv[0] == "traffic":
+        traffic(*argv[1:9], argv[9:])
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
