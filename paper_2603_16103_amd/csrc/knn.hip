@@ -703,7 +703,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
            const int* __restrict__ inv, int rows_logical, int block_min,
            int* __restrict__ nbr, const int2* __restrict__ list,
            const int* __restrict__ d_count) {
-  constexpr int MAXC = 512;  // cells one search may list
+  constexpr int MAXC = 1024;  // cells one search may list
+  constexpr int kRefine = 64;  // rows above which a listed cell is split
   __shared__ int s_start[MAXC];
   __shared__ int s_pref[MAXC + 1];
   __shared__ int s_hist[32];
@@ -917,11 +918,16 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       if (lane == 0) s_pref[0] = 0;
       __syncthreads();
       ncell = 0;
+      // a cell of more than kRefine rows (and above LT) is replaced by its
+      // eight children whose boxes meet the ball, while the list has room
+      const double sdc = sd * 0.5;
       for (int c0 = 0; c0 < ncube; c0 += 64) {
         const int ci = c0 + lane;
-        int a = 0, b = 0;
+        int a = 0, b = 0, x = 0, y = 0, z = 0;
         if (ci < ncube) {
-          const int x = lo3[0] + ci % nx, y = lo3[1] + (ci / nx) % ny, z = lo3[2] + ci / (nx * ny);
+          x = lo3[0] + ci % nx;
+          y = lo3[1] + (ci / nx) % ny;
+          z = lo3[2] + ci / (nx * ny);
           const double gx = fmax(fmax(g.lo[0] + x * sd - g.margin - qx, qx - (g.lo[0] + (x + 1) * sd + g.margin)), 0.0);
           const double gy = fmax(fmax(g.lo[1] + y * sd - g.margin - qy, qy - (g.lo[1] + (y + 1) * sd + g.margin)), 0.0);
           const double gz = fmax(fmax(g.lo[2] + z * sd - g.margin - qz, qz - (g.lo[2] + (z + 1) * sd + g.margin)), 0.0);
@@ -932,7 +938,32 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
             b = cstart[f + (1u << sub)] + rb;
           }
         }
-        add_cells(a, b);
+        const bool heavy = L < LT && b - a > kRefine;
+        const unsigned long long hm = __ballot(heavy);
+        // room: this step's cells and children plus every cell still to come
+        const int later = ncube - c0 - 64 > 0 ? ncube - c0 - 64 : 0;
+        const bool refine = hm && ncell + 64 + 7 * __popcll(hm) + later <= MAXC;
+        add_cells(refine && heavy ? 0 : a, refine && heavy ? 0 : b);
+        if (refine) {
+          const int subc = sub - 3;
+#pragma unroll 1
+          for (int ch = 0; ch < 8; ++ch) {
+            int ca = 0, cb = 0;
+            if (heavy) {
+              const int xc = 2 * x + (ch >> 2 & 1), yc = 2 * y + (ch >> 1 & 1), zc = 2 * z + (ch & 1);
+              const double gx = fmax(fmax(g.lo[0] + xc * sdc - g.margin - qx, qx - (g.lo[0] + (xc + 1) * sdc + g.margin)), 0.0);
+              const double gy = fmax(fmax(g.lo[1] + yc * sdc - g.margin - qy, qy - (g.lo[1] + (yc + 1) * sdc + g.margin)), 0.0);
+              const double gz = fmax(fmax(g.lo[2] + zc * sdc - g.margin - qz, qz - (g.lo[2] + (zc + 1) * sdc + g.margin)), 0.0);
+              if (!((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12))) {
+                const unsigned f = ((spread10((unsigned)xc) << 2) | (spread10((unsigned)yc) << 1) |
+                                    spread10((unsigned)zc)) << subc;
+                ca = cstart[f] + rb;
+                cb = cstart[f + (1u << subc)] + rb;
+              }
+            }
+            add_cells(ca, cb);
+          }
+        }
       }
       search(bin_base(kd) - 30);
     }
