@@ -288,6 +288,19 @@ constexpr unsigned long long kBlkX = pack_blk_axis(0), kBlkY = pack_blk_axis(1),
                              kBlkZ = pack_blk_axis(2);
 NG_DEV int blk(unsigned long long packed, int c) { return (int)((packed >> (2 * c)) & 3ull) - 1; }
 
+// Dilated coordinates (spread10 form, bit i at bit 3i): the neighbours' codes
+// follow from the centre's by dilated increment and decrement, without
+// re-spreading every neighbour.
+constexpr unsigned kDil = 0x09249249u;
+struct Dil3 {
+  unsigned m, c, p;  // spread10(v - 1), spread10(v), spread10(v + 1)
+};
+NG_DEV Dil3 dil3(unsigned v) {
+  const unsigned d = spread10(v);
+  return {(d - 1u) & kDil, d, ((d | ~kDil) + 1u) & kDil};
+}
+NG_DEV unsigned dil_pick(const Dil3& d, int off) { return off < 0 ? d.m : (off > 0 ? d.p : d.c); }
+
 constexpr int kExtCells = 64;   // cells of the k-th ball's range a lane may screen itself
 // float screen: a point whose exact d2 is <= B has float d2 <= B * kScreen
 // (the float evaluation rounds at most five times, about 3e-7 relative)
@@ -354,14 +367,16 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   for (;; --L) {
     const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
     const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
+    const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
     rows = 0;
     mask = 0u;
 #pragma unroll
     for (int c = 0; c < 27; ++c) {
-      const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
+      const int ox = blk(kBlkX, c), oy = blk(kBlkY, c), oz = blk(kBlkZ, c);
+      const int x = cx + ox, y = cy + oy, z = cz + oz;
       if (x < 0 || x >= G || y < 0 || y >= G || z < 0 || z >= G) continue;
-      const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                          spread10((unsigned)z)) << sub;
+      const unsigned f = ((dil_pick(dx, ox) << 2) | (dil_pick(dy, oy) << 1) | dil_pick(dz, oz))
+                         << sub;
       const int cnt = cstart[f + (1u << sub)] - cstart[f];
       rows += cnt;
       if (cnt > 0) mask |= 1u << c;
@@ -379,20 +394,29 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   const float marg = 1e-5f * q.ext;
   int base = (int)(__float_as_uint(side * side) >> 21) - 24;
   if (base < 0) base = 0;
-
-  // float distance from the query to the box of block cell c (widened by
-  // the quantisation margin)
+  const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
+  // squared float gap from the query to the slabs of the three cell columns
+  // around it on each axis (boxes widened by the quantisation margin)
+  auto gaps = [&](int a, int cc, float qa, float* g2) {
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+      const float lo = q.lof[a] + (cc + o) * side - marg, hi = q.lof[a] + (cc + o + 1) * side + marg;
+      const float gg = fmaxf(fmaxf(lo - qa, qa - hi), 0.f);
+      g2[o + 1] = gg * gg;
+    }
+  };
+  float gx2[3], gy2[3], gz2[3];
+  gaps(0, cx, qxf, gx2);
+  gaps(1, cy, qyf, gy2);
+  gaps(2, cz, qzf, gz2);
+  auto pick3 = [](const float* v, int off) { return off < 0 ? v[0] : (off > 0 ? v[2] : v[1]); };
+  // float distance from the query to the box of block cell c
   auto box_d2 = [&](int c) {
-    const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
-    const float gx = fmaxf(fmaxf(q.lof[0] + x * side - marg - qxf, qxf - (q.lof[0] + (x + 1) * side + marg)), 0.f);
-    const float gy = fmaxf(fmaxf(q.lof[1] + y * side - marg - qyf, qyf - (q.lof[1] + (y + 1) * side + marg)), 0.f);
-    const float gz = fmaxf(fmaxf(q.lof[2] + z * side - marg - qzf, qzf - (q.lof[2] + (z + 1) * side + marg)), 0.f);
-    return fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+    return pick3(gx2, blk(kBlkX, c)) + pick3(gy2, blk(kBlkY, c)) + pick3(gz2, blk(kBlkZ, c));
   };
   auto range = [&](int c, int& a, int& b) {
-    const int x = cx + blk(kBlkX, c), y = cy + blk(kBlkY, c), z = cz + blk(kBlkZ, c);
-    const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                        spread10((unsigned)z)) << sub;
+    const unsigned f = ((dil_pick(dx, blk(kBlkX, c)) << 2) | (dil_pick(dy, blk(kBlkY, c)) << 1) |
+                        dil_pick(dz, blk(kBlkZ, c))) << sub;
     a = cstart[f] + rb;
     b = cstart[f + (1u << sub)] + rb;
   };
