@@ -71,12 +71,27 @@ k_edge_emit(const int* __restrict__ nbr, int n, int k, const unsigned char* __re
             const int* __restrict__ eoff, int* __restrict__ src, int* __restrict__ tgt,
             int* __restrict__ indeg, int* __restrict__ islot) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= (long long)n * k || !flag[s]) return;
+  const bool in = s < (long long)n * k;
+  const bool emit = in && flag[s];
+  int rank = 0;  // emitting slots before this one in its row
+  if (64 % k == 0) {
+    // a row's slots are k consecutive lanes of one wave (the grid is a
+    // multiple of 64 and k divides 64): the rank is a ballot
+    const unsigned long long m = __ballot(emit);
+    const int lane = lane_id();
+    const int first = lane - (int)(s % k);  // lane of the row's first slot
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const unsigned long long row = first == 0 ? ~0ull : ~(~0ull >> (64 - first));
+    rank = __popcll(m & below & row);
+  }
+  if (!emit) return;
   const int p = (int)(s / k);
   const int t = (int)(s - (long long)p * k);
-  const unsigned char* f = flag + (long long)p * k;
-  int o = eoff[p];
-  for (int u = 0; u < t; ++u) o += f[u];
+  if (64 % k != 0) {
+    const unsigned char* f = flag + (long long)p * k;
+    for (int u = 0; u < t; ++u) rank += f[u];
+  }
+  const int o = eoff[p] + rank;
   const int j = nbr[s];
   src[o] = p;
   tgt[o] = j;

@@ -159,7 +159,7 @@ bool Engine::setup_job(Job& j, int pos) {
   launch_morton_keys(j.spec.in.pos, nullptr, (int)n, W.keys, box, st_);
   k_iota_e<<<blocks_for(n, 256), 256, 0, st_>>>(W.perm, (int)n);
   NG_LAUNCH_CHECK();
-  sort_pairs_u32(W.keys, W.perm, n, 30, W.temp, st_);
+  sort_pairs_u32(W.keys, W.perm, n, kSortKeyBits, W.temp, st_);
   fill_i32(W.counters, 0, 1, st_);
   const long long r0 = Ntot_;
   launch_activate_stored(j.spec.in.pos, j.spec.in.log_scale, j.spec.in.rot, j.spec.in.opacity,

@@ -89,6 +89,11 @@ NG_DEV unsigned spread10(unsigned v) {
 // 30-bit Morton key of a point on the 1024^3 grid over the bounding cube
 // whose per-axis bounds box[0..2] (min) and box[3..5] (max) are stored as
 // f2ord values.  Points outside the box clamp to its faces.
+// Rows only need to be ordered by their cell at the finest table level
+// (at most 8): the sort key is the level-8 cell, the top 24 bits of the key.
+constexpr int kSortKeyBits = 24;
+constexpr int kSortKeyShift = 30 - kSortKeyBits;
+
 NG_DEV unsigned morton_key(float x, float y, float z, const unsigned* box) {
   float lo[3], hi[3];
 #pragma unroll

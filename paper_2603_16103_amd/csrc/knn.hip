@@ -1,23 +1,21 @@
 // Exact k-nearest-neighbour graph over splat centres (Sec. 3.1).
 //
-// Spatial structure: the working array is kept sorted by the 30-bit Morton
-// key of the centres (quantised on a 1024^3 grid over the bounding cube), so
-// every octree cell is a contiguous range of rows; a table of cell starts at
-// one level gives the range of any cell at that level or coarser.
+// Spatial structure: the working array is kept sorted by the level-8 cell of
+// the 30-bit Morton key of the centres (quantised on a 1024^3 grid over the
+// bounding cube), so every octree cell of level 8 or coarser is a contiguous
+// range of rows; a table of cell starts at one level gives the range of any
+// cell at that level or coarser.
 //
-// Query, in two kernels.  A query whose own finest-level cell holds at least
-// k+1 rows (dense surroundings) is served by one lane: it scans that cell,
-// then rings of neighbouring cells, skipping cells beyond the current k-th
-// distance, and stops when the k-th distance is inside the searched block
-// (cells are disjoint, so every unseen row is farther).  The other queries
-// are served by a whole wave each, at a coarser level: the lanes share the
-// cells and rows and hold the k best one entry per lane, so a query near a
-// dense surface costs its rows / 64 steps instead of stalling 63 idle lanes.
-// Candidates are screened in float against a bound derived from the current
-// k-th key (never rejecting a point that the exact key would keep); survivors
-// get the exact key (d2, logical index) with d2 = ((dx*dx + dy*dy) + dz*dz)
-// in double without contraction.  The result is the exact kNN with ties
-// broken by index.
+// Query, in three kernels.  The block gather (one lane per query) screens the
+// rows of the 3x3x3 block of cells around the query at a level chosen by the
+// block's row count, plus the cells of the k-th ball outside the block, and
+// buffers every row that may enter the list.  The exact pass gives the
+// buffered rows the exact key and keeps the k best.  Queries the gather gives
+// up on (heavy blocks, wide balls, full buffers) are finished one wave each.
+// Candidates are screened in float against bounds widened for rounding (never
+// rejecting a point the exact key would keep); survivors get the exact key
+// (d2, logical index) with d2 = ((dx*dx + dy*dy) + dz*dz) in double without
+// contraction.  The result is the exact kNN with ties broken by index.
 #include <algorithm>
 #include <cstring>
 #include <climits>
@@ -96,7 +94,7 @@ __global__ void k_morton(const float* __restrict__ xyz3, const float4* __restric
     v[1] = xyz3[3 * (long long)i + 1];
     v[2] = xyz3[3 * (long long)i + 2];
   }
-  keys[i] = morton_key(v[0], v[1], v[2], box);
+  keys[i] = morton_key(v[0], v[1], v[2], box) >> kSortKeyShift;
 }
 
 __global__ void k_iota(int* v, int n) {
@@ -105,15 +103,15 @@ __global__ void k_iota(int* v, int n) {
 }
 
 // ---- cell table ------------------------------------------------------------
-// The working array is sorted by the 30-bit Morton key of the centres, so
-// every octree cell (a Morton prefix of 3L bits at level L) is a contiguous
-// range of rows.  The table holds, for every cell c of level LT, the first row
+// The working array is sorted by level-8 cell of the 30-bit Morton key of the
+// centres, so every octree cell of level L <= 8 (a Morton prefix of 3L bits)
+// is a contiguous range of rows.  The table holds, for every cell c of level LT, the first row
 // whose level-LT cell is >= c (cstart[ncells] = n); a cell of a coarser level
 // L is the range [cstart[c << 3(LT-L)], cstart[(c+1) << 3(LT-L)]).
 
 // hist[toff + c] = rows of segment sid in its level-LT cell c, from the run
 // boundaries of the sorted keys (each run adds its end and subtracts its
-// start); flags a key that is smaller than its predecessor in the segment.
+// start); flags a row whose cell is smaller than its predecessor's.
 // Segments without a table (LT = 0) are skipped.
 __global__ void k_cell_runs(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
                             const SegInfo* __restrict__ seg, int* __restrict__ hist,
@@ -137,7 +135,7 @@ __global__ void k_cell_runs(const float4* __restrict__ cen, int n, const int* __
     const float4 b = cen[i + 1];
     next_cell = morton_key(b.x, b.y, b.z, S.box) >> shift;
   }
-  if (!first && prev_key > key) atomicOr(unsorted, 1);
+  if (!first && (prev_key >> shift) > cell) atomicOr(unsorted, 1);  // rows ordered by cell
   if (first || (prev_key >> shift) != cell) atomicAdd(&hist[S.toff + cell], -(i - S.row0));
   if (last || next_cell != cell) atomicAdd(&hist[S.toff + cell], i - S.row0 + 1);
 }
@@ -1169,7 +1167,7 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   launch_morton_keys(mu, nullptr, n, keys, boxmem, st);
   k_iota<<<blocks_for(n, 256), 256, 0, st>>>(perm, n);
   NG_LAUNCH_CHECK();
-  sort_pairs_u32(keys, perm, n, 30, rest, st);
+  sort_pairs_u32(keys, perm, n, kSortKeyBits, rest, st);
   k_gather_cen<<<blocks_for(n, 256), 256, 0, st>>>(mu, perm, n, cen);
   NG_LAUNCH_CHECK();
   SegInfo h;

@@ -204,7 +204,7 @@ __global__ void k_out_keys(const float4* __restrict__ cen, const float4* __restr
     y = merged_coord(pa, pb, ca.y, cb.y);
     z = merged_coord(pa, pb, ca.z, cb.z);
   }
-  keys[q] = morton_key(x, y, z, box);
+  keys[q] = morton_key(x, y, z, box) >> kSortKeyShift;
 }
 
 // segment of each row in the Morton-sorted order (key of the stable second
@@ -344,7 +344,7 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   if (seg && nout > 0) {
     // Morton order of the output centres within each segment (stable:
     // equal keys keep the compacted order), then grouped by segment
-    sort_pairs_u32(keys, order, nout, 30, stemp, st);
+    sort_pairs_u32(keys, order, nout, kSortKeyBits, stemp, st);
     if (nseg > 1) {
       k_order_seg<<<blocks_for(nout, 256), 256, 0, st>>>(order, sg, (int)nout, keys);
       NG_LAUNCH_CHECK();
