@@ -407,7 +407,9 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   int it = 0;
   // Iterations run without a host round trip; the host reads the active
   // count every `batch` iterations (an empty iteration is two tiny launches).
-  const int batch = tuning_for(n).select_check;
+  // After the first read the active set is small and an iteration costs
+  // about two kernel launches, so later batches are twice as long.
+  int batch = tuning_for(n).select_check;
   while (true) {
     for (int b = 0; b < batch; ++b, ++it) {
       const int* in_list = it == 0 ? nullptr : act[(it + 1) & 1];
@@ -430,6 +432,7 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
     const int* hc = (const int*)host;
     known = hc[(it + 1) & 1];  // count produced by the last iteration
     if (known == 0) break;
+    if (batch < 16) batch *= 2;
   }
   r.iters = it;
   const long long M = ((const int*)host)[2];
