@@ -9,7 +9,7 @@ live scenes) and runs it to completion; the plain run calls
 ``nanogs_simplify`` per scene.  Each scene's batched output is checked
 bitwise against its plain output.
 
-``python -m paper_2603_16103_amd.batchbench [--scenes 64] [--hi 2e6]`` prints
+``python benchmarks/batched.py [--scenes 64] [--hi 2e6]`` prints
 one JSON line.
 """
 from __future__ import annotations

@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-``python -m paper_2603_16103_amd.profsum stats KERNEL_STATS_CSV OUT_MD TITLE CMD``
+``python benchmarks/profsum.py stats KERNEL_STATS_CSV OUT_MD TITLE CMD``
 writes a markdown table of a ``--kernel-trace --stats`` run.
 
-``python -m paper_2603_16103_amd.profsum traffic OUT_JSON OUT_MD CMD
+``python benchmarks/profsum.py traffic OUT_JSON OUT_MD CMD
 FETCH_CSV WRITE_CSV CALIB_FETCH_CSV CALIB_WRITE_CSV CALIB_BYTES KERNEL[=SOURCE] ...``
 turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the benchmark
 and the same two counters on a plain copy of CALIB_BYTES into HBM bytes per
@@ -22,7 +22,7 @@ import re
 import sys
 from collections import defaultdict
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2603_16103_amd")
 
 
 def short(name: str) -> str:

@@ -22,7 +22,8 @@
  *  - Workspace: each call that needs scratch takes (ws, ws_bytes); the size
  *    comes from the matching *_workspace_bytes query.  A smaller workspace
  *    gives NANOGS_EWORKSPACE.  Workspace contents are not preserved.
- *  - Index limits: n * k < 2^31.
+ *  - Index limits: n * k < 2^31; the whole loop and the batch (which keep
+ *    two adjacency entries per edge) need 2 * n * k < 2^31.
  */
 #ifndef NANOGS_H
 #define NANOGS_H
@@ -156,7 +157,7 @@ size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k,
  * clipped to [0,1].  Output order: splats keep the relative order of the
  * lowest input index they absorbed.  target_n >= n (or n <= 1) copies the
  * input through activation and back.  opt and stats are nullable (host).
- * Errors: EINVAL (n < 1, target_n < 1, k < 1 or > NANOGS_MAX_K, n*k too
+ * Errors: EINVAL (n < 1, target_n < 1, k < 1 or > NANOGS_MAX_K, 2*n*k too
  * large, bad options), EWORKSPACE, ENONFINITE (checked before any merge),
  * EHIP.  Synchronises `stream`. */
 nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n,
@@ -208,12 +209,12 @@ nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k,
 /* cost[e] = D_geo + D_app of edge (ei[e], ej[e]) over the activated splats:
  * D_geo is the Monte Carlo KL estimate of Appendix A with the S shared draws
  * crn (HOST [S][4], see nanogs_crn): the draw picks splat ei[e] when
- * u < pi = w_i / (w_i + w_j), the weight taken in float as
- * ((alpha*s0)*s1)*s2, and samples x = mu_c + chol(Sigma_c) z; D_app =
+ * u < pi = w_i / (w_i + w_j) (Eq. norm_mixture), pi taken in double from
+ * the float alpha and scales (w = ((alpha*s0)*s1)*s2; the common
+ * (2 pi)^{3/2} cancels), and samples x = mu_c + chol(Sigma_c) z; D_app =
  * ||f_i - f_j||^2 over the first opt->app_dims SH coefficients.  dgeo
  * (nullable) receives D_geo alone.  Accuracy (FP32 mode): |dC| <= 1e-4|C|
- * + 1e-5 against a float64 evaluation except where u is within float
- * rounding of pi.  opt nullable (defaults). */
+ * + 1e-5 against a float64 evaluation.  opt nullable (defaults). */
 size_t nanogs_edge_cost_workspace_bytes(int64_t n, int64_t m);
 nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n,
                                const int32_t* ei, const int32_t* ej, int64_t m,
@@ -244,8 +245,10 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej,
  * higher index is removed, survivors keep their relative order; (scale,
  * quat) of the merged covariance from its eigen-decomposition (eigenvalues
  * decreasing, signs fixed so the largest component of the first two axes is
- * positive, w >= 0).  Computed in double.  out must hold n splats and must
- * not alias in; the new count goes to device int64 *d_nout.  origin, when
+ * positive, w >= 0).  Centre, covariance, opacity and the eigen-
+ * decomposition are computed in double from the float inputs; f_m is formed
+ * in float with the mixture weights rounded to float.  out must hold n
+ * splats and must not alias in; the new count goes to device int64 *d_nout.  origin, when
  * both in and out give one, becomes the smaller origin of a pair. */
 size_t nanogs_merge_workspace_bytes(int64_t n);
 nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,

@@ -155,7 +155,7 @@ def _rank_exact(X, q, cand, keff):
 
 
 def knn(centres: np.ndarray, k: int, queries=None, chunk: int = 256,
-        method: str = "auto") -> np.ndarray:
+        method: str = "auto", workers: int = 1) -> np.ndarray:
     """Directed k nearest neighbours of each query among all centres.
 
     Key = (d2, j) with d2 = ((dx*dx + dy*dy) + dz*dz) in float64 of the
@@ -164,12 +164,15 @@ def knn(centres: np.ndarray, k: int, queries=None, chunk: int = 256,
     padded with -1 up to k columns.
 
     method "brute" is the definition itself (all N distances per query).
-    method "tree" only changes which points are ranked: a KD-tree library
-    query gives each query's distance r to its (k_eff+1)-th nearest point
-    (itself included), every point within r*(1+1e-9) is gathered, and
-    those are ranked with the same key; every true neighbour lies inside
-    that radius, so both methods return the same lists.  "auto" uses the
-    tree above 4096 points."""
+    method "tree" only changes which points are ranked.  A KD-tree library
+    query fetches each query's k_eff + 9 nearest points (itself included);
+    those are ranked with the key.  Every point not fetched lies at least
+    the last fetched library distance away, so the ranking is complete when
+    the k_eff-th key is clearly below that distance.  Rows where it is not
+    (many equal distances) gather every point within the (k_eff+1)-th
+    library distance times (1 + 1e-9) and rank those instead.  Both methods
+    return the same lists.  "auto" uses the tree above 4096 points.
+    ``workers``: threads of the library query."""
     X = np.asarray(centres, dtype=np.float64)
     n = X.shape[0]
     keff = min(max(1, k), n - 1)
@@ -182,11 +185,33 @@ def knn(centres: np.ndarray, k: int, queries=None, chunk: int = 256,
     if method == "tree":
         from scipy.spatial import cKDTree
         tree = cKDTree(X)
-        dk, _ = tree.query(X[qs], k=keff + 1)
-        dk = np.atleast_2d(dk)[:, -1] if keff + 1 > 1 else np.atleast_1d(dk)
-        balls = tree.query_ball_point(X[qs], dk * (1.0 + 1e-9) + 1e-300)
-        for r, q in enumerate(qs):
-            out[r, :keff] = _rank_exact(X, q, np.asarray(balls[r], dtype=np.int64), keff)
+        kq = min(keff + 9, n)
+        redo = []
+        for c0 in range(0, qs.size, 1 << 17):
+            qq = qs[c0:c0 + (1 << 17)]
+            dist, idx = tree.query(X[qq], k=kq, workers=workers)
+            dist = dist.reshape(qq.size, kq)
+            idx = idx.reshape(qq.size, kq)
+            d = X[idx] - X[qq][:, None, :]
+            d2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+            d2 = np.where(idx == qq[:, None], np.inf, d2)
+            # key (d2, j): order by j, then stably by d2
+            o = np.argsort(idx, axis=1, kind="stable")
+            idx = np.take_along_axis(idx, o, 1)
+            d2 = np.take_along_axis(d2, o, 1)
+            o = np.argsort(d2, axis=1, kind="stable")
+            idx = np.take_along_axis(idx, o, 1)
+            kth = np.take_along_axis(d2, o, 1)[:, keff - 1]
+            out[c0:c0 + qq.size, :keff] = idx[:, :keff]
+            ok = np.full(qq.size, kq == n) | (kth * (1.0 + 1e-9) < dist[:, -1] ** 2 * (1.0 - 1e-9))
+            redo.extend((c0 + np.nonzero(~ok)[0]).tolist())
+        if redo:
+            rows = np.asarray(redo, dtype=np.int64)
+            dk, _ = tree.query(X[qs[rows]], k=keff + 1)
+            dk = np.atleast_2d(dk)[:, -1] if keff + 1 > 1 else np.atleast_1d(dk)
+            balls = tree.query_ball_point(X[qs[rows]], dk * (1.0 + 1e-9) + 1e-300)
+            for t, r in enumerate(rows):
+                out[r, :keff] = _rank_exact(X, qs[r], np.asarray(balls[t], dtype=np.int64), keff)
         return out
     for c0 in range(0, qs.size, chunk):
         qq = qs[c0:c0 + chunk]
@@ -221,53 +246,59 @@ def union_edges(nbr: np.ndarray):
 # Stage 2: merge cost (Eq. cost, Eq. Dgeo, Eq. norm_mixture, Eq. Dmerge,
 # Appendix A Monte Carlo estimator, appearance term)
 # ---------------------------------------------------------------------------
-def _log_gauss(x, mu, Sig):
-    """log N(x; mu, Sigma) without the -(3/2) log(2 pi) constant, which
-    cancels between the mixture term and the merged term."""
-    d = x - mu
-    sol = np.linalg.solve(Sig, d[..., None])[..., 0]
-    maha = np.sum(d * sol, axis=-1)
-    logdet = np.linalg.slogdet(Sig)[1]
-    return -0.5 * maha - 0.5 * logdet
+def _log_gauss_chol(x, mu, L):
+    """log N(x; mu, L L^T) without the -(3/2) log(2 pi) constant, which
+    cancels between the mixture term and the merged term:
+    -1/2 |L^-1 (x - mu)|^2 - log det L, with L^-1 applied by forward
+    substitution (L lower triangular)."""
+    y = x - mu
+    v0 = y[..., 0] / L[..., 0, 0]
+    v1 = (y[..., 1] - L[..., 1, 0] * v0) / L[..., 1, 1]
+    v2 = (y[..., 2] - L[..., 2, 0] * v0 - L[..., 2, 1] * v1) / L[..., 2, 2]
+    logdet = np.log(L[..., 0, 0]) + np.log(L[..., 1, 1]) + np.log(L[..., 2, 2])
+    return -0.5 * (v0 * v0 + v1 * v1 + v2 * v2) - logdet
 
 
-def _decision_weights(st: State, a, b):
-    """Mixture weight of the lower-index splat in single precision.
-
-    READING: the component choice u < pi is an integer decision taken from
-    floating point, so it is taken in float32 from the float32 values of
-    alpha and s, as (((alpha*s0)*s1)*s2) / (w_a + w_b) (the (2 pi)^{3/2}
-    factor cancels); pi = 1/2 when both masses are zero."""
-    f32 = np.float32
-    al = st.alpha.astype(f32)
-    s = st.s.astype(f32)
-    wt = ((al * s[:, 0]) * s[:, 1]) * s[:, 2]
-    wa, wb = wt[a], wt[b]
-    W = (wa + wb).astype(f32)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        pa = np.where(W > 0, wa / np.where(W > 0, W, f32(1)), f32(0.5)).astype(f32)
-    return pa
-
-
-def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48):
+def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48,
+               chunk: int = 1 << 18, workers: int = 1):
     """C(i,j) = D_geo + D_app for every edge (i < j).
 
     D_geo = KL(p~_ij || q_m) estimated with the S shared draws (Appendix A):
-    pick component i when u < pi (READING: pi belongs to the lower index),
+    pi = w_i / (w_i + w_j) in float64 (Eq. norm_mixture, READING: pi belongs
+    to the lower index); a draw (u, z) picks component i when u < pi, and
     x = mu_c + chol(Sigma_c) z (READING: Cholesky factor, so the sample does
-    not depend on how (s, q) factor Sigma), then
+    not depend on how (s, q) factor Sigma); then
     g = log(pi N_i(x) + (1-pi) N_j(x)) - log q_m(x), averaged over the S
-    draws.  D_app = ||f_i - f_j||^2 over the first ``app_dims`` SH
-    coefficients.  Returns (cost, d_geo, d_app) in float64."""
+    draws, with q_m = N(mu_m, Sigma_m) the moment-matched Gaussian
+    (Eq. vm_cov).  D_app = ||f_i - f_j||^2 over the first ``app_dims`` SH
+    coefficients.  Returns (cost, d_geo, d_app) in float64.
+
+    The covariance of a splat and its Cholesky factor are formed once per
+    splat; the edges are evaluated in chunks (the cost of an edge depends on
+    that edge alone).  ``workers`` is accepted for symmetry with knn and does
+    not change anything."""
     a = np.asarray(ei, dtype=np.int64)
     b = np.asarray(ej, dtype=np.int64)
     if a.size == 0:
         z = np.zeros(0)
         return z, z, z
-    Sa = covariance(st.s[a], st.q[a])
-    Sb = covariance(st.s[b], st.q[b])
-    wa = mass(st.s[a], st.alpha[a])
-    wb = mass(st.s[b], st.alpha[b])
+    used = np.unique(np.concatenate([a, b]))
+    Sig = np.zeros((st.n, 3, 3))
+    Sig[used] = covariance(st.s[used], st.q[used])
+    L = np.zeros((st.n, 3, 3))
+    L[used] = np.linalg.cholesky(Sig[used])
+    w = np.zeros(st.n)
+    w[used] = mass(st.s[used], st.alpha[used])
+    parts = [_edge_costs_block(st, Sig, L, w, a[c0:c0 + chunk], b[c0:c0 + chunk], crn, app_dims)
+             for c0 in range(0, a.size, chunk)]
+    return tuple(np.concatenate([p[t] for p in parts]) for t in range(3))
+
+
+def _edge_costs_block(st: State, Sig, L, w, a, b, crn, app_dims):
+    """Costs of the edges (a[e], b[e]); Sig, L, w: per-splat covariance,
+    its lower Cholesky factor and mass (Eq. vm_weights)."""
+    Sa, Sb = Sig[a], Sig[b]
+    wa, wb = w[a], w[b]
     W = wa + wb
     with np.errstate(divide="ignore", invalid="ignore"):
         pa = np.where(W > 0, wa / np.where(W > 0, W, 1.0), 0.5)
@@ -278,24 +309,23 @@ def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48):
     db = mub - mum
     Sm = (pa[:, None, None] * (Sa + da[:, :, None] * da[:, None, :])
           + pb[:, None, None] * (Sb + db[:, :, None] * db[:, None, :]))
-    pa32 = _decision_weights(st, a, b)
-    La = np.linalg.cholesky(Sa)
-    Lb = np.linalg.cholesky(Sb)
+    La, Lb = L[a], L[b]
+    Lm = np.linalg.cholesky(Sm)
     crn = np.asarray(crn, dtype=np.float32)
     S = crn.shape[0]
     with np.errstate(divide="ignore"):
         lpa = np.log(pa)
         lpb = np.log(pb)
-    # samples on a leading axis: arrays are [S, E, ...]
-    u = crn[:, 0][:, None]
+    # draws on a leading axis: arrays are [S, E, ...]
+    u = crn[:, 0].astype(np.float64)[:, None]
     z = crn[:, 1:4].astype(np.float64)
-    take_a = u < pa32[None, :]
+    take_a = u < pa[None, :]  # pi = w_i / W in float64 (Eq. norm_mixture)
     xa = mua[None] + np.einsum("eij,sj->sei", La, z)
     xb = mub[None] + np.einsum("eij,sj->sei", Lb, z)
     x = np.where(take_a[..., None], xa, xb)
-    lna = _log_gauss(x, mua[None], np.broadcast_to(Sa, (S,) + Sa.shape))
-    lnb = _log_gauss(x, mub[None], np.broadcast_to(Sb, (S,) + Sb.shape))
-    lnm = _log_gauss(x, mum[None], np.broadcast_to(Sm, (S,) + Sm.shape))
+    lna = _log_gauss_chol(x, mua[None], La[None])
+    lnb = _log_gauss_chol(x, mub[None], Lb[None])
+    lnm = _log_gauss_chol(x, mum[None], Lm[None])
     g_sum = np.sum(np.logaddexp(lpa[None] + lna, lpb[None] + lnb) - lnm, axis=0)
     dgeo = g_sum / S
     df = st.f[a, :app_dims] - st.f[b, :app_dims]
@@ -319,14 +349,13 @@ def greedy_pairs(ei, ej, cost, n: int, P: int):
     ok = np.isfinite(c)
     idx = np.nonzero(ok)[0]
     order = idx[np.lexsort((ej[idx], ei[idx], c[idx]))]
-    used = np.zeros(n, dtype=bool)
+    used = bytearray(n)
     out = []
     if P <= 0:
         return np.zeros((0, 2), dtype=np.int64)
-    for e in order:
-        i, j = ei[e], ej[e]
+    for i, j in zip(ei[order].tolist(), ej[order].tolist()):
         if not used[i] and not used[j]:
-            used[i] = used[j] = True
+            used[i] = used[j] = 1
             out.append((i, j))
             if len(out) >= P:
                 break
@@ -363,31 +392,29 @@ def quat_from_rotation(R: np.ndarray) -> np.ndarray:
     """Unit quaternion (w, x, y, z), w >= 0, of rotation matrices, by
     Shepperd's method (branch on the largest of trace and diagonal)."""
     R = np.asarray(R, dtype=np.float64)
-    q = np.empty(R.shape[:-2] + (4,))
     t = R[..., 0, 0] + R[..., 1, 1] + R[..., 2, 2]
     cand = np.stack([t, R[..., 0, 0], R[..., 1, 1], R[..., 2, 2]], axis=-1)
-    br = np.argmax(cand, axis=-1)
-    Rf = R.reshape(-1, 3, 3)
-    qf = q.reshape(-1, 4)
-    for n, (m, b) in enumerate(zip(Rf, br.reshape(-1))):
-        if b == 0:
-            w = 0.5 * math.sqrt(max(1.0 + m[0, 0] + m[1, 1] + m[2, 2], 0.0))
-            qf[n] = (w, (m[2, 1] - m[1, 2]) / (4 * w), (m[0, 2] - m[2, 0]) / (4 * w),
-                     (m[1, 0] - m[0, 1]) / (4 * w))
-        elif b == 1:
-            x = 0.5 * math.sqrt(max(1.0 + m[0, 0] - m[1, 1] - m[2, 2], 0.0))
-            qf[n] = ((m[2, 1] - m[1, 2]) / (4 * x), x, (m[0, 1] + m[1, 0]) / (4 * x),
-                     (m[0, 2] + m[2, 0]) / (4 * x))
-        elif b == 2:
-            y = 0.5 * math.sqrt(max(1.0 - m[0, 0] + m[1, 1] - m[2, 2], 0.0))
-            qf[n] = ((m[0, 2] - m[2, 0]) / (4 * y), (m[0, 1] + m[1, 0]) / (4 * y), y,
-                     (m[1, 2] + m[2, 1]) / (4 * y))
-        else:
-            z = 0.5 * math.sqrt(max(1.0 - m[0, 0] - m[1, 1] + m[2, 2], 0.0))
-            qf[n] = ((m[1, 0] - m[0, 1]) / (4 * z), (m[0, 2] + m[2, 0]) / (4 * z),
-                     (m[1, 2] + m[2, 1]) / (4 * z), z)
-    q = qf.reshape(q.shape)
-    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    br = np.argmax(cand, axis=-1)[..., None]
+    m = lambda i, j: R[..., i, j]  # noqa: E731
+    with np.errstate(divide="ignore", invalid="ignore"):
+        # branch 0: w largest
+        w0 = 0.5 * np.sqrt(np.maximum(1.0 + t, 0.0))
+        q0 = np.stack([w0, (m(2, 1) - m(1, 2)) / (4 * w0), (m(0, 2) - m(2, 0)) / (4 * w0),
+                       (m(1, 0) - m(0, 1)) / (4 * w0)], -1)
+        # branch 1: x largest
+        x1 = 0.5 * np.sqrt(np.maximum(1.0 + m(0, 0) - m(1, 1) - m(2, 2), 0.0))
+        q1 = np.stack([(m(2, 1) - m(1, 2)) / (4 * x1), x1, (m(0, 1) + m(1, 0)) / (4 * x1),
+                       (m(0, 2) + m(2, 0)) / (4 * x1)], -1)
+        # branch 2: y largest
+        y2 = 0.5 * np.sqrt(np.maximum(1.0 - m(0, 0) + m(1, 1) - m(2, 2), 0.0))
+        q2 = np.stack([(m(0, 2) - m(2, 0)) / (4 * y2), (m(0, 1) + m(1, 0)) / (4 * y2), y2,
+                       (m(1, 2) + m(2, 1)) / (4 * y2)], -1)
+        # branch 3: z largest
+        z3 = 0.5 * np.sqrt(np.maximum(1.0 - m(0, 0) - m(1, 1) + m(2, 2), 0.0))
+        q3 = np.stack([(m(1, 0) - m(0, 1)) / (4 * z3), (m(0, 2) + m(2, 0)) / (4 * z3),
+                       (m(1, 2) + m(2, 1)) / (4 * z3), z3], -1)
+    q = np.where(br == 0, q0, np.where(br == 1, q1, np.where(br == 2, q2, q3)))
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
     q *= np.where(q[..., :1] < 0, -1.0, 1.0)
     return q
 
@@ -456,20 +483,21 @@ def opacity_prune(st: State, tau: float) -> State:
 # ---------------------------------------------------------------------------
 def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
              seed: int = 0, S: int = 1, app_dims: int = 48, trace=None,
-             max_rounds: int = 1 << 30):
+             max_rounds: int = 1 << 30, workers: int = 1):
     """Algorithm 1 without the opacity pre-filter: while N > N_tgt, rebuild
     the kNN graph, take the union edges, cost them, pick at most
     P = N - N_tgt greedy disjoint pairs, stop if none, merge.  The shared
     draws of pass r are ``crn_block(seed, r, S)``.  Returns the final State
     (alpha clipped to [0, 1]).  When ``trace`` is a list, each pass appends
-    the provenance pairs (origin_i, origin_j) it merged."""
+    the provenance pairs (origin_i, origin_j) it merged.  ``workers``:
+    threads for the per-query and per-edge steps (results do not change)."""
     st = activate(pos, log_scale, rot, opacity, sh)
     target_n = max(int(target_n), 1)
     r = 0
     while st.n > target_n and r < max_rounds:
         n = st.n
         keff = min(max(1, k), n - 1)
-        nbr = knn(st.mu, keff)
+        nbr = knn(st.mu, keff, workers=workers)
         ei, ej = union_edges(nbr)
         cost = edge_costs(st, ei, ej, crn_block(seed, r, S), app_dims)[0]
         P = n - target_n

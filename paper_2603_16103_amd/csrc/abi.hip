@@ -117,6 +117,17 @@ nanogs_status check_n(long long n, long long k) {
   return NANOGS_OK;
 }
 
+// The round engine's adjacency holds two entries per edge (one at each end)
+// with int32 offsets, and a pass has at most n * k edges.
+nanogs_status check_engine_n(long long n, long long k) {
+  NG_CHECK(check_n(n, k));
+  if (2 * n * k >= (1ll << 31) - 1) {
+    set_error("2 * n * k must be below 2^31 (int32 adjacency offsets)");
+    return NANOGS_EINVAL;
+  }
+  return NANOGS_OK;
+}
+
 nanogs_status check_ws(void* ws, size_t have, size_t need) {
   if (need == 0) return NANOGS_OK;
   if (!ws || have < need) {
@@ -206,7 +217,7 @@ Packed take_packed(Carver& c, long long n) {
 size_t cost_bytes(long long n, long long m) {
   Carver c(nullptr);
   take_packed(c, n);
-  c.take<float4>(2 * n);
+  c.take<float4>(pre_float4s(n));
   c.take<int>(m);
   c.take<int>(64);
   c.take<float>(NG_CRN_ROW);
@@ -275,7 +286,7 @@ nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n, int64_t tar
       set_error("n_out is null");
       return NANOGS_EINVAL;
     }
-    NG_CHECK(check_n(n, k));
+    NG_CHECK(check_engine_n(n, k));
     NG_CHECK(check_gaussians(in, "in"));
     NG_CHECK(check_gaussians(out, "out"));
     if (in->pos == out->pos || in->sh == out->sh) {
@@ -393,7 +404,7 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
     NG_CHECK(check_ws(ws, ws_bytes, cost_bytes(n, m)));
     Carver c(ws);
     Packed p = take_packed(c, n);
-    float4* pre = c.take<float4>(2 * n);
+    float4* pre = c.take<float4>(pre_float4s(n));
     int* fb_list = c.take<int>(m);
     int* counters = c.take<int>(64);
     float* dcrn = c.take<float>(NG_CRN_ROW);
@@ -514,7 +525,7 @@ nanogs_status nanogs_batch_create(int64_t max_rows, int32_t max_k, int32_t max_j
       set_error("max_rows must be >= 1 and max_jobs in [1, 4096]");
       return NANOGS_EINVAL;
     }
-    NG_CHECK(check_n(max_rows, max_k));
+    NG_CHECK(check_engine_n(max_rows, max_k));
     Opts o;
     NG_CHECK(read_opts(opt, &o));
     if (o.d_trace || o.d_origin) {

@@ -126,7 +126,7 @@ NG_DEV Tri<T> chol_from_scale_rot(T s0, T s1, T s2, T w, T x, T y, T z) {
 // D_geo of one pair.  ratio receives the smallest diagonal ratio seen.
 template <typename T>
 NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const Tri<T>& Lb,
-                   T ldLa, T ldLb, T pa, T pb, float pa32, const float* __restrict__ cv, int S,
+                   T ldLa, T ldLb, T pa, T pb, double pdec, const float* __restrict__ cv, int S,
                    T& ratio) {
   const V3<T> d = {mua.x - mub.x, mua.y - mub.y, mua.z - mub.z};
   const Tri<T> LA = chol_of_mix(La, Lb, sqrt(pa), sqrt(pb));
@@ -144,7 +144,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
   for (int s = 0; s < S; ++s) {
     const float u = cv[4 * s];
     const V3<T> zz = {(T)cv[4 * s + 1], (T)cv[4 * s + 2], (T)cv[4 * s + 3]};
-    const bool ca = u < pa32;
+    const bool ca = (double)u < pdec;
     const Tri<T>& Lc = ca ? La : Lb;
     const Tri<T>& Lo = ca ? Lb : La;
     const T ldc = ca ? ldLa : ldLb;
@@ -201,16 +201,29 @@ NG_DEV double dapp_f64(const float* __restrict__ sh, long long a, long long b, i
   return acc;
 }
 
-NG_DEV float decision_weight(float wa, float wb) {
-  const float W = wa + wb;
-  return W > 0.f ? wa / W : 0.5f;
+// Mass of a splat up to the common (2 pi)^{3/2} (Eq. vm_weights), in double
+// from the float values: ((alpha s0) s1) s2.
+NG_DEV double weight_f64(float4 sa) {
+#pragma clang fp contract(off)
+  return (((double)sa.w * (double)sa.x) * (double)sa.y) * (double)sa.z;
+}
+
+// Mixture weights pi = w_a / W and 1 - pi as w_b / W in double
+// (Eq. norm_mixture); W = 0 gives 1/2 each.
+NG_DEV void mix_weights(double wa, double wb, double& pa, double& pb) {
+#pragma clang fp contract(off)
+  const double W = wa + wb;
+  pa = W > 0.0 ? wa / W : 0.5;
+  pb = W > 0.0 ? wb / W : 0.5;
 }
 
 // ---- kernels ---------------------------------------------------------------
-__global__ void k_precompute(const float4* __restrict__ shp, int n, float4* __restrict__ pre) {
+__global__ void k_precompute(const float4* __restrict__ shp, int n, float4* __restrict__ pre,
+                             double* __restrict__ wd) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float4 a = shp[2 * (long long)p];
+  wd[p] = weight_f64(a);
   const float4 q = shp[2 * (long long)p + 1];
   const Tri<double> L = chol_from_scale_rot<double>(a.x, a.y, a.z, q.x, q.y, q.z, q.w);
   const double ld = log((double)a.x) + log((double)a.y) + log((double)a.z);
@@ -251,7 +264,7 @@ NG_DEV void write_adj(const AdjOut& adj, int e, int s, int t, int ls, int lt, fl
 
 __global__ void __launch_bounds__(256)
 k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
-            const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
+            const double* __restrict__ wd, const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
             const int* __restrict__ eb, int m, int n, int orient, const float* __restrict__ crn,
             int S, const int* __restrict__ sg, const SegInfo* __restrict__ seg, float fb_ratio,
             float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
@@ -278,13 +291,13 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
     const float4 pb0 = pre[2 * (long long)b], pb1 = pre[2 * (long long)b + 1];
     const Tri<float> La = {pa0.x, pa0.y, pa0.z, pa0.w, pa1.x, pa1.y};
     const Tri<float> Lb = {pb0.x, pb0.y, pb0.z, pb0.w, pb1.x, pb1.y};
-    const float pa = decision_weight(pa1.w, pb1.w);
-    const float W = pa1.w + pb1.w;
-    const float pb = W > 0.f ? pb1.w / W : 0.5f;
+    double pad, pbd;
+    mix_weights(wd[a], wd[b], pad, pbd);
+    const float pa = (float)pad, pb = (float)pbd;
     float ratio;
     const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const float dg = dgeo_pair<float>(v3(ca.x, ca.y, ca.z), v3(cb.x, cb.y, cb.z), La, Lb, pa1.z,
-                                      pb1.z, pa, pb, pa, cv, S, ratio);
+                                      pb1.z, pa, pb, pad, cv, S, ratio);
     const float c = dg + dapp_f32(sh, a, b, app_dims);
     fb = !(ratio >= fb_ratio) || !isfinite(c);
     cost[e] = c;
@@ -321,17 +334,12 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
     const Tri<double> Lb = chol_from_scale_rot<double>(sb.x, sb.y, sb.z, qb.x, qb.y, qb.z, qb.w);
     const double lda = log((double)sa.x) + log((double)sa.y) + log((double)sa.z);
     const double ldb = log((double)sb.x) + log((double)sb.y) + log((double)sb.z);
-    const float pa32 =
-        decision_weight(((sa.w * sa.x) * sa.y) * sa.z, ((sb.w * sb.x) * sb.y) * sb.z);
-    const double wa = (double)sa.w * (double)sa.x * (double)sa.y * (double)sa.z;
-    const double wb = (double)sb.w * (double)sb.x * (double)sb.y * (double)sb.z;
-    const double W = wa + wb;
-    const double pa = W > 0.0 ? wa / W : 0.5;
-    const double pb = W > 0.0 ? wb / W : 0.5;
+    double pa, pb;
+    mix_weights(weight_f64(sa), weight_f64(sb), pa, pb);
     double ratio;
     const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const double dg = dgeo_pair<double>(v3<double>(ca.x, ca.y, ca.z), v3<double>(cb.x, cb.y, cb.z),
-                                        La, Lb, lda, ldb, pa, pb, pa32, cv, S, ratio);
+                                        La, Lb, lda, ldb, pa, pb, pa, cv, S, ratio);
     const float c = (float)(dg + dapp_f64(sh, a, b, app_dims));
     cost[e] = c;
     if (dgeo_out) dgeo_out[e] = (float)dg;
@@ -343,7 +351,7 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
 
 void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st) {
   if (n <= 0) return;
-  k_precompute<<<blocks_for(n, 256), 256, 0, st>>>(shp, n, pre);
+  k_precompute<<<blocks_for(n, 256), 256, 0, st>>>(shp, n, pre, pre_weights(pre, n));
   NG_LAUNCH_CHECK();
 }
 
@@ -353,7 +361,8 @@ void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int
                       AdjOut adj, hipStream_t st) {
   if (m <= 0) return;
   const int bs = tuning_for(n).cost_block;
-  k_edge_cost<<<blocks_for(m, bs), bs, 0, st>>>(cen, pre, sh, app_dims, ea, eb, m, n,
+  k_edge_cost<<<blocks_for(m, bs), bs, 0, st>>>(cen, pre, pre_weights((float4*)pre, n), sh,
+                                                  app_dims, ea, eb, m, n,
                                                   orient ? 1 : 0, crn.tab, crn.S, crn.sg, crn.seg,
                                                   fb_ratio, cost, dgeo, fb_list, fb_count, adj);
   NG_LAUNCH_CHECK();

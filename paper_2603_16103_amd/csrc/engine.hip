@@ -89,7 +89,7 @@ static EngineWs carve_engine(void* base, long long R, int K, int J) {
   EngineWs s;
   s.w[0] = take_work_e(c, R);
   s.w[1] = take_work_e(c, R);
-  s.pre = c.take<float4>(2 * R);
+  s.pre = c.take<float4>(pre_float4s(R));
   s.nbr = c.take<int>(R * K);
   s.src = c.take<int>(R * K);
   s.tgt = c.take<int>(R * K);

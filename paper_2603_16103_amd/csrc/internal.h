@@ -12,6 +12,8 @@
 // Per pass, per splat (cost kernel input):
 //   pre[2p]       float4 (L00, L10, L11, L20)     Cholesky factor of Sigma
 //   pre[2p+1]     float4 (L21, L22, log det L, w~) with w~ = ((a*s0)*s1)*s2
+//   after the 2n float4: n doubles, the same weight in double (the mixture
+//   weight pi that picks a draw's component is taken in double)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -279,6 +281,10 @@ struct AdjOut {
   unsigned long long* akey;
   int* au;
 };
+// pre holds pre_float4s(n) float4: the factors of every splat, then their
+// double weights.
+inline long long pre_float4s(long long n) { return 2 * n + (n + 1) / 2; }
+inline double* pre_weights(float4* pre, long long n) { return (double*)(pre + 2 * n); }
 void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st);
 // FP32 cost of edges [0, m); edges needing FP64 are appended to fb_list.
 // Edges with an end outside [0, n) get a NaN cost.  orient: the end with the

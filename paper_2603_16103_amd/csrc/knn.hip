@@ -310,13 +310,24 @@ NG_DEV float d2_screen(float qx, float qy, float qz, float4 c) {
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-// Query geometry shared by the block gather and the exact pass.
+// Query geometry shared by the block gather and the exact pass.  tq is the
+// query in grid units (fine cells of the quantisation, unclamped): cell
+// boxes are tested in that frame, where cell faces are exact integers and
+// the rounding of a coordinate does not grow with its distance from the
+// origin.
 struct QueryGeo {
   float qxf, qyf, qzf;
   float lof[3];
   float ext, sc;
+  float tq[3];
   unsigned qi[3];
 };
+
+// Slack of a cell face in grid units: the grid coordinate of a point is
+// within about 1e-4 grid units of its exact value (one rounding of v - lo,
+// whose magnitude is at most the extent, and one of the product with the
+// scale), for the query and for the candidate alike.
+constexpr float kGridSlack = 1.0f / 64.0f;
 
 NG_DEV QueryGeo query_geo(const float4& cq, const SegInfo& S) {
   QueryGeo q;
@@ -331,6 +342,9 @@ NG_DEV QueryGeo query_geo(const float4& cq, const SegInfo& S) {
   }
   q.ext = fmaxf(fmaxf(hif[0] - q.lof[0], hif[1] - q.lof[1]), hif[2] - q.lof[2]);
   q.sc = q.ext > 0.f ? 1023.0f / q.ext : 0.f;
+  q.tq[0] = (q.qxf - q.lof[0]) * q.sc;
+  q.tq[1] = (q.qyf - q.lof[1]) * q.sc;
+  q.tq[2] = (q.qzf - q.lof[2]) * q.sc;
   q.qi[0] = quant(q.qxf, q.lof[0], q.sc);
   q.qi[1] = quant(q.qyf, q.lof[1], q.sc);
   q.qi[2] = quant(q.qzf, q.lof[2], q.sc);
@@ -388,25 +402,27 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
 
   const int sl = 10 - L, sub = 3 * (LT - L);
   const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
-  const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;
-  const float marg = 1e-5f * q.ext;
+  const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;  // real units
+  const float side_g = (float)(1 << sl);                             // grid units
+  const float sc2 = q.sc * q.sc;  // real squared distance -> grid units
   int base = (int)(__float_as_uint(side * side) >> 21) - 24;
   if (base < 0) base = 0;
   const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
-  // squared float gap from the query to the slabs of the three cell columns
-  // around it on each axis (boxes widened by the quantisation margin)
-  auto gaps = [&](int a, int cc, float qa, float* g2) {
+  // squared gap (grid units) from the query to the slabs of the three cell
+  // columns around it on each axis (faces widened by the grid slack)
+  auto gaps = [&](int cc, float ta, float* g2) {
 #pragma unroll
     for (int o = -1; o <= 1; ++o) {
-      const float lo = q.lof[a] + (cc + o) * side - marg, hi = q.lof[a] + (cc + o + 1) * side + marg;
-      const float gg = fmaxf(fmaxf(lo - qa, qa - hi), 0.f);
+      const float lo = (float)(cc + o) * side_g - kGridSlack;
+      const float hi = (float)(cc + o + 1) * side_g + kGridSlack;
+      const float gg = fmaxf(fmaxf(lo - ta, ta - hi), 0.f);
       g2[o + 1] = gg * gg;
     }
   };
   float gx2[3], gy2[3], gz2[3];
-  gaps(0, cx, qxf, gx2);
-  gaps(1, cy, qyf, gy2);
-  gaps(2, cz, qzf, gz2);
+  gaps(cx, q.tq[0], gx2);
+  gaps(cy, q.tq[1], gy2);
+  gaps(cz, q.tq[2], gz2);
   auto pick3 = [](const float* v, int off) { return off < 0 ? v[0] : (off > 0 ? v[2] : v[1]); };
   // float distance from the query to the box of block cell c
   auto box_d2 = [&](int c) {
@@ -462,7 +478,7 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   };
   float tau = INFINITY;
   for_cells([&](int c, int a, int b, int cn) {
-    if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * kPrune)) {
+    if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * sc2 * kPrune)) {
       nscreen += b - a;
       int j = a;
       for (; j + 4 <= b; j += 4) {
@@ -490,7 +506,7 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
     nb += in ? 1 : 0;
   };
   for_cells([&](int c, int a, int b, int) {
-    if (c > 0 && box_d2(c) > tau * kPrune) return;
+    if (c > 0 && box_d2(c) > tau * sc2 * kPrune) return;
     nscreen += b - a;
     int j = a;
     for (; j + 4 <= b; j += 4) {
@@ -511,16 +527,17 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   // than kExtCells cells (then the wave search takes the query).
   if (q.sc > 0.f) {  // (a zero-extent grid has every row in the own cell)
     const int G = 1 << L;
-    const float r = sqrtf(adm) * 1.000001f + 2.f * marg;
-    const float qq[3] = {qxf, qyf, qzf};
+    // ball radius in grid units, widened by the slack of the faces and of
+    // the subtraction below
+    const float rg = sqrtf(adm) * q.sc * 1.000002f + 2.f * kGridSlack;
     const int c3[3] = {cx, cy, cz};
     int lo3[3], hi3[3];
     bool inside = true;
     int vol = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float f0 = floorf((qq[a] - r - q.lof[a]) / side);
-      const float f1 = floorf((qq[a] + r - q.lof[a]) / side);
+      const float f0 = floorf((q.tq[a] - rg) / side_g);
+      const float f1 = floorf((q.tq[a] + rg) / side_g);
       lo3[a] = f0 < 0.f ? 0 : (f0 > (float)(G - 1) ? G - 1 : (int)f0);
       hi3[a] = f1 < 0.f ? 0 : (f1 > (float)(G - 1) ? G - 1 : (int)f1);
       inside = inside && lo3[a] >= c3[a] - 1 && hi3[a] <= c3[a] + 1;
@@ -535,10 +552,12 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
       for (int i = 0; i < vol; ++i) {
         const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
         if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
-        const float gx = fmaxf(fmaxf(q.lof[0] + x * side - marg - qxf, qxf - (q.lof[0] + (x + 1) * side + marg)), 0.f);
-        const float gy = fmaxf(fmaxf(q.lof[1] + y * side - marg - qyf, qyf - (q.lof[1] + (y + 1) * side + marg)), 0.f);
-        const float gz = fmaxf(fmaxf(q.lof[2] + z * side - marg - qzf, qzf - (q.lof[2] + (z + 1) * side + marg)), 0.f);
-        if (!(fmaf(gz, gz, fmaf(gy, gy, gx * gx)) > tau * kPrune)) emask |= 1ull << i;
+        auto gap = [&](int c, float ta) {
+          return fmaxf(fmaxf((float)c * side_g - kGridSlack - ta,
+                             ta - ((float)(c + 1) * side_g + kGridSlack)), 0.f);
+        };
+        const float gx = gap(x, q.tq[0]), gy = gap(y, q.tq[1]), gz = gap(z, q.tq[2]);
+        if (!(fmaf(gz, gz, fmaf(gy, gy, gx * gx)) > tau * sc2 * kPrune)) emask |= 1ull << i;
       }
       auto erange = [&](int i, int& a, int& b) {
         const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);

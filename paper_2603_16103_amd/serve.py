@@ -79,12 +79,20 @@ class _HostScene:
                        (scene.pos, scene.log_scale, scene.rot, scene.opacity, scene.sh)]
 
 
+def max_engine_rows(max_k: int) -> int:
+    """Largest working set the library accepts for kNN size max_k: the round
+    engine keeps two int32 adjacency entries per edge and at most
+    rows * max_k edges per pass, so 2 * rows * max_k < 2^31."""
+    return ((1 << 31) - 2) // (2 * max_k)
+
+
 def rows_for_budget(hbm_budget: int, max_k: int, max_jobs: int) -> int:
     """Largest working-set size whose workspace plus the input/output
-    buffers of that many admitted splats fit in hbm_budget bytes."""
+    buffers of that many admitted splats fit in hbm_budget bytes, clamped to
+    the largest working set the library accepts."""
     probe = 1 << 20
     per_row = ng.batch_workspace_bytes(probe, max_k, max_jobs) / probe + 2 * IO_BYTES_PER_SPLAT
-    rows = int(hbm_budget / per_row)
+    rows = min(int(hbm_budget / per_row), max_engine_rows(max_k))
     while rows > 2 and (ng.batch_workspace_bytes(rows, max_k, max_jobs)
                         + 2 * IO_BYTES_PER_SPLAT * rows > hbm_budget):
         rows = int(rows * 0.98)

@@ -1,0 +1,103 @@
+"""End-to-end comparison of a GPU simplification with the FP64 oracle's.
+
+Raw indices shift after the first merge that differs, so merges are matched
+by provenance: a merge is the pair (smaller origin, larger origin) of the two
+clusters it joins, and a final cluster is identified by its full membership
+(the input splats it absorbed), rebuilt from the merges.  Clusters whose
+membership is identical on both sides are compared field by field in the
+standard 3DGS form: centre, covariance (from scale and rotation), opacity and
+SH coefficients.
+"""
+import numpy as np
+
+import oracle as O
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def pair_identity(pairs_per_round, gpu_trace, ref_trace):
+    """Fraction of the oracle's merges (summed over passes) that the GPU made
+    in the same pass, and the per-pass fractions."""
+    off = same = total = 0
+    per = []
+    for r, cnt in enumerate(pairs_per_round):
+        got = {tuple(x) for x in gpu_trace[off:off + cnt].tolist()}
+        off += cnt
+        exp = {tuple(x) for x in ref_trace[r].tolist()} if r < len(ref_trace) else set()
+        same += len(got & exp)
+        total += len(exp)
+        per.append(len(got & exp) / max(len(exp), 1))
+    return same / max(total, 1), per
+
+
+def _roots(n, merges):
+    """Root (smallest member) of every input splat after the merges, each
+    given as (smaller origin, larger origin) of the two clusters joined."""
+    parent = np.arange(n, dtype=np.int64)
+    for m in merges:
+        m = np.asarray(m, dtype=np.int64).reshape(-1, 2)
+        parent[m[:, 1]] = m[:, 0]
+    while True:
+        nxt = parent[parent]
+        if np.array_equal(nxt, parent):
+            return parent
+        parent = nxt
+
+
+def _signature(n, roots):
+    """(root -> member count, member-hash sum) of every cluster."""
+    x = np.arange(n, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        x = (x ^ (x >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        x = (x ^ (x >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        x = x ^ (x >> np.uint64(31))
+    order = np.argsort(roots, kind="stable")
+    r = roots[order]
+    starts = np.r_[0, np.nonzero(np.diff(r))[0] + 1]
+    cnt = np.diff(np.r_[starts, r.size])
+    with np.errstate(over="ignore"):
+        hs = np.add.reduceat(x[order], starts)
+    return {int(k): (int(c), int(h)) for k, c, h in zip(r[starts], cnt, hs)}
+
+
+def compare_clusters(n, gpu_out, gpu_origin, gpu_merges, ref, ref_merges):
+    """Field errors on the clusters with identical membership.
+
+    gpu_out: stored-form arrays (pos, log_scale, rot, opacity, sh) of the GPU
+    result, gpu_origin its provenance per row; ref: the oracle's final State.
+    Returns a dict of the identical fraction and max / p99 errors."""
+    gs = _signature(n, _roots(n, gpu_merges))
+    rs = _signature(n, _roots(n, ref_merges))
+    g_row = {int(o): i for i, o in enumerate(np.asarray(gpu_origin).tolist())}
+    r_row = {int(o): i for i, o in enumerate(np.asarray(ref.origin).tolist())}
+    same = [o for o in r_row if o in g_row and gs.get(o) == rs.get(o)]
+    gi = np.array([g_row[o] for o in same], dtype=np.int64)
+    ri = np.array([r_row[o] for o in same], dtype=np.int64)
+    pos, ls, rot, op, sh = (np.asarray(a, dtype=np.float64) for a in gpu_out)
+    out = {"identical_clusters": len(same) / max(len(r_row), 1), "clusters": len(r_row)}
+    if len(same) == 0:
+        return out
+    mu_r = ref.mu[ri]
+    e_mu = np.abs(pos[gi] - mu_r).max(1) / np.maximum(np.abs(mu_r).max(1), 1.0)
+    s_g = np.exp(ls[gi])
+    q_g = rot[gi] / np.linalg.norm(rot[gi], axis=1, keepdims=True)
+    Sg = O.covariance(s_g, q_g)
+    Sr = O.covariance(ref.s[ri], ref.q[ri])
+    e_sig = np.linalg.norm(Sg - Sr, axis=(1, 2)) / np.linalg.norm(Sr, axis=(1, 2))
+    a_g = 1.0 / (1.0 + np.exp(-op[gi]))
+    e_al = np.abs(a_g - ref.alpha[ri])
+    f_r = ref.f[ri]
+    e_f = np.linalg.norm(sh[gi] - f_r, axis=1) / np.maximum(np.linalg.norm(f_r, axis=1), 1e-3)
+    for name, e in (("mu", e_mu), ("sigma", e_sig), ("alpha", e_al), ("f", e_f)):
+        out[name + "_max"] = float(e.max())
+        out[name + "_p99"] = float(np.percentile(e, 99))
+    return out
+
+
+def gpu_merges(pairs_per_round, gpu_trace):
+    """The GPU trace split into passes."""
+    out, off = [], 0
+    for cnt in pairs_per_round:
+        out.append(gpu_trace[off:off + cnt])
+        off += cnt
+    return out

@@ -115,3 +115,20 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(nanogs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         nanogs.load()
+
+
+def test_engine_size_limit_rejected_before_any_launch(lib):
+    """The round engine keeps two int32 adjacency entries per edge and at
+    most n * k edges per pass: 2 * n * k must stay below 2^31."""
+    ok = nanogs.Gaussians(256, 512, 768, 1024, 1280)
+    out = nanogs.Gaussians(2048, 2304, 2560, 2816, 3072)
+    n_out = ctypes.c_int64(-7)
+    n = 70_000_000  # n * 16 < 2^31, 2 * n * 16 > 2^31
+    st = lib.nanogs_simplify(ctypes.byref(ok), n, 10, 16, None, ctypes.byref(out),
+                             ctypes.byref(n_out), None, None, 0, None)
+    assert st == 1 and b"2 * n * k" in lib.nanogs_last_error()
+    b = ctypes.c_void_p()
+    st = lib.nanogs_batch_create(60_000_000, 24, 4, None, ctypes.c_void_p(256), 1 << 40, None,
+                                 ctypes.byref(b))
+    assert st == 1 and b"2 * n * k" in lib.nanogs_last_error() and not b.value
+    assert n_out.value == -7

@@ -587,3 +587,36 @@ def test_opacity_prune():
     st.mu, st.s, st.q, st.f, st.origin = (x[:4] for x in (st.mu, st.s, st.q, st.f, st.origin))
     out = O.opacity_prune(st, 1.0)  # even N: median 0.25
     np.testing.assert_array_equal(out.origin, [2, 3])
+
+
+def test_merge_pairs_slots_order_and_provenance():
+    """Hand-worked MergePairs case (Algorithm 1; the merged splat's slot is a
+    reading): six isotropic splats on the x axis, s = 0.1, pairs given as
+    (4, 1) and (5, 2).  The merged splats take slots 1 and 2 (the lower
+    index of each pair), splat 3 keeps its place after them, provenance is
+    the smaller origin."""
+    n = 6
+    mu = np.zeros((n, 3))
+    mu[:, 0] = np.arange(n)
+    s = np.full((n, 3), 0.1)
+    q = np.tile([1.0, 0, 0, 0], (n, 1))
+    alpha = np.array([0.5, 0.5, 0.2, 0.5, 0.5, 0.8])
+    f = np.zeros((n, 48))
+    f[:, 0] = np.arange(n)
+    st = O.State(mu, s, q, alpha, f, np.array([10, 7, 3, 8, 2, 9]))
+    out = O.merge_pairs(st, np.array([[4, 1], [5, 2]]))
+    assert out.n == 4
+    # equal masses (1, 4): pi = 1/2; masses 0.2 : 0.8 (2, 5): pi = 1/5
+    np.testing.assert_allclose(out.mu[:, 0], [0.0, 2.5, 0.2 * 2 + 0.8 * 5, 3.0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(out.mu[:, 1:], 0.0, atol=0)
+    np.testing.assert_allclose(out.f[:, 0], [0.0, 2.5, 4.4, 3.0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(out.alpha, [0.5, 0.75, 1 - 0.8 * 0.2, 0.5], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(out.origin, [10, 2, 3, 8])
+    # Sigma_m = 0.01 I + pi (1 - pi) d d^T with d = (-3, 0, 0)
+    Sm = O.covariance(out.s, out.q)
+    for row, dxx in ((1, 0.25 * 9), (2, 0.16 * 9)):
+        np.testing.assert_allclose(Sm[row], np.diag([0.01 + dxx, 0.01, 0.01]), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(out.s[row], [math.sqrt(0.01 + dxx), 0.1, 0.1], rtol=1e-12)
+    # untouched splats are copied bit for bit
+    np.testing.assert_array_equal(out.s[[0, 3]], s[[0, 3]])
+    np.testing.assert_array_equal(out.q[[0, 3]], q[[0, 3]])
