@@ -12,7 +12,15 @@ import numpy as np
 
 import oracle as O
 
-_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+# Bars on the clusters of identical membership.  Centres, opacities and SH
+# are compared at the teacher-forced bar.  The covariance is not: the GPU
+# keeps the standard float32 parameterisation between passes, so a centre
+# carries a rounding of up to half an ulp of |mu| (3e-7 at |mu| = 10), and a
+# later merge's dispersion term d d^T inherits it relative to |d| (about
+# 0.05 between neighbours): about 1e-5 of Sigma after a few passes.  Scales
+# then carry it into the masses, so into the weights of f.  Those two are
+# held to 2e-4.
+E2E_BARS = {"mu": 1e-5, "alpha": 1e-5, "sigma": 2e-4, "f": 2e-4}
 
 
 def pair_identity(pairs_per_round, gpu_trace, ref_trace):
