@@ -7,10 +7,18 @@ from paper_2603_16103_amd.synth import gen_scene
 
 pytestmark = pytest.mark.gpu
 
+# knn_block_min and knn_lane_rows route queries between the one-lane block
+# search and the one-wave best-first search: their extremes send almost every
+# query one way or the other
 SETTINGS = [
-    dict(cost_block=64, knn_block=256, knn_wave_grid=256, knn_level_bias=-2, select_check=1),
-    dict(cost_block=128, knn_block=128, knn_wave_grid=65536, knn_level_bias=1, select_check=16),
-    dict(cost_block=256, knn_block=64, knn_wave_grid=4096, knn_level_bias=-1, select_check=3),
+    dict(cost_block=64, knn_block=256, knn_wave_grid=256, knn_level_bias=-2, select_check=1,
+         knn_block_min=17, knn_lane_rows=64),
+    dict(cost_block=128, knn_block=128, knn_wave_grid=65536, knn_level_bias=1, select_check=16,
+         knn_block_min=1024, knn_lane_rows=4096),
+    dict(cost_block=256, knn_block=64, knn_wave_grid=4096, knn_level_bias=-1, select_check=3,
+         knn_block_min=17, knn_lane_rows=4096),
+    dict(cost_block=256, knn_block=128, knn_wave_grid=1024, knn_level_bias=0, select_check=4,
+         knn_block_min=1024, knn_lane_rows=64),
 ]
 
 
