@@ -273,8 +273,9 @@ typedef struct {
   int32_t knn_level_bias; /* finest cell-table level relative to the default
                              (one above the smallest L with 8^L >= N, at most
                              8): -2..1, positive values add nothing (0) */
-  int32_t select_check;   /* matching iterations between host reads of the
-                             active count: 1..16 (4) */
+  int32_t select_check;   /* matching iterations launched over the whole
+                             grid before one workgroup finishes the
+                             matching on the device: 1..16 (4) */
   int32_t knn_block_min;  /* rows the 3x3x3 block of cells around a query
                              must hold for the block search to use that
                              cell level: 17..1024 (32) */

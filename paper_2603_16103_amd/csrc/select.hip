@@ -20,6 +20,9 @@
 // ends), so pick[] is never read stale.  With a budget the scan keeps exactly
 // the P smallest keys of that matching (later scan decisions never change
 // earlier ones), found by radix select over (cost, i, j).
+#include <algorithm>
+#include <cmath>
+
 #include "internal.h"
 
 namespace ng {
@@ -69,49 +72,112 @@ __global__ void k_adj_fill(const int* __restrict__ ea, const int* __restrict__ e
 // vertex is free.
 //
 // pick: each active vertex takes its smallest entry whose other end is free.
-// The entries are read four at a time (keys, other ends, then the other
-// ends' partner slots), so a lane waits on two loads per four entries.
+// Other ends only ever go from free to matched, so a vertex keeps its kTop
+// smallest entries (sorted) from its last full scan: the first of them whose
+// other end is still free is the smallest free entry of all, since every
+// entry outside the cache has a larger key.  Only a vertex whose cached ends
+// are all matched scans its whole range again (and refills the cache with
+// the smallest entries whose other end is free, the only ones that can
+// matter later).
+constexpr int kTop = 4;
+
+struct PickState {
+  unsigned long long* tkey;  // [n][kTop] cached smallest keys, ascending
+  int* tu;                   // [n][kTop] their other ends
+  int* tn;                   // [n] cached entries (0: none cached yet)
+};
+
+// One vertex's pick; returns the other end (-1: no free entry) and the key.
+NG_DEV int pick_vertex(int v, bool all_free, const int* __restrict__ aoff,
+                       const unsigned long long* __restrict__ akey, const int* __restrict__ au,
+                       const int* __restrict__ partner, const PickState& ps,
+                       unsigned long long& bkey) {
+  if (!all_free) {
+    const int tn = ps.tn[v];
+#pragma unroll
+    for (int q = 0; q < kTop; ++q) {
+      if (q < tn) {
+        const int u = ps.tu[(long long)v * kTop + q];
+        if (partner[u] < 0) {
+          bkey = ps.tkey[(long long)v * kTop + q];
+          return u;
+        }
+      }
+    }
+  }
+  // full scan: the kTop smallest entries with a free other end, sorted
+  unsigned long long k[kTop];
+  int uu[kTop];
+#pragma unroll
+  for (int q = 0; q < kTop; ++q) {
+    k[q] = KEY_MAX;
+    uu[q] = -1;
+  }
+  auto consider = [&](unsigned long long key, int u) {
+    if (!(key < k[kTop - 1])) return;
+    // sorted insertion (registers, fully unrolled)
+    bool lt_next = true;
+#pragma unroll
+    for (int q = kTop - 1; q > 0; --q) {
+      const bool lt_prev = key < k[q - 1];
+      const unsigned long long nk = lt_prev ? k[q - 1] : (lt_next ? key : k[q]);
+      const int nu = lt_prev ? uu[q - 1] : (lt_next ? u : uu[q]);
+      k[q] = nk;
+      uu[q] = nu;
+      lt_next = lt_prev;
+    }
+    if (lt_next) {
+      k[0] = key;
+      uu[0] = u;
+    }
+  };
+  int t = aoff[v];
+  const int t1 = aoff[v + 1];
+  for (; t + 4 <= t1; t += 4) {
+    unsigned long long kk[4];
+    int u[4];
+    bool f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      kk[q] = akey[t + q];
+      u[q] = au[t + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f[q] = all_free || partner[u[q]] < 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (f[q] && kk[q] != KEY_MAX) consider(kk[q], u[q]);
+  }
+  for (; t < t1; ++t) {
+    const unsigned long long key = akey[t];
+    const int u = au[t];
+    if (key != KEY_MAX && (all_free || partner[u] < 0)) consider(key, u);
+  }
+  int n_ok = 0;
+#pragma unroll
+  for (int q = 0; q < kTop; ++q) {
+    ps.tkey[(long long)v * kTop + q] = k[q];
+    ps.tu[(long long)v * kTop + q] = uu[q];
+    n_ok += uu[q] >= 0 ? 1 : 0;
+  }
+  ps.tn[v] = n_ok;
+  bkey = k[0];
+  return uu[0];
+}
+
 __global__ void __launch_bounds__(256)
 k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
           const int* __restrict__ au, const int* __restrict__ partner,
           const int* __restrict__ act, const int* __restrict__ act_count, int n,
-          int* __restrict__ pick, unsigned* __restrict__ pcost, int* __restrict__ next_count) {
+          int* __restrict__ pick, unsigned* __restrict__ pcost, int* __restrict__ next_count,
+          PickState ps) {
   const int cnt = act ? *act_count : n;
   if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
   const bool all_free = act == nullptr;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
     const int v = act ? act[i] : i;
     unsigned long long best = KEY_MAX;
-    int bu = -1;
-    int t = aoff[v];
-    const int t1 = aoff[v + 1];
-    for (; t + 4 <= t1; t += 4) {
-      unsigned long long k[4];
-      int u[4];
-      bool f[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        k[q] = akey[t + q];
-        u[q] = au[t + q];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) f[q] = all_free || partner[u[q]] < 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (f[q] && k[q] < best) {
-          best = k[q];
-          bu = u[q];
-        }
-    }
-    for (; t < t1; ++t) {
-      const unsigned long long key = akey[t];
-      const int u = au[t];
-      if (key < best && (all_free || partner[u] < 0)) {
-        best = key;
-        bu = u;
-      }
-    }
-    pick[v] = bu;
+    pick[v] = pick_vertex(v, all_free, aoff, akey, au, partner, ps, best);
     pcost[v] = (unsigned)(best >> 32);
   }
 }
@@ -141,9 +207,41 @@ NG_DEV int block_append(bool flag, int* s_cnt, int* count) {
   return slot;
 }
 
-// match: mutual picks are matched (each end writes only its own partner
-// slot, the lower logical end records the pair); vertices whose pick was not
-// returned stay active.  Appends use one atomic per block and list.
+// match step for active entry i (cnt entries): mutual picks are matched (each
+// end writes only its own partner slot, the lower logical end records the
+// pair); vertices whose pick was not returned stay active.
+template <int NW>
+NG_DEV void match_entry(int i, int cnt, const int* __restrict__ act, const int* __restrict__ pick,
+                        const unsigned* __restrict__ pcost, const int* __restrict__ lg,
+                        int* __restrict__ partner, int* __restrict__ next_act,
+                        int* __restrict__ next_count, int* __restrict__ pair_a,
+                        int* __restrict__ pair_b, unsigned* __restrict__ pair_c,
+                        int* __restrict__ npairs, int* s_cnt) {
+  bool keep = false, rec = false;
+  int v = 0, u = -1;
+  if (i < cnt) {
+    v = act ? act[i] : i;
+    u = pick[v];
+    if (u >= 0) {
+      if (pick[u] == v) {
+        partner[v] = u;
+        rec = logical(lg, v) < logical(lg, u);
+      } else {
+        keep = true;
+      }
+    }
+  }
+  const int ks = block_append<NW>(keep, s_cnt, next_count);
+  if (keep) next_act[ks] = v;
+  const int ps = block_append<NW>(rec, s_cnt, npairs);
+  if (rec) {
+    pair_a[ps] = v;
+    pair_b[ps] = u;
+    pair_c[ps] = pcost[v];
+  }
+}
+
+// Appends use one atomic per block and list.
 constexpr int kMatchBlock = 1024;
 __global__ void __launch_bounds__(kMatchBlock)
 k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n,
@@ -156,31 +254,56 @@ k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n
   const int cnt = act ? *act_count : n;
   // whole blocks stay in the loop for the block-wide appends
   const int span = (cnt + kMatchBlock - 1) / kMatchBlock * kMatchBlock;
-  for (int i0 = blockIdx.x * kMatchBlock; i0 < span; i0 += gridDim.x * kMatchBlock) {
-    const int i = i0 + (int)threadIdx.x;
-    bool keep = false, rec = false;
-    int v = 0, u = -1;
-    if (i < cnt) {
-      v = act ? act[i] : i;
-      u = pick[v];
-      if (u >= 0) {
-        if (pick[u] == v) {
-          partner[v] = u;
-          rec = logical(lg, v) < logical(lg, u);
-        } else {
-          keep = true;
-        }
-      }
+  for (int i0 = blockIdx.x * kMatchBlock; i0 < span; i0 += gridDim.x * kMatchBlock)
+    match_entry<NW>(i0 + (int)threadIdx.x, cnt, act, pick, pcost, lg, partner, next_act,
+                    next_count, pair_a, pair_b, pair_c, npairs, s_cnt);
+}
+
+// The remaining iterations in one workgroup: pick and match alternate over
+// the active list (lists swap between A and B) until it is empty, with no
+// launch or host round trip per iteration.  cnt[0] / cnt[1]: the counts of
+// lists A / B; the list the last grid-wide match wrote is `in_sel`.
+// iters (device) receives the number of iterations run here.
+__global__ void __launch_bounds__(kMatchBlock)
+k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
+          const int* __restrict__ au, int* __restrict__ partner, int* __restrict__ listA,
+          int* __restrict__ listB, int* __restrict__ cnt, int in_sel, int* __restrict__ pick,
+          unsigned* __restrict__ pcost, const int* __restrict__ lg, int* __restrict__ pair_a,
+          int* __restrict__ pair_b, unsigned* __restrict__ pair_c, int* __restrict__ npairs,
+          PickState ps, int* __restrict__ iters) {
+  constexpr int NW = kMatchBlock / 64;
+  __shared__ int s_cnt[NW + 1];
+  __shared__ int s_n;
+  int sel = in_sel;
+  int it = 0;
+  while (true) {
+    int* in = sel == 0 ? listA : listB;
+    int* out = sel == 0 ? listB : listA;
+    int* in_cnt = cnt + sel;
+    int* out_cnt = cnt + (sel ^ 1);
+    if (threadIdx.x == 0) s_n = *in_cnt;
+    __syncthreads();
+    const int c = s_n;
+    if (c == 0) break;
+    for (int i = threadIdx.x; i < c; i += kMatchBlock) {
+      const int v = in[i];
+      unsigned long long best = KEY_MAX;
+      pick[v] = pick_vertex(v, false, aoff, akey, au, partner, ps, best);
+      pcost[v] = (unsigned)(best >> 32);
     }
-    const int ks = block_append<NW>(keep, s_cnt, next_count);
-    if (keep) next_act[ks] = v;
-    const int ps = block_append<NW>(rec, s_cnt, npairs);
-    if (rec) {
-      pair_a[ps] = v;
-      pair_b[ps] = u;
-      pair_c[ps] = pcost[v];
-    }
+    if (threadIdx.x == 0) *out_cnt = 0;
+    __threadfence_block();
+    __syncthreads();
+    const int span = (c + kMatchBlock - 1) / kMatchBlock * kMatchBlock;
+    for (int i0 = 0; i0 < span; i0 += kMatchBlock)
+      match_entry<NW>(i0 + (int)threadIdx.x, c, in, pick, pcost, lg, partner, out, out_cnt,
+                      pair_a, pair_b, pair_c, npairs, s_cnt);
+    __threadfence_block();
+    __syncthreads();
+    sel ^= 1;
+    ++it;
   }
+  if (threadIdx.x == 0) *iters = it;
 }
 
 // ---- budget: keep the P smallest (cost, i, j) of each segment's matching --
@@ -340,6 +463,9 @@ size_t select_temp_bytes(long long n, long long m, int nseg) {
   c.take<long long>(nseg);        // budgets
   c.take<int>(nseg);              // pairs kept
   c.take<int>(64);                // counters
+  c.take<unsigned long long>(n * kTop);  // cached smallest keys
+  c.take<int>(n * kTop);          // their other ends
+  c.take<int>(n);                 // cached counts
   (void)m;
   return c.bytes() + sort_temp_bytes(n / 2 + 1);
 }
@@ -396,45 +522,54 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   int* pend = c.take<int>(nseg);
   long long* Pdev = c.take<long long>(nseg);
   int* mseg = c.take<int>(nseg);
-  int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs
+  int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs, [3]: tail iterations
+  PickState ps;
+  ps.tkey = c.take<unsigned long long>((long long)n * kTop);
+  ps.tu = c.take<int>((long long)n * kTop);
+  ps.tn = c.take<int>(n);
   void* stemp = (char*)temp + c.bytes();
   long long* host = pinned_host();
 
   fill_i32(partner, -1, n, st);
   fill_i32(counters, 0, 64, st);
   SelectResult r{0, 0};
-  long long known = n;  // upper bound of the active count
+  // A fixed schedule: grid-wide iterations until about 2^11 vertices are
+  // left (each iteration leaves a bit over half of the active vertices on
+  // the synthetic scenes, about 1.2 iterations per halving), at least
+  // select_check of them, then one workgroup finishes the remaining ones on
+  // the device.  No host round trip happens before the end; the grids of
+  // later launches are sized for the expected active count (the kernels
+  // stride over the actual one).
+  int grid_iters = (int)std::ceil(1.2 * std::log2(std::max((double)n, 2.0) / 2048.0));
+  grid_iters = std::max(grid_iters, tuning_for(n).select_check);
+  grid_iters = std::min(grid_iters, 24);
   int it = 0;
-  // Iterations run without a host round trip; the host reads the active
-  // count every `batch` iterations (an empty iteration is two tiny launches).
-  // After the first read the active set is small and an iteration costs
-  // about two kernel launches, so later batches are twice as long.
-  int batch = tuning_for(n).select_check;
-  while (true) {
-    for (int b = 0; b < batch; ++b, ++it) {
-      const int* in_list = it == 0 ? nullptr : act[(it + 1) & 1];
-      const int* in_cnt = counters + ((it + 1) & 1);
-      int* out_list = act[it & 1];
-      int* out_cnt = counters + (it & 1);
-      const unsigned g = grid_for(known);
-      k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n,
-                                   pick, pcost, out_cnt);
-      NG_LAUNCH_CHECK();
-      unsigned gm = (unsigned)((known + kMatchBlock - 1) / kMatchBlock);
-      gm = gm < 1 ? 1 : (gm > 1024 ? 1024 : gm);
-      k_ld_match<<<gm, kMatchBlock, 0, st>>>(in_list, in_cnt, n, pick, pcost, lg, partner,
-                                             out_list, out_cnt, pair_a, pair_b, pair_c,
-                                             counters + 2);
-      NG_LAUNCH_CHECK();
-    }
-    NG_HIP(hipMemcpyAsync(host, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    NG_HIP(hipStreamSynchronize(st));
-    const int* hc = (const int*)host;
-    known = hc[(it + 1) & 1];  // count produced by the last iteration
-    if (known == 0) break;
-    if (batch < 16) batch *= 2;
+  double expect = n;
+  for (; it < grid_iters; ++it) {
+    const int* in_list = it == 0 ? nullptr : act[(it + 1) & 1];
+    const int* in_cnt = counters + ((it + 1) & 1);
+    int* out_list = act[it & 1];
+    int* out_cnt = counters + (it & 1);
+    const long long span = std::max(2048ll, (long long)expect);
+    expect *= 0.6;
+    const unsigned g = grid_for(span);
+    k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n, pick,
+                                 pcost, out_cnt, ps);
+    NG_LAUNCH_CHECK();
+    unsigned gm = (unsigned)((span + kMatchBlock - 1) / kMatchBlock);
+    gm = gm < 1 ? 1 : (gm > 1024 ? 1024 : gm);
+    k_ld_match<<<gm, kMatchBlock, 0, st>>>(in_list, in_cnt, n, pick, pcost, lg, partner,
+                                           out_list, out_cnt, pair_a, pair_b, pair_c,
+                                           counters + 2);
+    NG_LAUNCH_CHECK();
   }
-  r.iters = it;
+  k_ld_tail<<<1, kMatchBlock, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, act[0], act[1],
+                                       counters, (it - 1) & 1, pick, pcost, lg, pair_a, pair_b,
+                                       pair_c, counters + 2, ps, counters + 3);
+  NG_LAUNCH_CHECK();
+  NG_HIP(hipMemcpyAsync(host, counters, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  NG_HIP(hipStreamSynchronize(st));
+  r.iters = it + ((const int*)host)[3];
   const long long M = ((const int*)host)[2];
   // per-segment budgets (the matching of each segment, then its P smallest)
   NG_HIP(hipMemcpyAsync(Pdev, hP, nseg * sizeof(long long), hipMemcpyHostToDevice, st));
