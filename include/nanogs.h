@@ -222,6 +222,24 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n,
                                float* cost, float* dgeo, void* ws,
                                size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as nanogs_edge_cost, bit for bit, with no workspace argument.
+ * Its scratch (packed splats, per-splat factors, the FP64-fallback list,
+ * counters and draws) is a fixed 32 MiB array in the library's code object,
+ * one per GPU, held until the process ends; the call allocates nothing.
+ * Limits: n <= NANOGS_NOALLOC_MAX_N and m <= NANOGS_NOALLOC_MAX_M, else
+ * EINVAL before any launch.  Every call on one GPU uses that GPU's single
+ * array: calls that overlap on one GPU (other streams or host threads) race
+ * and give undefined results; calls in one stream order are safe. */
+#define NANOGS_NOALLOC_MAX_N 131072
+#define NANOGS_NOALLOC_MAX_M 2097152
+nanogs_status nanogs_edge_cost_noalloc(const nanogs_splats* s, int64_t n,
+                                       const int32_t* ei, const int32_t* ej,
+                                       int64_t m, const float* crn,
+                                       const nanogs_options* opt, float* cost,
+                                       float* dgeo, hipStream_t stream);
+
 /* ---- stage 3: greedy disjoint pairs (Algorithm 1 GreedyDisjointPairs) --- */
 
 /* partner[n] receives the result of scanning the edges in increasing

@@ -3,6 +3,7 @@
 // pairs -> merge, until the target count or a pass without pairs).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/nanogs.h"
@@ -383,25 +384,32 @@ size_t nanogs_edge_cost_workspace_bytes(int64_t n, int64_t m) {
   return cost_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
 }
 
-nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t* ei,
-                               const int32_t* ej, int64_t m, const float* crn,
-                               const nanogs_options* opt, float* cost, float* dgeo, void* ws,
-                               size_t ws_bytes, hipStream_t stream) {
-  return guarded([&]() -> nanogs_status {
-    NG_CHECK(check_n(n, 1));
-    if (m < 0 || m >= (1ll << 31)) {
-      set_error("m must be in [0, 2^31)");
-      return NANOGS_EINVAL;
-    }
-    Opts o;
-    NG_CHECK(read_opts(opt, &o));
-    if (m == 0) return NANOGS_OK;
-    NG_CHECK(check_splats(s, "s"));
-    NG_CHECK(check_ptr(ei, 4, "ei"));
-    NG_CHECK(check_ptr(ej, 4, "ej"));
-    NG_CHECK(check_ptr(crn, 4, "crn"));
-    NG_CHECK(check_ptr(cost, 4, "cost"));
-    NG_CHECK(check_ws(ws, ws_bytes, cost_bytes(n, m)));
+}  // extern "C"
+
+namespace {
+
+nanogs_status check_edge_cost_args(const nanogs_splats* s, int64_t n, const int32_t* ei,
+                                   const int32_t* ej, int64_t m, const float* crn,
+                                   const nanogs_options* opt, float* cost, Opts* o) {
+  NG_CHECK(check_n(n, 1));
+  if (m < 0 || m >= (1ll << 31)) {
+    set_error("m must be in [0, 2^31)");
+    return NANOGS_EINVAL;
+  }
+  NG_CHECK(read_opts(opt, o));
+  if (m == 0) return NANOGS_OK;
+  NG_CHECK(check_splats(s, "s"));
+  NG_CHECK(check_ptr(ei, 4, "ei"));
+  NG_CHECK(check_ptr(ej, 4, "ej"));
+  NG_CHECK(check_ptr(crn, 4, "crn"));
+  NG_CHECK(check_ptr(cost, 4, "cost"));
+  return NANOGS_OK;
+}
+
+// The stage's launches over scratch memory ws of cost_bytes(n, m) bytes.
+void edge_cost_run(const nanogs_splats* s, int64_t n, const int32_t* ei, const int32_t* ej,
+                   int64_t m, const float* crn, const Opts& o, float* cost, float* dgeo,
+                   void* ws, hipStream_t stream) {
     Carver c(ws);
     Packed p = take_packed(c, n);
     float4* pre = c.take<float4>(pre_float4s(n));
@@ -423,6 +431,66 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
       launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, false, fb_list,
                             counters, (int)m, args, cost, dgeo, AdjOut{}, stream);
     }
+}
+
+// Scratch of the allocation-free edge-cost entry point: one array per GPU,
+// in the library's code object (it lives as long as the process).  Host code
+// never uses the symbol's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_ptr() {
+  int dev = 0;
+  NG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw HipError{"device index out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    NG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t* ei,
+                               const int32_t* ej, int64_t m, const float* crn,
+                               const nanogs_options* opt, float* cost, float* dgeo, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    Opts o;
+    NG_CHECK(check_edge_cost_args(s, n, ei, ej, m, crn, opt, cost, &o));
+    if (m == 0) return NANOGS_OK;
+    NG_CHECK(check_ws(ws, ws_bytes, cost_bytes(n, m)));
+    edge_cost_run(s, n, ei, ej, m, crn, o, cost, dgeo, ws, stream);
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_edge_cost_noalloc(const nanogs_splats* s, int64_t n, const int32_t* ei,
+                                       const int32_t* ej, int64_t m, const float* crn,
+                                       const nanogs_options* opt, float* cost, float* dgeo,
+                                       hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    Opts o;
+    NG_CHECK(check_edge_cost_args(s, n, ei, ej, m, crn, opt, cost, &o));
+    if (m == 0) return NANOGS_OK;
+    if (n > NANOGS_NOALLOC_MAX_N || m > NANOGS_NOALLOC_MAX_M ||
+        cost_bytes(n, m) > kScratchBytes) {
+      set_error("nanogs_edge_cost_noalloc: n must be <= " +
+                std::to_string(NANOGS_NOALLOC_MAX_N) + " and m <= " +
+                std::to_string(NANOGS_NOALLOC_MAX_M) + " (fixed scratch of " +
+                std::to_string(kScratchBytes >> 20) + " MiB)");
+      return NANOGS_EINVAL;
+    }
+    edge_cost_run(s, n, ei, ej, m, crn, o, cost, dgeo, scratch_ptr(), stream);
     return NANOGS_OK;
   });
 }

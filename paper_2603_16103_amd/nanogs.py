@@ -124,6 +124,8 @@ _SIGS = {
     "nanogs_edge_cost_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_edge_cost": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, _P, _I64, _P,
                                         ctypes.POINTER(Options), _P, _P, _P, _SZ, _P]),
+    "nanogs_edge_cost_noalloc": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, _P, _I64,
+                                                _P, ctypes.POINTER(Options), _P, _P, _P]),
     "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
@@ -410,6 +412,31 @@ def edge_cost(s: SplatTensors, ei, ej, crn_block, opts: Options | None = None,
                                 blk.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
                                 _ptr(cost), _ptr(dgeo), _ptr(ws), nb, _stream()))
     return (cost[:m], dgeo[:m]) if with_dgeo else cost[:m]
+
+
+NOALLOC_MAX_N = 131072
+NOALLOC_MAX_M = 2097152
+
+
+def edge_cost_noalloc(s: SplatTensors, ei, ej, crn_block, opts: Options | None = None,
+                      cost=None):
+    """edge_cost through the entry point that allocates nothing (the library's
+    fixed per-GPU scratch); `cost` (float32 [m] on the GPU) may be given so
+    that this call allocates nothing either."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    m = int(ei.shape[0])
+    opts = opts if opts is not None else options()
+    blk = np.ascontiguousarray(crn_block, dtype=np.float32)
+    opts.S = int(blk.shape[0])
+    if cost is None:
+        cost = torch.empty(max(m, 1), dtype=torch.float32, device="cuda")
+    ss = s.struct()
+    _check(lib.nanogs_edge_cost_noalloc(ctypes.byref(ss), s.n, _ptr(ei), _ptr(ej), m,
+                                        blk.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                                        _ptr(cost), None, _stream()))
+    return cost[:m]
 
 
 def select(ei, ej, cost, n: int, max_pairs: int):
