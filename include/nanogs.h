@@ -93,6 +93,9 @@ typedef struct {
                          splat (smallest input index it absorbed) */
   int32_t timing;     /* 1: time each stage with HIP events on the call's
                          stream into nanogs_stats.stage_ms (0) */
+  float tau;          /* opacity pre-filter of nanogs_simplify (Algorithm
+                         1, before the loop): keep the splats with alpha >=
+                         min(tau, median alpha); < 0 turns it off (-1) */
 } nanogs_options;
 
 /* Stages timed into nanogs_stats.stage_ms when options.timing is set. */
@@ -126,6 +129,7 @@ typedef struct {
                                                        of the block gather */
   double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
   int32_t stage_launches[NANOGS_NTIMED];
+  int64_t n_kept;  /* splats the opacity pre-filter kept (n when it is off) */
 } nanogs_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -144,7 +148,7 @@ const char* nanogs_last_error(void);
  * computed in double and rounded to float.  Host-only, no device work. */
 void nanogs_crn(uint64_t seed, int32_t round, int32_t S, float* out);
 
-/* ---- whole loop (Algorithm 1, without the opacity pre-filter) ---------- */
+/* ---- whole loop (Algorithm 1) ------------------------------------------- */
 
 size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k,
                                        const nanogs_options* opt);
@@ -157,6 +161,10 @@ size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k,
  * clipped to [0,1].  Output order: splats keep the relative order of the
  * lowest input index they absorbed.  target_n >= n (or n <= 1) copies the
  * input through activation and back.  opt and stats are nullable (host).
+ * With options.tau >= 0 the opacity pre-filter (see nanogs_prune) runs
+ * first on the activated opacities and the loop runs on its survivors;
+ * provenance (d_origin, d_trace) still names input indices.  The workspace
+ * query must then see the same options.
  * Errors: EINVAL (n < 1, target_n < 1, k < 1 or > NANOGS_MAX_K, 2*n*k too
  * large, bad options), EWORKSPACE, ENONFINITE (checked before any merge),
  * EHIP.  Synchronises `stream`. */
@@ -165,6 +173,28 @@ nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n,
                               const nanogs_options* opt, nanogs_gaussians* out,
                               int64_t* n_out, nanogs_stats* stats, void* ws,
                               size_t ws_bytes, hipStream_t stream);
+
+/* Coarse-to-fine hierarchy (Sec. 3.4: every pass leaves a valid coarser
+ * representation): nanogs_simplify that also writes the set at the start of
+ * every pass.  Level r (r < *lod_levels) occupies rows
+ * [lod_offsets[r], lod_offsets[r+1]) of lod (device, stored form, capacity
+ * lod_capacity rows), in the order of that pass (level 0 is the input, or
+ * the opacity filter's survivors); lod_parent[row] (device, capacity
+ * lod_capacity) is the index, within level r+1, of the splat it becomes:
+ * both ends of a merged pair name the merged splat.  Level *lod_levels is
+ * out[0, *n_out).  A level that would not fit in lod_capacity rows ends the
+ * hierarchy there (the loop still finishes); sum_r N_r <= 2 n rows always
+ * suffice when every pass halves the set.  lod_offsets (host, at least
+ * NANOGS_MAX_ROUNDS + 1 entries) and lod_levels (host) are written.  Other
+ * arguments and errors as nanogs_simplify. */
+nanogs_status nanogs_simplify_lod(const nanogs_gaussians* in, int64_t n,
+                                  int64_t target_n, int32_t k,
+                                  const nanogs_options* opt, nanogs_gaussians* out,
+                                  int64_t* n_out, nanogs_gaussians* lod,
+                                  int32_t* lod_parent, int64_t lod_capacity,
+                                  int64_t* lod_offsets, int32_t* lod_levels,
+                                  nanogs_stats* stats, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
 
 /* ---- boundary conversions ---------------------------------------------- */
 
@@ -181,6 +211,20 @@ nanogs_status nanogs_activate(const nanogs_gaussians* g, int64_t n,
  * final step of Algorithm 1), rot = quat with w >= 0; mu and sh copied. */
 nanogs_status nanogs_deactivate(const nanogs_splats* s, int64_t n,
                                 nanogs_gaussians* g, hipStream_t stream);
+
+/* ---- opacity pre-filter (Algorithm 1, before the loop) ------------------ */
+
+/* Robust opacity filter: with tau' = min(tau, median of alpha) (the mean of
+ * the two middle values for an even n), out receives the splats of `in`
+ * whose alpha >= tau', in their input order (origin carried when both in and
+ * out give one).  The median and the comparison are taken in double from the
+ * float opacities.  out must hold n splats and may not alias in; the count
+ * goes to device int64 *d_nout.  Errors: EINVAL (tau not finite, bad
+ * pointers), EWORKSPACE. */
+size_t nanogs_prune_workspace_bytes(int64_t n);
+nanogs_status nanogs_prune(const nanogs_splats* in, int64_t n, float tau,
+                           nanogs_splats* out, int64_t* d_nout, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /* ---- stage 1: kNN merge graph (Sec. 3.1) -------------------------------- */
 

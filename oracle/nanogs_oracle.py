@@ -463,6 +463,20 @@ def merge_pairs(st: State, pairs: np.ndarray) -> State:
     return State(mu[keep], s[keep], q[keep], alpha[keep], f[keep], origin[keep])
 
 
+def merge_parents(n: int, pairs: np.ndarray) -> np.ndarray:
+    """Index in the next set of every splat, under the MergePairs reading:
+    the lower index keeps its place among the survivors (relative order
+    kept), the higher index goes to the same merged splat."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    a = np.minimum(pairs[:, 0], pairs[:, 1])
+    b = np.maximum(pairs[:, 0], pairs[:, 1])
+    keep = np.ones(n, dtype=bool)
+    keep[b] = False
+    parent = np.cumsum(keep) - 1
+    parent[b] = parent[a]
+    return parent
+
+
 # ---------------------------------------------------------------------------
 # Opacity pre-filter (Algorithm 1, before the loop)
 # ---------------------------------------------------------------------------
@@ -483,15 +497,20 @@ def opacity_prune(st: State, tau: float) -> State:
 # ---------------------------------------------------------------------------
 def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
              seed: int = 0, S: int = 1, app_dims: int = 48, trace=None,
-             max_rounds: int = 1 << 30, workers: int = 1):
-    """Algorithm 1 without the opacity pre-filter: while N > N_tgt, rebuild
+             max_rounds: int = 1 << 30, workers: int = 1, tau=None, lod=None):
+    """Algorithm 1: the opacity pre-filter when ``tau`` is given (the target
+    count is the caller's, fixed before the filter), then while N > N_tgt, rebuild
     the kNN graph, take the union edges, cost them, pick at most
     P = N - N_tgt greedy disjoint pairs, stop if none, merge.  The shared
     draws of pass r are ``crn_block(seed, r, S)``.  Returns the final State
     (alpha clipped to [0, 1]).  When ``trace`` is a list, each pass appends
-    the provenance pairs (origin_i, origin_j) it merged.  ``workers``:
+    the provenance pairs (origin_i, origin_j) it merged.  When ``lod`` is a
+    list, each pass appends (the set at its start, merge_parents of its
+    pairs): the coarse-to-fine hierarchy (Sec. 3.4).  ``workers``:
     threads for the per-query and per-edge steps (results do not change)."""
     st = activate(pos, log_scale, rot, opacity, sh)
+    if tau is not None:
+        st = opacity_prune(st, tau)
     target_n = max(int(target_n), 1)
     r = 0
     while st.n > target_n and r < max_rounds:
@@ -506,6 +525,9 @@ def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
             break
         if trace is not None:
             trace.append(np.sort(st.origin[pairs], axis=1))
+        if lod is not None:
+            lod.append((State(st.mu.copy(), st.s.copy(), st.q.copy(), st.alpha.copy(),
+                              st.f.copy(), st.origin.copy()), merge_parents(n, pairs)))
         st = merge_pairs(st, pairs)
         r += 1
     st.alpha = np.clip(st.alpha, 0.0, 1.0)

@@ -2,6 +2,7 @@
 // of Algorithm 1 (kNN graph -> union edges -> edge costs -> greedy disjoint
 // pairs -> merge, until the target count or a pass without pairs).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -31,6 +32,7 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
     r.d_trace = o->d_trace;
     r.d_origin = o->d_origin;
     r.timing = o->timing;
+    r.tau = o->tau;
   }
   if (r.S < 1 || r.S > NANOGS_MAX_S) {
     set_error("options.S must be in [1, 16]");
@@ -50,6 +52,10 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
   }
   if (r.max_rounds < 0) {
     set_error("options.max_rounds must be >= 0");
+    return NANOGS_EINVAL;
+  }
+  if (std::isnan(r.tau) || std::isinf(r.tau)) {
+    set_error("options.tau must be finite (< 0 turns the opacity pre-filter off)");
     return NANOGS_EINVAL;
   }
   *out = r;
@@ -160,28 +166,96 @@ nanogs_status guarded(F&& f) {
 // ---------------------------------------------------------------------------
 // simplify: one job on an engine sized for it
 // ---------------------------------------------------------------------------
-size_t simplify_bytes(long long n, int k) {
-  if (n < 1) n = 1;
-  return Engine::workspace_bytes(n, k, 1);
+// Stored-form copy of the splats the opacity pre-filter keeps, and the input
+// index of each.
+struct PrunedInput {
+  nanogs_gaussians g;
+  int* kept;
+  void* temp;
+};
+
+PrunedInput take_pruned(void* base, long long n, size_t* bytes) {
+  Carver c(base);
+  PrunedInput p;
+  p.g.pos = c.take<float>(3 * n);
+  p.g.log_scale = c.take<float>(3 * n);
+  p.g.rot = c.take<float>(4 * n);
+  p.g.opacity = c.take<float>(n);
+  p.g.sh = c.take<float>(NG_SH * n);
+  p.kept = c.take<int>(n);
+  p.temp = base ? (char*)base + c.bytes() : nullptr;
+  if (bytes) *bytes = c.bytes() + prune_temp_bytes(n);
+  return p;
 }
+
+size_t simplify_bytes(long long n, int k, bool prune) {
+  if (n < 1) n = 1;
+  size_t b = Engine::workspace_bytes(n, k, 1);
+  if (prune) {
+    size_t pb = 0;
+    take_pruned(nullptr, n, &pb);
+    b += pb + 256;
+  }
+  return b;
+}
+
+struct LodOut {
+  nanogs_gaussians* lod = nullptr;
+  int32_t* parent = nullptr;
+  long long cap = 0;
+  int64_t* offsets = nullptr;
+  int32_t* levels = nullptr;
+};
 
 nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long target_n, int k,
                            const Opts& o, nanogs_gaussians* out, int64_t* n_out,
-                           nanogs_stats* stats, void* ws, hipStream_t st) {
+                           nanogs_stats* stats, void* ws, hipStream_t st,
+                           const LodOut& lod = LodOut()) {
   thread_local StageTimer T;
   T.begin_call(o.timing != 0, st);
+  // opacity pre-filter (Algorithm 1, before the loop): the loop runs on the
+  // survivors; provenance is mapped back to input indices at the end
+  nanogs_gaussians src = *in;
+  long long n_run = n;
+  const int* kept = nullptr;
+  if (o.tau >= 0.0f) {
+    const size_t eb = Engine::workspace_bytes(n < 2 ? 2 : n, k, 1);
+    PrunedInput pin = take_pruned((char*)ws + ((eb + 255) & ~(size_t)255), n, nullptr);
+    bool nonfinite = false;
+    n_run = prune_stored(in->pos, in->log_scale, in->rot, in->opacity, in->sh, (int)n, o.tau,
+                         pin.g.pos, pin.g.log_scale, pin.g.rot, pin.g.opacity, pin.g.sh, pin.kept,
+                         &nonfinite, pin.temp, st);
+    if (nonfinite) {
+      set_error("input contains a non-finite value");
+      return NANOGS_ENONFINITE;
+    }
+    src = pin.g;
+    kept = pin.kept;
+  }
   Engine E(n, k, 1, o, ws, st);
   JobSpec js;
-  js.in = *in;
+  js.in = src;
   js.out = *out;
-  js.n = n;
+  js.n = n_run;
   js.target = target_n;
   js.k = k;
   js.seed = o.seed;
   js.d_origin = o.d_origin;
   js.d_trace = o.d_trace;
+  long long lod_offsets[NANOGS_MAX_ROUNDS + 1] = {0};
+  if (lod.lod) {
+    js.lod = *lod.lod;
+    js.lod_parent = lod.parent;
+    js.lod_cap = lod.cap;
+    js.lod_offsets = lod_offsets;
+  }
   const int id = E.submit(js);
   E.run(&T);
+  if (lod.lod) {
+    const int lv = E.job(id).lod_levels;
+    *lod.levels = lv;
+    for (int r = 0; r <= lv; ++r) lod.offsets[r] = lod_offsets[r];
+  }
   nanogs_stats local = E.job(id).stats;
   T.collect(local.stage_ms, local.stage_launches);
   const Job& j = E.job(id);
@@ -191,7 +265,18 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
     return (nanogs_status)j.status;
   }
   local.n_out = j.stats.n_out;
+  local.n_kept = n_run;
   *n_out = j.stats.n_out;
+  if (kept) {
+    if (o.d_origin) remap_indices(o.d_origin, j.stats.n_out, kept, st);
+    if (o.d_trace) {
+      long long traced = 0;
+      for (int r = 0; r < j.stats.rounds && r < NANOGS_MAX_ROUNDS; ++r)
+        traced += j.stats.pairs_per_round[r];
+      remap_indices(o.d_trace, 2 * traced, kept, st);
+    }
+    NG_HIP(hipStreamSynchronize(st));
+  }
   if (stats) *stats = local;
   return NANOGS_OK;
 }
@@ -255,6 +340,7 @@ void nanogs_default_options(nanogs_options* opt) {
   opt->seed = 0;
   opt->max_rounds = 0;
   opt->timing = 0;
+  opt->tau = -1.0f;
 }
 
 const char* nanogs_last_error(void) { return g_error.c_str(); }
@@ -267,7 +353,7 @@ void nanogs_crn(uint64_t seed, int32_t round, int32_t S, float* out) {
 size_t nanogs_simplify_workspace_bytes(int64_t n, int32_t k, const nanogs_options* opt) {
   (void)opt;
   if (n < 1 || k < 1 || k > NANOGS_MAX_K) return 0;
-  return simplify_bytes(n, k);
+  return simplify_bytes(n, k, opt && opt->tau >= 0.0f);
 }
 
 nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n, int64_t target_n, int32_t k,
@@ -296,8 +382,49 @@ nanogs_status nanogs_simplify(const nanogs_gaussians* in, int64_t n, int64_t tar
     }
     Opts o;
     NG_CHECK(read_opts(opt, &o));
-    NG_CHECK(check_ws(ws, ws_bytes, simplify_bytes(n, k)));
+    NG_CHECK(check_ws(ws, ws_bytes, simplify_bytes(n, k, o.tau >= 0.0f)));
     return run_simplify(in, n, target_n, k, o, out, n_out, stats, ws, stream);
+  });
+}
+
+nanogs_status nanogs_simplify_lod(const nanogs_gaussians* in, int64_t n, int64_t target_n,
+                                  int32_t k, const nanogs_options* opt, nanogs_gaussians* out,
+                                  int64_t* n_out, nanogs_gaussians* lod, int32_t* lod_parent,
+                                  int64_t lod_capacity, int64_t* lod_offsets,
+                                  int32_t* lod_levels, nanogs_stats* stats, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    if (n < 1 || target_n < 1) {
+      set_error("n and target_n must be >= 1");
+      return NANOGS_EINVAL;
+    }
+    if (!n_out || !lod_offsets || !lod_levels) {
+      set_error("n_out, lod_offsets and lod_levels (host) must not be null");
+      return NANOGS_EINVAL;
+    }
+    if (lod_capacity < 0) {
+      set_error("lod_capacity must be >= 0");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_engine_n(n, k));
+    NG_CHECK(check_gaussians(in, "in"));
+    NG_CHECK(check_gaussians(out, "out"));
+    NG_CHECK(check_gaussians(lod, "lod"));
+    NG_CHECK(check_ptr(lod_parent, 4, "lod_parent"));
+    if (in->pos == out->pos || in->sh == out->sh || lod->pos == in->pos || lod->pos == out->pos) {
+      set_error("in, out and lod may not alias");
+      return NANOGS_EINVAL;
+    }
+    Opts o;
+    NG_CHECK(read_opts(opt, &o));
+    NG_CHECK(check_ws(ws, ws_bytes, simplify_bytes(n, k, o.tau >= 0.0f)));
+    LodOut lo;
+    lo.lod = lod;
+    lo.parent = lod_parent;
+    lo.cap = lod_capacity;
+    lo.offsets = lod_offsets;
+    lo.levels = lod_levels;
+    return run_simplify(in, n, target_n, k, o, out, n_out, stats, ws, stream, lo);
   });
 }
 
@@ -573,6 +700,36 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* pa
   });
 }
 
+size_t nanogs_prune_workspace_bytes(int64_t n) { return prune_temp_bytes(n < 1 ? 1 : n); }
+
+nanogs_status nanogs_prune(const nanogs_splats* in, int64_t n, float tau, nanogs_splats* out,
+                           int64_t* d_nout, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    NG_CHECK(check_ptr(d_nout, 8, "d_nout"));
+    if (std::isnan(tau) || std::isinf(tau)) {
+      set_error("tau must be finite");
+      return NANOGS_EINVAL;
+    }
+    if (n == 0) {
+      set_i64((long long*)d_nout, 0, stream);
+      return NANOGS_OK;
+    }
+    NG_CHECK(check_splats(in, "in"));
+    NG_CHECK(check_splats(out, "out"));
+    if (in->sh == out->sh || in->mu == out->mu) {
+      set_error("in and out may not alias");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_ws(ws, ws_bytes, prune_temp_bytes(n)));
+    prune_splats(in->mu, in->scale, in->quat, in->alpha, in->sh, in->origin, (int)n, tau, out->mu,
+                 out->scale, out->quat, out->alpha, out->sh,
+                 (in->origin && out->origin) ? out->origin : nullptr, (long long*)d_nout, ws,
+                 stream);
+    return NANOGS_OK;
+  });
+}
+
 // ---- batched and served form ----------------------------------------------
 
 size_t nanogs_batch_workspace_bytes(int64_t max_rows, int32_t max_k, int32_t max_jobs) {
@@ -598,6 +755,11 @@ nanogs_status nanogs_batch_create(int64_t max_rows, int32_t max_k, int32_t max_j
     NG_CHECK(read_opts(opt, &o));
     if (o.d_trace || o.d_origin) {
       set_error("batch options take no trace/origin buffers (origin is per job)");
+      return NANOGS_EINVAL;
+    }
+    if (o.tau >= 0.0f) {
+      set_error("the opacity pre-filter (options.tau) is applied by nanogs_simplify and "
+                "nanogs_prune, not by batches");
       return NANOGS_EINVAL;
     }
     NG_CHECK(check_ws(ws, ws_bytes, Engine::workspace_bytes(max_rows, max_k, max_jobs)));

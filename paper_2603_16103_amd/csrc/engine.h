@@ -29,6 +29,7 @@ struct Opts {
   int* d_trace = nullptr;
   int* d_origin = nullptr;
   int timing = 0;
+  float tau = -1.0f;  // opacity pre-filter threshold (< 0: off)
 };
 
 enum JobState { JOB_QUEUED = 0, JOB_RUNNING = 1, JOB_DRAINING = 2, JOB_DONE = 3, JOB_FAILED = 4 };
@@ -42,6 +43,13 @@ struct JobSpec {
   uint64_t seed = 0;
   int* d_origin = nullptr;  // nullable device [n]
   int* d_trace = nullptr;   // nullable device [n][2] (single-job batches only)
+  // coarse-to-fine hierarchy (single-job batches only): each pass's set in
+  // the stored form at rows lod_offsets[r].. of lod, and lod_parent[row] =
+  // index of the splat of the next level it becomes
+  nanogs_gaussians lod = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int* lod_parent = nullptr;
+  long long lod_cap = 0;
+  long long* lod_offsets = nullptr;  // host [NANOGS_MAX_ROUNDS + 1]
 };
 
 struct Job {
@@ -54,6 +62,8 @@ struct Job {
   long long row0 = 0;  // first row (and logical index) in the working set
   int round = 0;
   long long traced = 0;
+  int lod_levels = 0;  // hierarchy levels written
+  long long lod_used = 0;
   unsigned box[6] = {0, 0, 0, 0, 0, 0};
   nanogs_stats stats;
 };

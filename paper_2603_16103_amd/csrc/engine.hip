@@ -360,14 +360,31 @@ int Engine::step(StageTimer* T) {
 
   // single running job with a trace buffer: provenance pairs of this pass
   int* trace = nullptr;
+  int* parent = nullptr;
   if (searching == 1 && nseg == 1) {
     Job& j = jobs_[live_[0]];
     if (j.spec.d_trace) trace = j.spec.d_trace + 2 * j.traced;
+    // hierarchy level of this pass: the set before its merges, and where
+    // each of its splats goes
+    if (j.spec.lod.pos && j.lod_levels < NANOGS_MAX_ROUNDS && j.lod_used + j.N <= j.spec.lod_cap) {
+      const long long o = j.lod_used;
+      nanogs_gaussians& L = j.spec.lod;
+      launch_deactivate_work(a.cen + j.row0, a.lg + j.row0, a.shp + 2 * j.row0, a.org + j.row0,
+                             (int)j.N, (int)j.row0, L.pos + 3 * o, L.log_scale + 3 * o,
+                             L.rot + 4 * o, L.opacity + o, nullptr, st_);
+      launch_copy_sh_rows(a.sh + j.row0 * NG_SH, nullptr, L.sh + o * NG_SH, a.lg + j.row0,
+                          (int)j.row0, (int)j.N, st_);
+      parent = j.spec.lod_parent + o - j.row0;
+      j.spec.lod_offsets[j.lod_levels] = o;
+      j.lod_used = o + j.N;
+      j.spec.lod_offsets[j.lod_levels + 1] = j.lod_used;
+      ++j.lod_levels;
+    }
   }
   tk = T ? T->start(NANOGS_T_MERGE) : -1;
   const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
                                      b.lg, b.shp, b.sh, b.org, trace, W.temp, st_, nullptr, sg,
-                                     b.sg, W.seg, nseg);
+                                     b.sg, W.seg, nseg, parent);
   if (T) T->stop(tk);
   cur_ ^= 1;
   Ntot_ = nn;

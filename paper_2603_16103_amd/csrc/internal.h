@@ -335,12 +335,32 @@ size_t merge_temp_bytes(long long n);
 // order.  Writes the provenance pairs
 // (min origin, max origin) of the merges to trace (nullable) in the order of
 // the lower logical index.
+// parent (nullable, indexed by logical index) receives the logical index of
+// the output splat each input splat becomes (both ends of a pair the same).
 // Synchronises st.
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
                         hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
-                        const SegInfo* seg, int nseg);
+                        const SegInfo* seg, int nseg, int* parent = nullptr);
+
+// prune.hip -- opacity pre-filter (tau' = min(tau, median alpha), keep alpha >= tau')
+size_t prune_temp_bytes(long long n);
+// Activated plain arrays -> their survivors (origin nullable); the count goes
+// to the device int64 *d_nout.  Asynchronous.
+void prune_splats(const float* mu, const float* scale, const float* quat, const float* alpha,
+                  const float* sh, const int* origin, int n, float tau, float* mu_o,
+                  float* scale_o, float* quat_o, float* alpha_o, float* sh_o, int* origin_o,
+                  long long* d_nout, void* temp, hipStream_t st);
+// Stored-form arrays -> their survivors; kept[o] = input index of survivor o.
+// Returns the survivors' count; *nonfinite is set when an opacity is not
+// finite.  Synchronises st.
+long long prune_stored(const float* pos, const float* ls, const float* rot, const float* op,
+                       const float* sh, int n, float tau, float* pos_o, float* ls_o,
+                       float* rot_o, float* op_o, float* sh_o, int* kept, bool* nonfinite,
+                       void* temp, hipStream_t st);
+// v[i] = map[v[i]] for i < count (entries < 0 kept).
+void remap_indices(int* v, long long count, const int* map, hipStream_t st);
 
 // crn.cpp
 void crn_host(uint64_t seed, int round, int S, float* out);

@@ -226,7 +226,7 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
                               float4* __restrict__ cen_o, int* __restrict__ lg_o,
                               float4* __restrict__ shp_o, int* __restrict__ org_o,
                               float4* __restrict__ desc, int* __restrict__ trace,
-                              int* __restrict__ trace_count) {
+                              int* __restrict__ trace_count, int* __restrict__ parent) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nout) return;
   const int p = order[q];
@@ -236,6 +236,12 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
   const int j = partner[p];
   const float4 ca = cen[p];
   const float4 sa = shp[2 * (long long)p], qa = shp[2 * (long long)p + 1];
+  if (parent) {
+    // hierarchy: both ends of a merged pair (or a lone splat) point at the
+    // output splat they become, by logical index
+    parent[lp] = newL;
+    if (j >= 0 && j < n) parent[logical(lg, j)] = newL;
+  }
   if (j < 0 || j >= n) {
     cen_o[q] = make_float4(ca.x, ca.y, ca.z, __int_as_float(newL));
     lg_o[q] = newL;
@@ -315,7 +321,7 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
                         hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
-                        const SegInfo* seg, int nseg) {
+                        const SegInfo* seg, int nseg, int* parent) {
   Carver c(temp);
   int* keep = c.take<int>(n);
   int* newpos = c.take<int>(n);
@@ -357,7 +363,7 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
     k_merge_attrs<<<blocks_for(nout, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order,
                                                          (int)nout, rsum, seg ? sg : nullptr,
                                                          sg_o, seg, cen_o, lg_o, shp_o, org_o,
-                                                         desc, trace, counters + 2);
+                                                         desc, trace, counters + 2, parent);
     NG_LAUNCH_CHECK();
     k_merge_sh<<<blocks_for(nout * 12, 256), 256, 0, st>>>((const float4*)sh, desc, (int)nout,
                                                            (float4*)sh_o);

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("fb_ratio", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
                 ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("tau", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -66,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("knn_retry_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("knn_screens_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("stage_ms", ctypes.c_double * NTIMED),
-                ("stage_launches", ctypes.c_int32 * NTIMED)]
+                ("stage_launches", ctypes.c_int32 * NTIMED),
+                ("n_kept", ctypes.c_int64)]
 
     def as_dict(self):
         r = self.rounds + (1 if self.early_exit else 0)
@@ -81,7 +82,8 @@ class Stats(ctypes.Structure):
                 "knn_retry_per_round": list(self.knn_retry_per_round[:r]),
                 "knn_screens_per_round": list(self.knn_screens_per_round[:r]),
                 "stage_ms": dict(zip(STAGES, self.stage_ms)),
-                "stage_launches": dict(zip(STAGES, self.stage_launches))}
+                "stage_launches": dict(zip(STAGES, self.stage_launches)),
+                "n_kept": self.n_kept}
 
 
 class Tuning(ctypes.Structure):
@@ -126,6 +128,14 @@ _SIGS = {
                                         ctypes.POINTER(Options), _P, _P, _P, _SZ, _P]),
     "nanogs_edge_cost_noalloc": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, _P, _I64,
                                                 _P, ctypes.POINTER(Options), _P, _P, _P]),
+    "nanogs_simplify_lod": (ctypes.c_int, [ctypes.POINTER(Gaussians), _I64, _I64, _I32,
+                                           ctypes.POINTER(Options), ctypes.POINTER(Gaussians),
+                                           ctypes.POINTER(_I64), ctypes.POINTER(Gaussians), _P,
+                                           _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                           ctypes.POINTER(Stats), _P, _SZ, _P]),
+    "nanogs_prune_workspace_bytes": (_SZ, [_I64]),
+    "nanogs_prune": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, ctypes.c_float,
+                                    ctypes.POINTER(Splats), _P, _P, _SZ, _P]),
     "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
@@ -206,7 +216,7 @@ def _workspace(nbytes: int):
 
 
 def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
-            d_trace=None, d_origin=None, timing=False) -> Options:
+            d_trace=None, d_origin=None, timing=False, tau=-1.0) -> Options:
     o = Options()
     load().nanogs_default_options(ctypes.byref(o))
     o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
@@ -214,6 +224,7 @@ def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, m
     o.d_trace = _ptr(d_trace).value if d_trace is not None else None
     o.d_origin = _ptr(d_origin).value if d_origin is not None else None
     o.timing = 1 if timing else 0
+    o.tau = tau
     return o
 
 
@@ -347,6 +358,38 @@ def simplify(g: GaussianTensors, target_n: int | None = None, k: int = 16,
     return (res, st.as_dict()) if return_stats else res
 
 
+def simplify_lod(g: GaussianTensors, target_n: int, k: int = 16, opts: Options | None = None,
+                 capacity: int | None = None):
+    """simplify that also returns the coarse-to-fine hierarchy: (result,
+    levels, parents, stats) where levels[r] is the stored-form set at the
+    start of pass r (GaussianTensors), parents[r] maps each splat of level r
+    to its index in level r+1 (the last level is the result)."""
+    torch = _torch()
+    lib = load()
+    opts = opts if opts is not None else options()
+    cap = capacity if capacity is not None else 2 * g.n
+    out = GaussianTensors.empty(g.n)
+    lod = GaussianTensors.empty(max(cap, 1))
+    parent = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+    nb = lib.nanogs_simplify_workspace_bytes(g.n, k, ctypes.byref(opts))
+    ws = _workspace(nb)
+    n_out = ctypes.c_int64(0)
+    offs = (ctypes.c_int64 * (MAX_ROUNDS + 1))()
+    nlev = ctypes.c_int32(0)
+    st = Stats()
+    gi, go, gl = g.struct(), out.struct(), lod.struct()
+    _check(lib.nanogs_simplify_lod(ctypes.byref(gi), g.n, target_n, k, ctypes.byref(opts),
+                                   ctypes.byref(go), ctypes.byref(n_out), ctypes.byref(gl),
+                                   _ptr(parent), cap, offs, ctypes.byref(nlev), ctypes.byref(st),
+                                   _ptr(ws), nb, _stream()))
+    L = int(nlev.value)
+    levels = [GaussianTensors(lod.pos[offs[r]:offs[r + 1]], lod.log_scale[offs[r]:offs[r + 1]],
+                              lod.rot[offs[r]:offs[r + 1]], lod.opacity[offs[r]:offs[r + 1]],
+                              lod.sh[offs[r]:offs[r + 1]]) for r in range(L)]
+    parents = [parent[offs[r]:offs[r + 1]] for r in range(L)]
+    return out.slice(int(n_out.value)), levels, parents, st.as_dict()
+
+
 def activate(g: GaussianTensors, s: SplatTensors | None = None, check_finite: bool = True):
     torch = _torch()
     s = s if s is not None else SplatTensors.empty(g.n)
@@ -437,6 +480,23 @@ def edge_cost_noalloc(s: SplatTensors, ei, ej, crn_block, opts: Options | None =
                                         blk.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
                                         _ptr(cost), None, _stream()))
     return cost[:m]
+
+
+def prune(s: SplatTensors, tau: float) -> SplatTensors:
+    """Opacity pre-filter: the splats with alpha >= min(tau, median alpha),
+    in order (origin carried when s has one)."""
+    torch = _torch()
+    lib = load()
+    out = SplatTensors.empty(s.n, with_origin=s.origin is not None)
+    d_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_prune_workspace_bytes(s.n)
+    ws = _workspace(nb)
+    si, so = s.struct(), out.struct()
+    _check(lib.nanogs_prune(ctypes.byref(si), s.n, float(tau), ctypes.byref(so), _ptr(d_n),
+                            _ptr(ws), nb, _stream()))
+    k = int(d_n.item())
+    return SplatTensors(out.mu[:k], out.scale[:k], out.quat[:k], out.alpha[:k], out.sh[:k],
+                        out.origin[:k] if out.origin is not None else None)
 
 
 def select(ei, ej, cost, n: int, max_pairs: int):

@@ -620,3 +620,41 @@ def test_merge_pairs_slots_order_and_provenance():
     # untouched splats are copied bit for bit
     np.testing.assert_array_equal(out.s[[0, 3]], s[[0, 3]])
     np.testing.assert_array_equal(out.q[[0, 3]], q[[0, 3]])
+
+
+def test_simplify_with_prefilter_is_prune_then_loop():
+    """Algorithm 1 order: the target is fixed first, the opacity filter runs
+    before the loop, and the loop then sees only the survivors."""
+    sc = gen_scene(1200, 15)
+    tau = 0.3
+    st0 = O.activate(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh)
+    kept = O.opacity_prune(st0, tau).origin
+    med = float(np.median(st0.alpha))
+    assert np.array_equal(kept, np.nonzero(st0.alpha >= min(tau, med))[0])
+    a = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, 200, 16, tau=tau)
+    b = O.simplify(sc.pos[kept], sc.log_scale[kept], sc.rot[kept], sc.opacity[kept],
+                   sc.sh[kept], 200, 16)
+    assert a.n == b.n == 200
+    np.testing.assert_array_equal(a.origin, kept[b.origin])
+    np.testing.assert_array_equal(a.mu, b.mu)
+
+
+def test_merge_parents_hand_case_and_hierarchy():
+    """Parents of the hand-worked MergePairs case, and the hierarchy of a
+    small loop: every level's parents map it onto the next level, each
+    merged splat has exactly the two children the pass merged."""
+    par = O.merge_parents(6, np.array([[4, 1], [5, 2]]))
+    np.testing.assert_array_equal(par, [0, 1, 2, 3, 1, 2])
+    sc = gen_scene(800, 16)
+    lod, trace = [], []
+    st = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, 100, 16, lod=lod,
+                    trace=trace)
+    sizes = [lv.n for lv, _ in lod] + [st.n]
+    assert sizes[0] == 800 and sizes[-1] == 100
+    for r, (lv, par) in enumerate(lod):
+        assert par.shape == (lv.n,) and par.min() == 0 and par.max() == sizes[r + 1] - 1
+        cnt = np.bincount(par, minlength=sizes[r + 1])
+        assert set(cnt.tolist()) <= {1, 2}
+        two = np.nonzero(cnt == 2)[0]
+        got = sorted(tuple(sorted(lv.origin[par == p].tolist())) for p in two)
+        assert got == sorted(map(tuple, trace[r].tolist()))
