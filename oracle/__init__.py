@@ -8,5 +8,5 @@ from .nanogs_oracle import (  # noqa: F401
     crn_block, splitmix64, activate, rotation_matrix, covariance,
     knn, union_edges, edge_costs, greedy_pairs, mpmm, merge_pairs,
     scale_rot_from_cov, quat_from_rotation, simplify, deactivate,
-    opacity_prune, State, mass, merge_parents,
+    opacity_prune, State, mass, merge_parents, gauss_kl, COST_MC, COST_MC_STRAT, COST_BOUND,
 )

@@ -259,8 +259,13 @@ def _log_gauss_chol(x, mu, L):
     return -0.5 * (v0 * v0 + v1 * v1 + v2 * v2) - logdet
 
 
+COST_MC = 0     # Monte Carlo estimate of Appendix A (Eq. mc_kl_estimator)
+COST_MC_STRAT = 1  # both components sampled with every draw (stratified)
+COST_BOUND = 2  # closed-form bound pi KL(N_i||q_m) + (1-pi) KL(N_j||q_m)
+
+
 def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48,
-               chunk: int = 1 << 18, workers: int = 1):
+               chunk: int = 1 << 18, workers: int = 1, mode: int = COST_MC):
     """C(i,j) = D_geo + D_app for every edge (i < j).
 
     D_geo = KL(p~_ij || q_m) estimated with the S shared draws (Appendix A):
@@ -272,6 +277,21 @@ def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48,
     draws, with q_m = N(mu_m, Sigma_m) the moment-matched Gaussian
     (Eq. vm_cov).  D_app = ||f_i - f_j||^2 over the first ``app_dims`` SH
     coefficients.  Returns (cost, d_geo, d_app) in float64.
+
+    ``mode`` picks the geometric term (READING: the paper defines D_geo and
+    estimates it by Monte Carlo; the two other modes are cost variants built
+    on the same definition):
+      COST_MC     the estimate above;
+      COST_MC_STRAT the same expectation without the component draw: each
+                  draw z is used in both components, x_i = mu_i + L_i z
+                  weighted pi and x_j = mu_j + L_j z weighted 1 - pi, so
+                  D = mean_s [pi g(x_i) + (1-pi) g(x_j)] with g = log p~ -
+                  log q_m; exactly symmetric in (i, j) and exactly zero for
+                  an identical pair;
+      COST_BOUND  joint convexity of KL in its first argument bounds the
+                  mixture's divergence by pi KL(N_i || q_m) + (1-pi)
+                  KL(N_j || q_m), each term the closed form of Appendix A
+                  for single Gaussians; no draws.
 
     The covariance of a splat and its Cholesky factor are formed once per
     splat; the edges are evaluated in chunks (the cost of an edge depends on
@@ -289,12 +309,24 @@ def edge_costs(st: State, ei, ej, crn: np.ndarray, app_dims: int = 48,
     L[used] = np.linalg.cholesky(Sig[used])
     w = np.zeros(st.n)
     w[used] = mass(st.s[used], st.alpha[used])
-    parts = [_edge_costs_block(st, Sig, L, w, a[c0:c0 + chunk], b[c0:c0 + chunk], crn, app_dims)
+    parts = [_edge_costs_block(st, Sig, L, w, a[c0:c0 + chunk], b[c0:c0 + chunk], crn, app_dims,
+                               mode)
              for c0 in range(0, a.size, chunk)]
     return tuple(np.concatenate([p[t] for p in parts]) for t in range(3))
 
 
-def _edge_costs_block(st: State, Sig, L, w, a, b, crn, app_dims):
+def gauss_kl(mu_a, Sa, mu_b, Sb):
+    """KL(N(mu_a, Sa) || N(mu_b, Sb)) in closed form (Appendix A, d = 3)."""
+    d = 3
+    diff = mu_b - mu_a
+    sol = np.linalg.solve(Sb, np.concatenate([Sa, diff[..., None]], axis=-1))
+    tr = np.trace(sol[..., :d], axis1=-2, axis2=-1)
+    maha = np.sum(diff * sol[..., d], axis=-1)
+    ld = np.linalg.slogdet(Sb)[1] - np.linalg.slogdet(Sa)[1]
+    return 0.5 * (tr + maha - d + ld)
+
+
+def _edge_costs_block(st: State, Sig, L, w, a, b, crn, app_dims, mode=COST_MC):
     """Costs of the edges (a[e], b[e]); Sig, L, w: per-splat covariance,
     its lower Cholesky factor and mass (Eq. vm_weights)."""
     Sa, Sb = Sig[a], Sig[b]
@@ -310,13 +342,33 @@ def _edge_costs_block(st: State, Sig, L, w, a, b, crn, app_dims):
     Sm = (pa[:, None, None] * (Sa + da[:, :, None] * da[:, None, :])
           + pb[:, None, None] * (Sb + db[:, :, None] * db[:, None, :]))
     La, Lb = L[a], L[b]
+    df = st.f[a, :app_dims] - st.f[b, :app_dims]
+    dapp = np.sum(df * df, axis=1)
+    if mode == COST_BOUND:
+        with np.errstate(invalid="ignore"):
+            dgeo = (np.where(pa > 0, pa * gauss_kl(mua, Sa, mum, Sm), 0.0)
+                    + np.where(pb > 0, pb * gauss_kl(mub, Sb, mum, Sm), 0.0))
+        return dgeo + dapp, dgeo, dapp
     Lm = np.linalg.cholesky(Sm)
     crn = np.asarray(crn, dtype=np.float32)
     S = crn.shape[0]
     with np.errstate(divide="ignore"):
         lpa = np.log(pa)
         lpb = np.log(pb)
-    # draws on a leading axis: arrays are [S, E, ...]
+    if mode == COST_MC_STRAT:
+        z = crn[:, 1:4].astype(np.float64)
+
+        def g(x):
+            return (np.logaddexp(lpa[None] + _log_gauss_chol(x, mua[None], La[None]),
+                                 lpb[None] + _log_gauss_chol(x, mub[None], Lb[None]))
+                    - _log_gauss_chol(x, mum[None], Lm[None]))
+
+        xa = mua[None] + np.einsum("eij,sj->sei", La, z)
+        xb = mub[None] + np.einsum("eij,sj->sei", Lb, z)
+        with np.errstate(invalid="ignore"):
+            strat = (np.where(pa > 0, pa * g(xa), 0.0) + np.where(pb > 0, pb * g(xb), 0.0))
+        dgeo = np.mean(strat, axis=0)
+        return dgeo + dapp, dgeo, dapp
     u = crn[:, 0].astype(np.float64)[:, None]
     z = crn[:, 1:4].astype(np.float64)
     take_a = u < pa[None, :]  # pi = w_i / W in float64 (Eq. norm_mixture)
@@ -328,8 +380,6 @@ def _edge_costs_block(st: State, Sig, L, w, a, b, crn, app_dims):
     lnm = _log_gauss_chol(x, mum[None], Lm[None])
     g_sum = np.sum(np.logaddexp(lpa[None] + lna, lpb[None] + lnb) - lnm, axis=0)
     dgeo = g_sum / S
-    df = st.f[a, :app_dims] - st.f[b, :app_dims]
-    dapp = np.sum(df * df, axis=1)
     return dgeo + dapp, dgeo, dapp
 
 
@@ -497,7 +547,8 @@ def opacity_prune(st: State, tau: float) -> State:
 # ---------------------------------------------------------------------------
 def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
              seed: int = 0, S: int = 1, app_dims: int = 48, trace=None,
-             max_rounds: int = 1 << 30, workers: int = 1, tau=None, lod=None):
+             max_rounds: int = 1 << 30, workers: int = 1, tau=None, lod=None,
+             cost_mode: int = COST_MC):
     """Algorithm 1: the opacity pre-filter when ``tau`` is given (the target
     count is the caller's, fixed before the filter), then while N > N_tgt, rebuild
     the kNN graph, take the union edges, cost them, pick at most
@@ -518,7 +569,7 @@ def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
         keff = min(max(1, k), n - 1)
         nbr = knn(st.mu, keff, workers=workers)
         ei, ej = union_edges(nbr)
-        cost = edge_costs(st, ei, ej, crn_block(seed, r, S), app_dims)[0]
+        cost = edge_costs(st, ei, ej, crn_block(seed, r, S), app_dims, mode=cost_mode)[0]
         P = n - target_n
         pairs = greedy_pairs(ei, ej, cost, n, P)
         if pairs.shape[0] == 0:

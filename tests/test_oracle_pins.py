@@ -658,3 +658,53 @@ def test_merge_parents_hand_case_and_hierarchy():
         two = np.nonzero(cnt == 2)[0]
         got = sorted(tuple(sorted(lv.origin[par == p].tolist())) for p in two)
         assert got == sorted(map(tuple, trace[r].tolist()))
+
+
+def test_cost_stratified_unbiased_symmetric_and_zero():
+    """Component-stratified estimator: its mean is the KL (1-D quadrature on
+    equal covariances, many draws), it is exactly symmetric in the pair, and
+    it is exactly zero for an identical pair (p~ = q_m at every point)."""
+    rng = np.random.default_rng(11)
+    s = np.array([0.05, 0.02, 0.01])
+    q = _rand_quat(rng, 1)[0]
+    L = np.linalg.cholesky(O.covariance(s, q))
+    for pi, delta in ((0.3, 3.32), (0.5, 1.0), (0.8, 5.0)):
+        d = L @ np.array([delta, 0.0, 0.0])
+        st = _state([[0, 0, 0], d], [s, s], [q, q], [pi, 1 - pi])
+        crn = _iid_crn(rng, 1 << 16)
+        _, dg, _ = O.edge_costs(st, [0], [1], crn, mode=O.COST_MC_STRAT)
+        _, dg2, _ = O.edge_costs(st, [1], [0], crn, mode=O.COST_MC_STRAT)
+        kl = _kl_1d(pi, delta)
+        assert abs(dg[0] - kl) < 0.006 + 0.01 * kl, (pi, delta, dg[0], kl)
+        assert dg[0] == dg2[0]
+    st = _state([[0, 0, 0], [0, 0, 0]], [s, s], [q, q], [0.4, 0.7])
+    _, dg, _ = O.edge_costs(st, [0], [1], _iid_crn(rng, 64), mode=O.COST_MC_STRAT)
+    assert abs(dg[0]) < 1e-12
+
+
+def test_cost_bound_hand_closed_form_and_bound():
+    """Closed-form bound on equal isotropic covariances sigma^2 I, centres
+    delta apart along x (merged covariance sigma^2 I + c delta^2 e1 e1^T,
+    c = pi (1 - pi)), derived by hand; it is >= the true KL (1-D quadrature)
+    and zero for an identical pair or a massless partner."""
+    sig = 0.03
+    for pi, delta in ((0.3, 0.05), (0.5, 0.02), (0.8, 0.09)):
+        st = _state([[0, 0, 0], [delta, 0, 0]], np.full((2, 3), sig), [[1, 0, 0, 0]] * 2,
+                    [pi, 1 - pi])
+        _, dg, _ = O.edge_costs(st, [0], [1], np.zeros((1, 4), np.float32), mode=O.COST_BOUND)
+        v = sig ** 2 + pi * (1 - pi) * delta ** 2
+
+        def kl_to_m(w_other):
+            return 0.5 * (sig ** 2 / v + 2 + w_other ** 2 * delta ** 2 / v - 3
+                          + math.log(v / sig ** 2))
+        hand = pi * kl_to_m(1 - pi) + (1 - pi) * kl_to_m(pi)
+        assert abs(dg[0] - hand) < 1e-12 * max(1.0, hand), (dg[0], hand)
+        assert dg[0] >= _kl_1d(pi, delta / sig) - 1e-9
+    st = _state([[0.1, 0.2, 0.3]] * 2, [[0.01, 0.02, 0.03]] * 2, [[0.5, 0.5, 0.5, 0.5]] * 2,
+                [0.3, 0.9])
+    _, dg, _ = O.edge_costs(st, [0], [1], np.zeros((1, 4), np.float32), mode=O.COST_BOUND)
+    assert abs(dg[0]) < 1e-12
+    st = _state([[0, 0, 0], [0.05, 0, 0]], [[0.01, 0.02, 0.03]] * 2, [[1, 0, 0, 0]] * 2,
+                [0.5, 0.0])
+    _, dg, _ = O.edge_costs(st, [0], [1], np.zeros((1, 4), np.float32), mode=O.COST_BOUND)
+    assert abs(dg[0]) < 1e-12
