@@ -78,6 +78,17 @@ typedef struct {
 #define NANOGS_PREC_FP32 0  /* FP32 costs, FP64 for ill-conditioned pairs */
 #define NANOGS_PREC_FP64 1  /* every edge cost in FP64 */
 
+/* Geometric term D_geo of the edge cost (options.cost_mode). */
+#define NANOGS_COST_MC 0     /* Appendix A's Monte Carlo estimate of KL(p || q_m):
+                                per draw the component is picked by u < pi */
+#define NANOGS_COST_STRAT 1  /* same expectation, component-stratified: each
+                                draw's z is used in both components, weighted
+                                pi and 1 - pi (no component draw) */
+#define NANOGS_COST_BOUND 2  /* pi KL(N_i || q_m) + (1 - pi) KL(N_j || q_m)
+                                with the closed-form Gaussian KL of Appendix
+                                A: an upper bound of the mixture's
+                                divergence (joint convexity), no draws */
+
 typedef struct {
   int32_t S;          /* Monte Carlo draws per edge, 1..NANOGS_MAX_S (1) */
   int32_t app_dims;   /* SH coefficients in the appearance term, 1..48 (48) */
@@ -96,6 +107,8 @@ typedef struct {
   float tau;          /* opacity pre-filter of nanogs_simplify (Algorithm
                          1, before the loop): keep the splats with alpha >=
                          min(tau, median alpha); < 0 turns it off (-1) */
+  int32_t cost_mode;  /* NANOGS_COST_MC (default), NANOGS_COST_STRAT or
+                         NANOGS_COST_BOUND */
 } nanogs_options;
 
 /* Stages timed into nanogs_stats.stage_ms when options.timing is set. */

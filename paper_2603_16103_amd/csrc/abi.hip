@@ -33,6 +33,7 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
     r.d_origin = o->d_origin;
     r.timing = o->timing;
     r.tau = o->tau;
+    r.cost_mode = o->cost_mode;
   }
   if (r.S < 1 || r.S > NANOGS_MAX_S) {
     set_error("options.S must be in [1, 16]");
@@ -56,6 +57,11 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
   }
   if (std::isnan(r.tau) || std::isinf(r.tau)) {
     set_error("options.tau must be finite (< 0 turns the opacity pre-filter off)");
+    return NANOGS_EINVAL;
+  }
+  if (r.cost_mode != NANOGS_COST_MC && r.cost_mode != NANOGS_COST_STRAT &&
+      r.cost_mode != NANOGS_COST_BOUND) {
+    set_error("options.cost_mode must be NANOGS_COST_MC, NANOGS_COST_STRAT or NANOGS_COST_BOUND");
     return NANOGS_EINVAL;
   }
   *out = r;
@@ -341,6 +347,7 @@ void nanogs_default_options(nanogs_options* opt) {
   opt->max_rounds = 0;
   opt->timing = 0;
   opt->tau = -1.0f;
+  opt->cost_mode = NANOGS_COST_MC;
 }
 
 const char* nanogs_last_error(void) { return g_error.c_str(); }
@@ -544,7 +551,7 @@ void edge_cost_run(const nanogs_splats* s, int64_t n, const int32_t* ei, const i
     int* counters = c.take<int>(64);
     float* dcrn = c.take<float>(NG_CRN_ROW);
     NG_HIP(hipMemcpyAsync(dcrn, crn, sizeof(float) * 4 * o.S, hipMemcpyHostToDevice, stream));
-    const CrnTab args{dcrn, o.S, nullptr, nullptr};
+    const CrnTab args{dcrn, o.S, nullptr, nullptr, o.cost_mode};
     launch_pack_splats(s->mu, s->scale, s->quat, s->alpha, s->origin, (int)n, p.cen, p.lg, p.shp,
                        p.org, stream);
     if (o.precision == NANOGS_PREC_FP64) {

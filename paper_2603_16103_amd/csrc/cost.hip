@@ -21,6 +21,7 @@
 // instead of eps * cond; edges whose factors still look ill-conditioned
 // (a diagonal ratio below fb_ratio) or give a non-finite value are recomputed
 // in double from (s, q) by a second kernel.
+#include "../../include/nanogs.h"
 #include "internal.h"
 
 namespace ng {
@@ -123,11 +124,35 @@ NG_DEV Tri<T> chol_from_scale_rot(T s0, T s1, T s2, T w, T x, T y, T z) {
   return {g[0][0], g[1][0], g[1][1], g[2][0], g[2][1], l22};
 }
 
-// D_geo of one pair.  ratio receives the smallest diagonal ratio seen.
+// Back substitution with the transpose: h = L^-T y.
+template <typename T>
+NG_DEV V3<T> tri_solve_t(const Tri<T>& L, const V3<T>& y) {
+  V3<T> h;
+  h.z = y.z / L.a22;
+  h.y = (y.y - L.a21 * h.z) / L.a11;
+  h.x = (y.x - L.a10 * h.y - L.a20 * h.z) / L.a00;
+  return h;
+}
+
+// L^T h for lower-triangular L.
+template <typename T>
+NG_DEV V3<T> tri_mul_t(const Tri<T>& L, const V3<T>& h) {
+  return {L.a00 * h.x + L.a10 * h.y + L.a20 * h.z, L.a11 * h.y + L.a21 * h.z, L.a22 * h.z};
+}
+
+// Geometric term of the cost (NANOGS_COST_*):
+//   MC     the Monte Carlo estimate of Appendix A: each draw picks the
+//          component by u < pi and evaluates g = log p~(x) - log q_m(x);
+//   STRAT  each draw's z is used in both components, weighted pi and 1 - pi
+//          (the same expectation, no component draw);
+//   BOUND  pi KL(N_i || q_m) + (1 - pi) KL(N_j || q_m) in closed form (the
+//          single-Gaussian KL of Appendix A; joint convexity makes it an
+//          upper bound of the mixture's divergence), no draws.
+// ratio receives the smallest diagonal ratio seen.
 template <typename T>
 NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const Tri<T>& Lb,
                    T ldLa, T ldLb, T pa, T pb, double pdec, const float* __restrict__ cv, int S,
-                   T& ratio) {
+                   int mode, T& ratio) {
   const V3<T> d = {mua.x - mub.x, mua.y - mub.y, mua.z - mub.z};
   const Tri<T> LA = chol_of_mix(La, Lb, sqrt(pa), sqrt(pb));
   ratio = fmin(fmin(tri_ratio(La), tri_ratio(Lb)), tri_ratio(LA));
@@ -136,15 +161,30 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
   const T c = pa * pb;
   const T den = T(1) + c * ee;
   const T half_logdet_m = log(LA.a00 * LA.a11 * LA.a22) + T(0.5) * log1p(c * ee);
+  if (mode == NANOGS_COST_BOUND) {
+    // KL(N_c || q_m) = 1/2 [tr(Sm^-1 Sc) + w_o^2 |e|^2 / den - 3] +
+    // half log det Sm - log det L_c, with Sm^-1 = A^-1 - c A^-1 d d^T A^-1
+    // / den (A = L_A L_A^T) and w_o the other component's weight
+    const V3<T> h = tri_solve_t(LA, e);  // A^-1 d
+    auto kl = [&](const Tri<T>& Lc, T ldc, T w_other) {
+      const V3<T> c0 = tri_solve(LA, V3<T>{Lc.a00, Lc.a10, Lc.a20});
+      const V3<T> c1 = tri_solve(LA, V3<T>{T(0), Lc.a11, Lc.a21});
+      const V3<T> c2 = tri_solve(LA, V3<T>{T(0), T(0), Lc.a22});
+      const T tr_a = dot(c0, c0) + dot(c1, c1) + dot(c2, c2);
+      const V3<T> r = tri_mul_t(Lc, h);
+      const T tr = tr_a - c * dot(r, r) / den;
+      return T(0.5) * (tr + w_other * w_other * ee / den - T(3)) + half_logdet_m - ldc;
+    };
+    const T ka = pa > T(0) ? pa * kl(La, ldLa, pb) : T(0);
+    const T kb = pb > T(0) ? pb * kl(Lb, ldLb, pa) : T(0);
+    return ka + kb;
+  }
   const T lpa = log(pa), lpb = log(pb);
   const T ne = sqrt(ee);
   const T inv_ne = ne > T(0) ? T(1) / ne : T(0);
   const V3<T> eh = {e.x * inv_ne, e.y * inv_ne, e.z * inv_ne};
-  T acc = T(0);
-  for (int s = 0; s < S; ++s) {
-    const float u = cv[4 * s];
-    const V3<T> zz = {(T)cv[4 * s + 1], (T)cv[4 * s + 2], (T)cv[4 * s + 3]};
-    const bool ca = (double)u < pdec;
+  // g = log p~(x) - log q_m(x) at x = mu_c + L_c z (c = a or b)
+  auto g_at = [&](bool ca, const V3<T>& zz) {
     const Tri<T>& Lc = ca ? La : Lb;
     const Tri<T>& Lo = ca ? Lb : La;
     const T ldc = ca ? ldLa : ldLb;
@@ -167,7 +207,19 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
     const T lb = lpb + (ca ? lno : lnc);
     const T mx = fmax(la, lb), mn = fmin(la, lb);
     const T lse = mx + log1p(exp(mn - mx));
-    acc += lse - lnm;
+    return lse - lnm;
+  };
+  T acc = T(0);
+  for (int s = 0; s < S; ++s) {
+    const V3<T> zz = {(T)cv[4 * s + 1], (T)cv[4 * s + 2], (T)cv[4 * s + 3]};
+    if (mode == NANOGS_COST_STRAT) {
+      const T ga = pa > T(0) ? pa * g_at(true, zz) : T(0);
+      const T gb = pb > T(0) ? pb * g_at(false, zz) : T(0);
+      acc += ga + gb;
+    } else {
+      const float u = cv[4 * s];
+      acc += g_at((double)u < pdec, zz);
+    }
   }
   return acc / (T)S;
 }
@@ -266,7 +318,8 @@ __global__ void __launch_bounds__(256)
 k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
             const double* __restrict__ wd, const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
             const int* __restrict__ eb, int m, int n, int orient, const float* __restrict__ crn,
-            int S, const int* __restrict__ sg, const SegInfo* __restrict__ seg, float fb_ratio,
+            int S, int mode, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
+            float fb_ratio,
             float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
             int* __restrict__ fb_count, AdjOut adj) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,7 +350,7 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
     float ratio;
     const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const float dg = dgeo_pair<float>(v3(ca.x, ca.y, ca.z), v3(cb.x, cb.y, cb.z), La, Lb, pa1.z,
-                                      pb1.z, pa, pb, pad, cv, S, ratio);
+                                      pb1.z, pa, pb, pad, cv, S, mode, ratio);
     const float c = dg + dapp_f32(sh, a, b, app_dims);
     fb = !(ratio >= fb_ratio) || !isfinite(c);
     cost[e] = c;
@@ -312,7 +365,7 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
                  const float* __restrict__ sh, int app_dims, const int* __restrict__ ea,
                  const int* __restrict__ eb, int n, int orient, const int* __restrict__ list,
                  const int* __restrict__ d_count, int count_cap, const float* __restrict__ crn,
-                 int S, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
+                 int S, int mode, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
                  float* __restrict__ cost, float* __restrict__ dgeo_out, AdjOut adj) {
   const int count = d_count ? min(*d_count, count_cap) : count_cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
@@ -339,7 +392,7 @@ k_edge_cost_fp64(const float4* __restrict__ cen, const float4* __restrict__ shp,
     double ratio;
     const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
     const double dg = dgeo_pair<double>(v3<double>(ca.x, ca.y, ca.z), v3<double>(cb.x, cb.y, cb.z),
-                                        La, Lb, lda, ldb, pa, pb, pa, cv, S, ratio);
+                                        La, Lb, lda, ldb, pa, pb, pa, cv, S, mode, ratio);
     const float c = (float)(dg + dapp_f64(sh, a, b, app_dims));
     cost[e] = c;
     if (dgeo_out) dgeo_out[e] = (float)dg;
@@ -363,7 +416,8 @@ void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int
   const int bs = tuning_for(n).cost_block;
   k_edge_cost<<<blocks_for(m, bs), bs, 0, st>>>(cen, pre, pre_weights((float4*)pre, n), sh,
                                                   app_dims, ea, eb, m, n,
-                                                  orient ? 1 : 0, crn.tab, crn.S, crn.sg, crn.seg,
+                                                  orient ? 1 : 0, crn.tab, crn.S, crn.mode, crn.sg,
+                                                  crn.seg,
                                                   fb_ratio, cost, dgeo, fb_list, fb_count, adj);
   NG_LAUNCH_CHECK();
 }
@@ -376,7 +430,8 @@ void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh
   unsigned b = blocks_for(count_cap, 256);
   if (b > 2048) b = 2048;
   k_edge_cost_fp64<<<b, 256, 0, st>>>(cen, shp, sh, app_dims, ea, eb, n, orient ? 1 : 0, list,
-                                      d_count, count_cap, crn.tab, crn.S, crn.sg, crn.seg, cost,
+                                      d_count, count_cap, crn.tab, crn.S, crn.mode, crn.sg, crn.seg,
+                                      cost,
                                       dgeo, adj);
   NG_LAUNCH_CHECK();
 }

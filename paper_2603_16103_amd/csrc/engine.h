@@ -30,6 +30,7 @@ struct Opts {
   int* d_origin = nullptr;
   int timing = 0;
   float tau = -1.0f;  // opacity pre-filter threshold (< 0: off)
+  int cost_mode = NANOGS_COST_MC;
 };
 
 enum JobState { JOB_QUEUED = 0, JOB_RUNNING = 1, JOB_DRAINING = 2, JOB_DONE = 3, JOB_FAILED = 4 };

@@ -309,7 +309,7 @@ int Engine::step(StageTimer* T) {
   const long long knn_screens = host[3];
   if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
 
-  const CrnTab ct{W.crn, o_.S, sg, W.seg};
+  const CrnTab ct{W.crn, o_.S, sg, W.seg, o_.cost_mode};
   const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
   int* fb_count = W.counters + 1;
   fill_i32(fb_count, 0, 1, st_);

@@ -270,6 +270,7 @@ struct CrnTab {
   int S;
   const int* sg;
   const SegInfo* seg;
+  int mode = 0;  // geometric term (NANOGS_COST_*)
 };
 // Adjacency entries written by the cost kernels: each edge (src, tgt) puts
 // key (orderable cost << 32 | logical index of the other end) and the other

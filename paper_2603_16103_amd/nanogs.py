@@ -22,6 +22,9 @@ MAX_S = 16
 MAX_ROUNDS = 64
 PREC_FP32 = 0
 PREC_FP64 = 1
+COST_MC = 0
+COST_STRAT = 1
+COST_BOUND = 2
 STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "select",
           "merge", "setup", "output", "knn_exact", "knn_wave")
 NTIMED = len(STAGES)
@@ -52,7 +55,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("fb_ratio", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
                 ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p),
-                ("timing", ctypes.c_int32), ("tau", ctypes.c_float)]
+                ("timing", ctypes.c_int32), ("tau", ctypes.c_float),
+                ("cost_mode", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -216,7 +220,7 @@ def _workspace(nbytes: int):
 
 
 def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
-            d_trace=None, d_origin=None, timing=False, tau=-1.0) -> Options:
+            d_trace=None, d_origin=None, timing=False, tau=-1.0, cost_mode=COST_MC) -> Options:
     o = Options()
     load().nanogs_default_options(ctypes.byref(o))
     o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
@@ -225,6 +229,7 @@ def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, m
     o.d_origin = _ptr(d_origin).value if d_origin is not None else None
     o.timing = 1 if timing else 0
     o.tau = tau
+    o.cost_mode = cost_mode
     return o
 
 
