@@ -42,7 +42,9 @@ typedef enum {
   NANOGS_EWORKSPACE = 2,  /* workspace smaller than the size query asked for */
   NANOGS_ENONFINITE = 3,  /* an input value is NaN or infinite */
   NANOGS_EHIP = 4,        /* a HIP runtime call failed */
-  NANOGS_ENOTREADY = 5    /* the library found no usable HIP device */
+  NANOGS_ENOTREADY = 5,   /* the library found no usable HIP device */
+  NANOGS_ENOMEM = 6,      /* out of device or host memory */
+  NANOGS_ECANCELLED = 7   /* the job was cancelled (nanogs_batch_cancel) */
 } nanogs_status;
 
 #define NANOGS_SH_COEFFS 48   /* degree-3 spherical harmonics per splat */
@@ -253,9 +255,10 @@ nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr,
 
 /* Undirected union of the lists (Algorithm 1 UndirectedUnionEdges): every
  * unordered pair {i,j} with j in nbr(i) or i in nbr(j) exactly once, as
- * ei[e] < ej[e].  Order: by emitting row i, then by slot t, where row i emits
- * j = nbr[i][t] unless i > j and i is also in nbr(j).  ei/ej capacity n*k;
- * the edge count goes to the device int64 *d_m.  Entries < 0 are skipped. */
+ * ei[e] < ej[e], in lexicographic (ei, ej) order (so an edge's position is
+ * its rank in that order).  ei/ej capacity n*k; the edge count goes to the
+ * device int64 *d_m (no host read: the call does not synchronise).  Entries
+ * < 0 are skipped. */
 size_t nanogs_edges_workspace_bytes(int64_t n, int32_t k);
 nanogs_status nanogs_edges(const int32_t* nbr, int64_t n, int32_t k,
                            int32_t* ei, int32_t* ej, int64_t* d_m, void* ws,
@@ -312,6 +315,31 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej,
                             int64_t max_pairs, int32_t* partner,
                             int64_t* d_npairs, void* ws, size_t ws_bytes,
                             hipStream_t stream);
+
+/* Device-count forms of stages 2 and 3 (the three-stage decomposition of
+ * Sec. 3 chained on the device): the edge count is the device int64 *d_m
+ * (as nanogs_edges writes it), m_cap (host) bounds it and sizes the launches
+ * and the workspace (the _workspace_bytes queries above with m = m_cap);
+ * nanogs_select_dev's budget is the device int64 *d_max_pairs.  The draws
+ * d_crn are a DEVICE [S][4] array (options.S rows).  These calls neither
+ * read device memory back nor synchronise: a chain knn -> edges ->
+ * edge_cost_dev -> select_dev -> merge can be enqueued, or captured into a
+ * HIP graph, without the host seeing a count.  Results are those of
+ * nanogs_edge_cost / nanogs_select with m = *d_m, max_pairs = *d_max_pairs.
+ * Errors: as the host-count forms (checked on the host-side arguments only;
+ * *d_m is clamped to [0, m_cap], a negative budget keeps no pair). */
+nanogs_status nanogs_edge_cost_dev(const nanogs_splats* s, int64_t n,
+                                   const int32_t* ei, const int32_t* ej,
+                                   const int64_t* d_m, int64_t m_cap,
+                                   const float* d_crn, const nanogs_options* opt,
+                                   float* cost, float* dgeo, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+nanogs_status nanogs_select_dev(const int32_t* ei, const int32_t* ej,
+                                const float* cost, const int64_t* d_m,
+                                int64_t m_cap, int64_t n,
+                                const int64_t* d_max_pairs, int32_t* partner,
+                                int64_t* d_npairs, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
 
 /* ---- stage 4: merge + compaction (Sec. 3.3, Algorithm 1 MergePairs) ---- */
 
@@ -404,6 +432,14 @@ nanogs_status nanogs_batch_submit(nanogs_batch* b, const nanogs_gaussians* in,
                                   int64_t n, int64_t target_n, int32_t k,
                                   uint64_t seed, nanogs_gaussians* out,
                                   int32_t* d_origin, int32_t* job_id);
+
+/* Cancels a queued or running job: its state becomes -NANOGS_ECANCELLED at
+ * once, its output buffers are not written (those it was given may be
+ * released after the next nanogs_batch_step), and a running job's rows
+ * leave the working set at the next pass.  Cancelling a job that has
+ * finished, failed or been cancelled has no effect.  Errors: EINVAL (bad
+ * batch or job id). */
+nanogs_status nanogs_batch_cancel(nanogs_batch* b, int32_t job_id);
 
 /* One pass for every job in the working set; queued jobs join first, in
  * submission order, while their rows fit.  *n_done (nullable) receives the

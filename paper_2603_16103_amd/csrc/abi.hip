@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 
 #include "../../include/nanogs.h"
@@ -162,7 +163,10 @@ nanogs_status guarded(F&& f) {
     return f();
   } catch (const HipError& e) {
     set_error(e.msg);
-    return NANOGS_EHIP;
+    return e.code == hipErrorOutOfMemory ? NANOGS_ENOMEM : NANOGS_EHIP;
+  } catch (const std::bad_alloc& e) {
+    set_error(std::string("host allocation failed: ") + e.what());
+    return NANOGS_ENOMEM;
   } catch (const std::exception& e) {
     set_error(e.what());
     return NANOGS_EHIP;
@@ -541,27 +545,35 @@ nanogs_status check_edge_cost_args(const nanogs_splats* s, int64_t n, const int3
 }
 
 // The stage's launches over scratch memory ws of cost_bytes(n, m) bytes.
+// With d_m (device int64) the edge count is *d_m clamped to m, which then
+// only bounds it, and crn is a device array; otherwise crn is host memory.
 void edge_cost_run(const nanogs_splats* s, int64_t n, const int32_t* ei, const int32_t* ej,
                    int64_t m, const float* crn, const Opts& o, float* cost, float* dgeo,
-                   void* ws, hipStream_t stream) {
+                   void* ws, hipStream_t stream, const int64_t* d_m = nullptr) {
     Carver c(ws);
     Packed p = take_packed(c, n);
     float4* pre = c.take<float4>(pre_float4s(n));
     int* fb_list = c.take<int>(m);
-    int* counters = c.take<int>(64);
+    int* counters = c.take<int>(64);  // [0] fallback count, [2] edge count (d_m)
     float* dcrn = c.take<float>(NG_CRN_ROW);
-    NG_HIP(hipMemcpyAsync(dcrn, crn, sizeof(float) * 4 * o.S, hipMemcpyHostToDevice, stream));
-    const CrnTab args{dcrn, o.S, nullptr, nullptr, o.cost_mode};
+    const int* mcount = nullptr;
+    if (d_m) {
+      count_to_i32((const long long*)d_m, m, counters + 2, stream);
+      mcount = counters + 2;
+    } else {
+      NG_HIP(hipMemcpyAsync(dcrn, crn, sizeof(float) * 4 * o.S, hipMemcpyHostToDevice, stream));
+    }
+    const CrnTab args{d_m ? crn : dcrn, o.S, nullptr, nullptr, o.cost_mode};
     launch_pack_splats(s->mu, s->scale, s->quat, s->alpha, s->origin, (int)n, p.cen, p.lg, p.shp,
                        p.org, stream);
     if (o.precision == NANOGS_PREC_FP64) {
       launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, false, nullptr,
-                            nullptr, (int)m, args, cost, dgeo, AdjOut{}, stream);
+                            mcount, (int)m, args, cost, dgeo, AdjOut{}, stream);
     } else {
       launch_precompute(p.shp, (int)n, pre, stream);
       fill_i32(counters, 0, 1, stream);
       launch_edge_cost(p.cen, pre, s->sh, o.app_dims, ei, ej, (int)m, (int)n, false, args,
-                       o.fb_ratio, cost, dgeo, fb_list, counters, AdjOut{}, stream);
+                       o.fb_ratio, cost, dgeo, fb_list, counters, AdjOut{}, stream, mcount);
       launch_edge_cost_fp64(p.cen, p.shp, s->sh, o.app_dims, ei, ej, (int)n, false, fb_list,
                             counters, (int)m, args, cost, dgeo, AdjOut{}, stream);
     }
@@ -608,6 +620,21 @@ nanogs_status nanogs_edge_cost(const nanogs_splats* s, int64_t n, const int32_t*
   });
 }
 
+nanogs_status nanogs_edge_cost_dev(const nanogs_splats* s, int64_t n, const int32_t* ei,
+                                   const int32_t* ej, const int64_t* d_m, int64_t m_cap,
+                                   const float* d_crn, const nanogs_options* opt, float* cost,
+                                   float* dgeo, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    Opts o;
+    NG_CHECK(check_edge_cost_args(s, n, ei, ej, m_cap, d_crn, opt, cost, &o));
+    NG_CHECK(check_ptr(d_m, 8, "d_m"));
+    if (m_cap == 0) return NANOGS_OK;
+    NG_CHECK(check_ws(ws, ws_bytes, cost_bytes(n, m_cap)));
+    edge_cost_run(s, n, ei, ej, m_cap, d_crn, o, cost, dgeo, ws, stream, d_m);
+    return NANOGS_OK;
+  });
+}
+
 nanogs_status nanogs_edge_cost_noalloc(const nanogs_splats* s, int64_t n, const int32_t* ei,
                                        const int32_t* ej, int64_t m, const float* crn,
                                        const nanogs_options* opt, float* cost, float* dgeo,
@@ -632,7 +659,7 @@ nanogs_status nanogs_edge_cost_noalloc(const nanogs_splats* s, int64_t n, const 
 size_t nanogs_select_workspace_bytes(int64_t n, int64_t m) {
   if (n < 1) n = 1;
   if (m < 1) m = 1;
-  return select_adj_bytes(n, m) + select_temp_bytes(n, m, 1);
+  return select_adj_bytes(n, m) + select_temp_bytes(n, m, 1) + 256;
 }
 
 nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* cost, int64_t m,
@@ -667,6 +694,43 @@ nanogs_status nanogs_select(const int32_t* ei, const int32_t* ej, const float* c
     const long long P = max_pairs;
     select_pairs(adj, (int)n, nullptr, nullptr, 1, &P, partner, temp, stream,
                  (long long*)d_npairs, nullptr);
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_select_dev(const int32_t* ei, const int32_t* ej, const float* cost,
+                                const int64_t* d_m, int64_t m_cap, int64_t n,
+                                const int64_t* d_max_pairs, int32_t* partner, int64_t* d_npairs,
+                                void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> nanogs_status {
+    NG_CHECK(check_n(n, 1));
+    if (m_cap < 0 || m_cap >= (1ll << 30)) {
+      set_error("m_cap must be in [0, 2^30)");
+      return NANOGS_EINVAL;
+    }
+    NG_CHECK(check_ptr(d_m, 8, "d_m"));
+    NG_CHECK(check_ptr(d_max_pairs, 8, "d_max_pairs"));
+    NG_CHECK(check_ptr(d_npairs, 8, "d_npairs"));
+    if (n == 0) {
+      set_i64((long long*)d_npairs, 0, stream);
+      return NANOGS_OK;
+    }
+    NG_CHECK(check_ptr(partner, 4, "partner"));
+    if (m_cap > 0) {
+      NG_CHECK(check_ptr(ei, 4, "ei"));
+      NG_CHECK(check_ptr(ej, 4, "ej"));
+      NG_CHECK(check_ptr(cost, 4, "cost"));
+    }
+    const long long mm = m_cap < 1 ? 1 : m_cap;
+    const size_t body = select_adj_bytes(n, mm) + select_temp_bytes(n, mm, 1);
+    NG_CHECK(check_ws(ws, ws_bytes, body + 256));
+    int* mcount = (int*)((char*)ws + body);
+    count_to_i32((const long long*)d_m, m_cap, mcount, stream);
+    Adjacency adj;
+    build_adjacency(ei, ej, cost, m_cap, (int)n, &adj, ws, stream, mcount);
+    void* temp = (char*)ws + select_adj_bytes(n, mm);
+    select_pairs(adj, (int)n, nullptr, nullptr, 1, nullptr, partner, temp, stream,
+                 (long long*)d_npairs, nullptr, (const long long*)d_max_pairs);
     return NANOGS_OK;
   });
 }
@@ -821,6 +885,17 @@ nanogs_status nanogs_batch_submit(nanogs_batch* b, const nanogs_gaussians* in, i
     js.seed = seed;
     js.d_origin = d_origin;
     *job_id = b->eng->submit(js);
+    return NANOGS_OK;
+  });
+}
+
+nanogs_status nanogs_batch_cancel(nanogs_batch* b, int32_t job_id) {
+  return guarded([&]() -> nanogs_status {
+    if (!b || job_id < 0 || job_id >= b->eng->num_jobs()) {
+      set_error("bad batch or job id");
+      return NANOGS_EINVAL;
+    }
+    b->eng->cancel(job_id);
     return NANOGS_OK;
   });
 }

@@ -321,8 +321,9 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
             int S, int mode, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
             float fb_ratio,
             float* __restrict__ cost, float* __restrict__ dgeo_out, int* __restrict__ fb_list,
-            int* __restrict__ fb_count, AdjOut adj) {
+            int* __restrict__ fb_count, AdjOut adj, const int* __restrict__ d_mcount) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d_mcount) m = min(m, *d_mcount);
   bool live = e < m;
   bool fb = false;
   if (live) {
@@ -411,14 +412,15 @@ void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st) {
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
                       const int* ea, const int* eb, int m, int n, bool orient, const CrnTab& crn,
                       float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
-                      AdjOut adj, hipStream_t st) {
+                      AdjOut adj, hipStream_t st, const int* d_mcount) {
   if (m <= 0) return;
   const int bs = tuning_for(n).cost_block;
   k_edge_cost<<<blocks_for(m, bs), bs, 0, st>>>(cen, pre, pre_weights((float4*)pre, n), sh,
                                                   app_dims, ea, eb, m, n,
                                                   orient ? 1 : 0, crn.tab, crn.S, crn.mode, crn.sg,
                                                   crn.seg,
-                                                  fb_ratio, cost, dgeo, fb_list, fb_count, adj);
+                                                  fb_ratio, cost, dgeo, fb_list, fb_count, adj,
+                                                  d_mcount);
   NG_LAUNCH_CHECK();
 }
 

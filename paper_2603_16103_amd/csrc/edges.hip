@@ -114,6 +114,36 @@ __global__ void k_edge_minmax(const int* __restrict__ src, const int* __restrict
   }
 }
 
+// Sort keys of the lexicographic order: pass 0 keys each edge position by
+// its larger end, pass 1 (after a stable sort by that) by its smaller end;
+// positions at and past the count get `pad`, above every index.
+__global__ void k_lex_keys(const int* __restrict__ lo, const int* __restrict__ hi,
+                           const int* __restrict__ d_m, long long cap, unsigned pad, int pass,
+                           unsigned* __restrict__ key, int* __restrict__ val) {
+  const int m = *d_m;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < cap;
+       p += (long long)gridDim.x * blockDim.x) {
+    if (pass == 0) {
+      val[p] = (int)p;
+      key[p] = p < m ? (unsigned)hi[p] : pad;
+    } else {
+      const int e = val[p];
+      key[p] = e < m ? (unsigned)lo[e] : pad;
+    }
+  }
+}
+
+__global__ void k_lex_gather(const int* __restrict__ lo, const int* __restrict__ hi,
+                             const int* __restrict__ d_m, const int* __restrict__ order,
+                             int* __restrict__ ei, int* __restrict__ ej) {
+  const int m = *d_m;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    const int e = order[p];
+    ei[p] = lo[e];
+    ej[p] = hi[e];
+  }
+}
+
 __global__ void k_add_offsets(const int* __restrict__ a, const int* __restrict__ b, int n1,
                               int* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,7 +166,11 @@ size_t edges_public_bytes(long long n, int k) {
   c.take<int>(n * k);
   c.take<int>(n * k);
   c.take<int>(n + 1);
-  return c.bytes() + edges_temp_bytes(n, k);
+  c.take<int>(n * k);       // smaller ends
+  c.take<int>(n * k);       // larger ends
+  c.take<unsigned>(n * k);  // sort keys
+  c.take<int>(n * k);       // sort values
+  return c.bytes() + std::max(edges_temp_bytes(n, k), sort_temp_bytes(n * k));
 }
 
 void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es, long long* d_m,
@@ -172,17 +206,34 @@ void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es,
 
 void union_edges_public(const int* nbr, int n, int k, int* ei, int* ej, long long* d_m,
                         void* ws, hipStream_t st) {
+  const long long cap = (long long)n * k;
   Carver c(ws);
   EdgeSet es{};
-  es.src = c.take<int>((long long)n * k);
-  es.tgt = c.take<int>((long long)n * k);
+  es.src = c.take<int>(cap);
+  es.tgt = c.take<int>(cap);
   es.eoff = c.take<int>(n + 1);
+  int* lo = c.take<int>(cap);
+  int* hi = c.take<int>(cap);
+  unsigned* key = c.take<unsigned>(cap);
+  int* val = c.take<int>(cap);
   void* temp = (char*)ws + c.bytes();
   launch_union_edges(nbr, nullptr, n, k, es, d_m, temp, st);
   // the total sits at eoff[n]
-  unsigned b = blocks_for((long long)n * k, 256);
+  const int* tot = es.eoff + n;
+  unsigned b = blocks_for(cap, 256);
   if (b > 4096) b = 4096;
-  k_edge_minmax<<<b, 256, 0, st>>>(es.src, es.tgt, es.eoff + n, ei, ej);
+  k_edge_minmax<<<b, 256, 0, st>>>(es.src, es.tgt, tot, lo, hi);
+  NG_LAUNCH_CHECK();
+  // lexicographic (smaller, larger) order by two stable sorts over the
+  // capacity (no host read of the count)
+  int bits = 1;
+  while ((1ll << bits) <= (long long)n) ++bits;
+  for (int pass = 0; pass < 2; ++pass) {
+    k_lex_keys<<<b, 256, 0, st>>>(lo, hi, tot, cap, (unsigned)n, pass, key, val);
+    NG_LAUNCH_CHECK();
+    sort_pairs_u32(key, val, cap, bits, temp, st);
+  }
+  k_lex_gather<<<b, 256, 0, st>>>(lo, hi, tot, val, ei, ej);
   NG_LAUNCH_CHECK();
 }
 

@@ -82,6 +82,10 @@ class Engine {
   Engine& operator=(const Engine&) = delete;
 
   int submit(const JobSpec& spec);  // returns the job id
+  // Cancels a queued or running job (state FAILED, status ECANCELLED; a
+  // running job's rows leave the working set at the next pass and its output
+  // is not written).  Returns false if the job had already finished.
+  bool cancel(int id);
   // One pass for every live job (queued jobs join first if they fit).
   // Returns the number of jobs that completed (or failed) in this step.
   int step(StageTimer* T = nullptr);

@@ -146,6 +146,21 @@ int Engine::submit(const JobSpec& spec) {
 
 long long Engine::rows_in_use() const { return Ntot_; }
 
+bool Engine::cancel(int id) {
+  Job& j = jobs_[id];
+  if (j.state == JOB_QUEUED) {
+    queue_.erase(std::find(queue_.begin(), queue_.end(), id));
+  } else if (j.state != JOB_RUNNING) {
+    return false;
+  }
+  // a running job stays in live_ until the next pass, which treats every
+  // segment that is not running as rows to drop
+  j.state = JOB_FAILED;
+  j.status = NANOGS_ECANCELLED;
+  j.error = "cancelled";
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // job set-up: Morton order of the job's centres, activation into rows
 // [Ntot, Ntot + n) of the working set, SH rows, non-finite check
@@ -395,7 +410,7 @@ int Engine::step(StageTimer* T) {
   for (int i = 0; i < nseg; ++i) {
     Job& j = jobs_[live_[i]];
     if (j.state != JOB_RUNNING) {
-      j.state = JOB_DONE;
+      if (j.state == JOB_DRAINING) j.state = JOB_DONE;
       continue;
     }
     j.N -= hM[i];

@@ -33,10 +33,11 @@ void set_error(const std::string& msg);
 
 struct HipError {
   std::string msg;
+  hipError_t code = hipErrorUnknown;
 };
 
 inline void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) throw HipError{std::string(what) + ": " + hipGetErrorString(e)};
+  if (e != hipSuccess) throw HipError{std::string(what) + ": " + hipGetErrorString(e), e};
 }
 #define NG_HIP(x) ::ng::hip_check((x), #x)
 #define NG_LAUNCH_CHECK() ::ng::hip_check(hipGetLastError(), "kernel launch")
@@ -156,6 +157,8 @@ size_t scan_temp_bytes(long long n);
 void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* temp,
                         hipStream_t st);
 void fill_i32(int* p, int v, long long n, hipStream_t st);
+// *out = min(max(*d, 0), cap) as int32 (device to device, one thread).
+void count_to_i32(const long long* d, long long cap, int* out, hipStream_t st);
 void fill_u64(unsigned long long* p, unsigned long long v, long long n, hipStream_t st);
 void set_i64(long long* d, long long v, hipStream_t st);
 // Small page-locked host buffer (64 int64 slots) for counts read back by the
@@ -287,14 +290,15 @@ struct AdjOut {
 inline long long pre_float4s(long long n) { return 2 * n + (n + 1) / 2; }
 inline double* pre_weights(float4* pre, long long n) { return (double*)(pre + 2 * n); }
 void launch_precompute(const float4* shp, int n, float4* pre, hipStream_t st);
-// FP32 cost of edges [0, m); edges needing FP64 are appended to fb_list.
-// Edges with an end outside [0, n) get a NaN cost.  orient: the end with the
-// smaller logical index (cen[].w) is the mixture's first component;
-// otherwise ea[e] is.  adj.akey nullable.
+// FP32 cost of edges [0, m) (m clamped to the device count *d_mcount when
+// that is given); edges needing FP64 are appended to fb_list.  Edges with an
+// end outside [0, n) get a NaN cost.  orient: the end with the smaller
+// logical index (cen[].w) is the mixture's first component; otherwise ea[e]
+// is.  adj.akey nullable.
 void launch_edge_cost(const float4* cen, const float4* pre, const float* sh, int app_dims,
                       const int* ea, const int* eb, int m, int n, bool orient, const CrnTab& crn,
                       float fb_ratio, float* cost, float* dgeo, int* fb_list, int* fb_count,
-                      AdjOut adj, hipStream_t st);
+                      AdjOut adj, hipStream_t st, const int* d_mcount = nullptr);
 // FP64 cost of the listed edges (list nullable: all edges [0, count_host)).
 void launch_edge_cost_fp64(const float4* cen, const float4* shp, const float* sh, int app_dims,
                            const int* ea, const int* eb, int n, bool orient, const int* list,
@@ -309,9 +313,10 @@ struct Adjacency {
 };
 size_t select_temp_bytes(long long n, long long m, int nseg);
 size_t select_adj_bytes(long long n, long long m);
-// Adjacency of an arbitrary edge list (cost per edge, caller numbering).
+// Adjacency of an arbitrary edge list (cost per edge, caller numbering);
+// m is clamped to the device count *d_mcount when that is given.
 void build_adjacency(const int* ea, const int* eb, const float* cost, long long m, int n,
-                     Adjacency* adj, void* ws, hipStream_t st);
+                     Adjacency* adj, void* ws, hipStream_t st, const int* d_mcount = nullptr);
 struct SelectResult {
   long long pairs;
   int iters;
@@ -320,10 +325,12 @@ struct SelectResult {
 // the nseg segments (row -> segment in sg, nullable when nseg = 1) keeps at
 // most hP[s] pairs (host array); hM (host, nullable) receives the pairs kept
 // per segment, d_npairs (device int64, nullable) segment 0's count.
-// Synchronises st.
+// Synchronises st, unless dP is given: then (nseg = 1) the budget is the
+// device int64 *dP, hP and hM are unused, nothing is read back and the
+// result's fields are -1.
 SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
                           const long long* hP, int* partner, void* temp, hipStream_t st,
-                          long long* d_npairs, long long* hM);
+                          long long* d_npairs, long long* hM, const long long* dP = nullptr);
 
 // merge.hip -- MPMM merge + stable compaction in working layout
 size_t merge_temp_bytes(long long n);

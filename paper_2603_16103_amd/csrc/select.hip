@@ -36,7 +36,8 @@ NG_DEV int logical(const int* lg, int p) { return lg ? lg[p] : p; }
 NG_DEV bool edge_ok(int a, int b, int n) { return a >= 0 && a < n && b >= 0 && b < n && a != b; }
 
 __global__ void k_deg_count(const int* __restrict__ ea, const int* __restrict__ eb, int m, int n,
-                            int* __restrict__ deg) {
+                            int* __restrict__ deg, const int* __restrict__ d_mcount) {
+  if (d_mcount) m = min(m, *d_mcount);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
     const int a = ea[e], b = eb[e];
     if (!edge_ok(a, b, n)) continue;
@@ -53,7 +54,9 @@ NG_DEV unsigned long long entry_key(float c, int other_logical) {
 __global__ void k_adj_fill(const int* __restrict__ ea, const int* __restrict__ eb,
                            const float* __restrict__ cost, int m, int n,
                            const int* __restrict__ aoff, int* __restrict__ cursor,
-                           unsigned long long* __restrict__ akey, int* __restrict__ au) {
+                           unsigned long long* __restrict__ akey, int* __restrict__ au,
+                           const int* __restrict__ d_mcount) {
+  if (d_mcount) m = min(m, *d_mcount);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
     const int a = ea[e], b = eb[e];
     if (!edge_ok(a, b, n)) continue;
@@ -481,7 +484,7 @@ size_t select_adj_bytes(long long n, long long m) {
 }
 
 void build_adjacency(const int* ea, const int* eb, const float* cost, long long m, int n,
-                     Adjacency* adj, void* ws, hipStream_t st) {
+                     Adjacency* adj, void* ws, hipStream_t st, const int* d_mcount) {
   Carver c(ws);
   int* deg = c.take<int>(n + 1);
   int* cursor = c.take<int>(n + 1);
@@ -494,21 +497,22 @@ void build_adjacency(const int* ea, const int* eb, const float* cost, long long 
   if (m > 0) {
     unsigned b = blocks_for(m, 256);
     if (b > 4096) b = 4096;
-    k_deg_count<<<b, 256, 0, st>>>(ea, eb, (int)m, n, deg);
+    k_deg_count<<<b, 256, 0, st>>>(ea, eb, (int)m, n, deg, d_mcount);
     NG_LAUNCH_CHECK();
   }
   scan_exclusive_i32(deg, adj->aoff, n + 1, nullptr, stemp, st);
   if (m > 0) {
     unsigned b = blocks_for(m, 256);
     if (b > 4096) b = 4096;
-    k_adj_fill<<<b, 256, 0, st>>>(ea, eb, cost, (int)m, n, adj->aoff, cursor, adj->akey, adj->au);
+    k_adj_fill<<<b, 256, 0, st>>>(ea, eb, cost, (int)m, n, adj->aoff, cursor, adj->akey, adj->au,
+                                  d_mcount);
     NG_LAUNCH_CHECK();
   }
 }
 
 SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
                           const long long* hP, int* partner, void* temp, hipStream_t st,
-                          long long* d_npairs, long long* hM) {
+                          long long* d_npairs, long long* hM, const long long* dP) {
   Carver c(temp);
   int* pick = c.take<int>(n);
   unsigned* pcost = c.take<unsigned>(n);
@@ -567,6 +571,17 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
                                        counters, (it - 1) & 1, pick, pcost, lg, pair_a, pair_b,
                                        pair_c, counters + 2, ps, counters + 3);
   NG_LAUNCH_CHECK();
+  if (dP) {
+    // device budget, single segment: keep the P smallest of the matching
+    k_topp_seg<<<1, 1024, 0, st>>>(pair_a, pair_b, pair_c, nullptr, pstart, pend, counters + 2, dP,
+                                   lg, partner, mseg);
+    NG_LAUNCH_CHECK();
+    if (d_npairs) {
+      k_store_npairs<<<1, 64, 0, st>>>(mseg, d_npairs);
+      NG_LAUNCH_CHECK();
+    }
+    return SelectResult{-1, -1};
+  }
   NG_HIP(hipMemcpyAsync(host, counters, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   NG_HIP(hipStreamSynchronize(st));
   r.iters = it + ((const int*)host)[3];

@@ -137,6 +137,18 @@ void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* 
   NG_LAUNCH_CHECK();
 }
 
+__global__ void k_count_i32(const long long* __restrict__ d, long long cap, int* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const long long v = *d;
+    *out = (int)(v < 0 ? 0 : (v > cap ? cap : v));
+  }
+}
+
+void count_to_i32(const long long* d, long long cap, int* out, hipStream_t st) {
+  k_count_i32<<<1, 64, 0, st>>>(d, cap, out);
+  NG_LAUNCH_CHECK();
+}
+
 void fill_i32(int* p, int v, long long n, hipStream_t st) {
   if (n <= 0) return;
   k_fill_i32<<<blocks_for(n, 256), 256, 0, st>>>(p, v, n);

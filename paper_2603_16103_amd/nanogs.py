@@ -29,7 +29,9 @@ STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "
           "merge", "setup", "output", "knn_exact", "knn_wave")
 NTIMED = len(STAGES)
 
-STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY"}
+STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY",
+          6: "ENOMEM", 7: "ECANCELLED"}
+ECANCELLED = 7
 
 
 class NanoGSError(RuntimeError):
@@ -140,6 +142,10 @@ _SIGS = {
     "nanogs_prune_workspace_bytes": (_SZ, [_I64]),
     "nanogs_prune": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, ctypes.c_float,
                                     ctypes.POINTER(Splats), _P, _P, _SZ, _P]),
+    "nanogs_edge_cost_dev": (ctypes.c_int, [ctypes.POINTER(Splats), _I64, _P, _P, _P, _I64, _P,
+                                            ctypes.POINTER(Options), _P, _P, _P, _SZ, _P]),
+    "nanogs_select_dev": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "nanogs_batch_cancel": (ctypes.c_int, [_P, _I32]),
     "nanogs_select_workspace_bytes": (_SZ, [_I64, _I64]),
     "nanogs_select": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "nanogs_merge_workspace_bytes": (_SZ, [_I64]),
@@ -519,6 +525,43 @@ def select(ei, ej, cost, n: int, max_pairs: int):
     return partner[:n], int(dn.item())
 
 
+def edge_cost_dev(s: SplatTensors, ei, ej, d_m, d_crn, opts: Options | None = None, ws=None):
+    """edge_cost with the edge count on the device: d_m int64 [1] cuda,
+    ei/ej of capacity m_cap >= *d_m, d_crn float32 [S,4] cuda.  Returns cost
+    [m_cap] (entries at and past *d_m untouched).  Reads nothing back, so it
+    may be captured into a CUDA/HIP graph (pass ws to avoid allocating)."""
+    torch = _torch()
+    lib = load()
+    m_cap = int(ei.shape[0])
+    opts = opts if opts is not None else options()
+    opts.S = int(d_crn.shape[0])
+    cost = torch.empty(max(m_cap, 1), dtype=torch.float32, device="cuda")
+    nb = lib.nanogs_edge_cost_workspace_bytes(s.n, m_cap)
+    ws = ws if ws is not None else _workspace(nb)
+    ss = s.struct()
+    _check(lib.nanogs_edge_cost_dev(ctypes.byref(ss), s.n, _ptr(ei), _ptr(ej), _ptr(d_m), m_cap,
+                                    _ptr(d_crn), ctypes.byref(opts), _ptr(cost), None, _ptr(ws),
+                                    nb, _stream()))
+    return cost[:m_cap]
+
+
+def select_dev(ei, ej, cost, d_m, n: int, d_max_pairs, ws=None):
+    """select with the edge count and the budget on the device (int64 [1]
+    cuda tensors) -> (partner [n] int32, d_npairs int64 [1] cuda).  Reads
+    nothing back."""
+    torch = _torch()
+    lib = load()
+    m_cap = int(ei.shape[0])
+    partner = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    dn = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_select_workspace_bytes(n, m_cap)
+    ws = ws if ws is not None else _workspace(nb)
+    _check(lib.nanogs_select_dev(_ptr(ei), _ptr(ej), _ptr(cost), _ptr(d_m), m_cap, n,
+                                 _ptr(d_max_pairs), _ptr(partner), _ptr(dn), _ptr(ws), nb,
+                                 _stream()))
+    return partner[:n], dn
+
+
 def merge(s: SplatTensors, partner):
     """MPMM merge + compaction -> SplatTensors of the new count."""
     torch = _torch()
@@ -590,6 +633,11 @@ class Batch:
                                           ctypes.byref(os_), _ptr(origin), ctypes.byref(jid)))
         self._keep[jid.value] = (g, out, origin)
         return jid.value
+
+    def cancel(self, jid: int):
+        """Cancels a queued or running job (state -ECANCELLED); no effect on
+        a finished one.  Its tensors are kept until release()."""
+        _check(load().nanogs_batch_cancel(self._h, jid))
 
     def step(self) -> int:
         d = ctypes.c_int32(0)

@@ -117,3 +117,47 @@ def test_batch_failures_are_isolated(gpu_lib):
     ref, _ = _alone(ng, good, t, k, sd)
     _same([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)], ref)
     b.close()
+
+
+def test_batch_cancel_queued_and_running(gpu_lib):
+    """A cancelled job leaves (queued: at once; running: at the next pass)
+    with state -ECANCELLED and no output; the others' results are unchanged
+    and its rows are freed."""
+    ng = gpu_lib
+    scenes = [_scene(s) for s in SPECS]
+    b = ng.Batch(max_rows=9000, max_k=24, max_jobs=4)
+    jobs = [b.submit(ng.GaussianTensors.from_scene(sc), t, k=k, seed=sd)
+            for sc, t, k, sd in scenes]
+    b.step()
+    states = [b.job(j)[0] for j in jobs]
+    log("states after one step", states, "rows", b.rows_in_use())
+    running = [j for j, s in zip(jobs, states) if s == ng.JOB_RUNNING]
+    queued = [j for j, s in zip(jobs, states) if s == ng.JOB_QUEUED]
+    assert running and queued
+    victims = [running[0], queued[0]]
+    for v in victims:
+        b.cancel(v)
+        assert b.job(v)[0] == -ng.ECANCELLED
+    rows_before = b.rows_in_use()
+    b.step()
+    assert b.rows_in_use() <= rows_before - scenes[jobs.index(running[0])][0].n + 9000
+    b.run()
+    for v in victims:
+        state, n_out, _ = b.job(v)
+        assert state == -ng.ECANCELLED and n_out == 0
+        b.cancel(v)  # no effect
+    for i, j in enumerate(jobs):
+        if j in victims:
+            continue
+        assert b.job(j)[0] == ng.JOB_DONE
+        b.cancel(j)  # finished: no effect
+        assert b.job(j)[0] == ng.JOB_DONE
+        sc, t, k, sd = scenes[i]
+        res = b.result(j)
+        ref, _ = _alone(ng, sc, t, k, sd)
+        _same([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot, res.opacity, res.sh)],
+              ref)
+    assert b.rows_in_use() == 0
+    with pytest.raises(ng.NanoGSError):
+        b.cancel(len(jobs) + 5)
+    b.close()

@@ -108,27 +108,29 @@ def test_knn_small_n(gpu_lib, n):
 # --------------------------------------------------------------------------
 # union edges
 # --------------------------------------------------------------------------
-def _emission_order(nbr):
-    n, k = nbr.shape
-    sets = [set(r[r >= 0].tolist()) for r in nbr]
-    out = []
-    for i in range(n):
-        for j in nbr[i]:
-            if j < 0:
-                continue
-            if i < j or i not in sets[j]:
-                out.append((min(i, j), max(i, j)))
-    return out
-
-
 def test_edges_bit_exact(gpu_lib, c1):
+    """The union edges in lexicographic (i, j) order, element by element."""
     sc, (mu, *_ ) = c1
     nbr = O.knn(mu, 16)
     ei, ej = gpu_lib.edges(_t(nbr))
-    got = list(zip(ei.cpu().numpy().tolist(), ej.cpu().numpy().tolist()))
-    assert got == _emission_order(nbr)
     ri, rj = O.union_edges(nbr)
-    assert sorted(got) == list(zip(ri.tolist(), rj.tolist()))
+    np.testing.assert_array_equal(ei.cpu().numpy(), ri)
+    np.testing.assert_array_equal(ej.cpu().numpy(), rj)
+
+
+@pytest.mark.parametrize("n,k", [(1, 16), (2, 1), (7, 32), (5000, 3)])
+def test_edges_small_and_padded(gpu_lib, n, k):
+    """Rows padded with -1 (k_eff < k), tiny sets, a ragged count."""
+    rng = np.random.default_rng(n + k)
+    mu = rng.normal(size=(n, 3)).astype(np.float32)
+    keff = min(k, n - 1)
+    nbr = np.full((n, k), -1, np.int32)
+    if keff > 0:
+        nbr[:, :keff] = O.knn(mu, keff)
+    ei, ej = gpu_lib.edges(_t(nbr))
+    ri, rj = O.union_edges(nbr)
+    np.testing.assert_array_equal(ei.cpu().numpy(), ri)
+    np.testing.assert_array_equal(ej.cpu().numpy(), rj)
 
 
 # --------------------------------------------------------------------------
