@@ -9,4 +9,5 @@ from .nanogs_oracle import (  # noqa: F401
     knn, union_edges, edge_costs, greedy_pairs, mpmm, merge_pairs,
     scale_rot_from_cov, quat_from_rotation, simplify, deactivate,
     opacity_prune, State, mass, merge_parents, gauss_kl, COST_MC, COST_MC_STRAT, COST_BOUND,
+    local_refresh, pass_budget,
 )

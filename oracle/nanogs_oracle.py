@@ -527,6 +527,47 @@ def merge_parents(n: int, pairs: np.ndarray) -> np.ndarray:
     return parent
 
 
+def local_refresh(centres: np.ndarray, keff: int, prev_nbr: np.ndarray, parent: np.ndarray,
+                  workers: int = 1):
+    """Local neighbourhood refresh (Sec. 3.4): re-query the kNN only around
+    the splats a pass formed.  READING: a splat of the new set is dirty when
+    it was formed by a merge, or when its list of the previous pass named a
+    splat that took part in a merge; a dirty splat gets its exact kNN over
+    the whole new set, every other splat keeps its previous list with the
+    indices carried to the new set (``parent``: new index of each old one,
+    as merge_parents gives it).  Returns (nbr [n, keff], dirty mask)."""
+    centres = np.asarray(centres)
+    n_new = centres.shape[0]
+    parent = np.asarray(parent, dtype=np.int64)
+    cnt = np.bincount(parent, minlength=n_new)
+    merged = cnt == 2
+    # the old index of every splat that survived unmerged
+    old_of = np.full(n_new, -1, dtype=np.int64)
+    surv = ~merged[parent]
+    old_of[parent[surv]] = np.nonzero(surv)[0]
+    nbr = np.empty((n_new, keff), dtype=np.int64)
+    dirty = merged.copy()
+    kept = np.nonzero(~merged)[0]
+    carried = parent[np.asarray(prev_nbr, dtype=np.int64)[old_of[kept]]]
+    touched = merged[carried].any(axis=1)
+    dirty[kept[touched]] = True
+    nbr[kept[~touched]] = carried[~touched]
+    rows = np.nonzero(dirty)[0]
+    if rows.size:
+        nbr[rows] = knn(centres, keff, queries=rows, workers=workers)
+    return nbr, dirty
+
+
+def pass_budget(n: int, target_n: int, pass_frac: float = 0.0) -> int:
+    """P = N - N_tgt (Algorithm 1).  With pass_frac > 0 (progressive
+    collapses, Sec. 3.4) a pass takes at most max(1, floor(f N)) pairs, f
+    being pass_frac rounded to float32 (the option's storage type)."""
+    P = n - target_n
+    if pass_frac > 0.0:
+        P = min(P, max(1, int(np.floor(float(np.float32(pass_frac)) * n))))
+    return P
+
+
 # ---------------------------------------------------------------------------
 # Opacity pre-filter (Algorithm 1, before the loop)
 # ---------------------------------------------------------------------------
@@ -548,7 +589,8 @@ def opacity_prune(st: State, tau: float) -> State:
 def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
              seed: int = 0, S: int = 1, app_dims: int = 48, trace=None,
              max_rounds: int = 1 << 30, workers: int = 1, tau=None, lod=None,
-             cost_mode: int = COST_MC):
+             cost_mode: int = COST_MC, refresh: str = "full", pass_frac: float = 0.0,
+             requeried=None):
     """Algorithm 1: the opacity pre-filter when ``tau`` is given (the target
     count is the caller's, fixed before the filter), then while N > N_tgt, rebuild
     the kNN graph, take the union edges, cost them, pick at most
@@ -557,20 +599,32 @@ def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
     (alpha clipped to [0, 1]).  When ``trace`` is a list, each pass appends
     the provenance pairs (origin_i, origin_j) it merged.  When ``lod`` is a
     list, each pass appends (the set at its start, merge_parents of its
-    pairs): the coarse-to-fine hierarchy (Sec. 3.4).  ``workers``:
-    threads for the per-query and per-edge steps (results do not change)."""
+    pairs): the coarse-to-fine hierarchy (Sec. 3.4).  ``refresh``: "full"
+    rebuilds the kNN graph every pass (the paper's setting), "local" keeps
+    the lists of the splats no merge touched (local_refresh) from the second
+    pass on; ``requeried`` (list) receives the rows queried per pass.
+    ``pass_frac``: per-pass pair cap (pass_budget).  ``workers``: threads
+    for the per-query and per-edge steps (results do not change)."""
     st = activate(pos, log_scale, rot, opacity, sh)
     if tau is not None:
         st = opacity_prune(st, tau)
     target_n = max(int(target_n), 1)
     r = 0
+    prev = None  # (lists, parent map) of the previous pass
     while st.n > target_n and r < max_rounds:
         n = st.n
         keff = min(max(1, k), n - 1)
-        nbr = knn(st.mu, keff, workers=workers)
+        if refresh == "local" and prev is not None and prev[0].shape[1] == keff:
+            nbr, dirty = local_refresh(st.mu, keff, prev[0], prev[1], workers=workers)
+            nq = int(dirty.sum())
+        else:
+            nbr = knn(st.mu, keff, workers=workers)
+            nq = n
+        if requeried is not None:
+            requeried.append(nq)
         ei, ej = union_edges(nbr)
         cost = edge_costs(st, ei, ej, crn_block(seed, r, S), app_dims, mode=cost_mode)[0]
-        P = n - target_n
+        P = pass_budget(n, target_n, pass_frac)
         pairs = greedy_pairs(ei, ej, cost, n, P)
         if pairs.shape[0] == 0:
             break
@@ -579,6 +633,7 @@ def simplify(pos, log_scale, rot, opacity, sh, target_n: int, k: int,
         if lod is not None:
             lod.append((State(st.mu.copy(), st.s.copy(), st.q.copy(), st.alpha.copy(),
                               st.f.copy(), st.origin.copy()), merge_parents(n, pairs)))
+        prev = (nbr, merge_parents(n, pairs))
         st = merge_pairs(st, pairs)
         r += 1
     st.alpha = np.clip(st.alpha, 0.0, 1.0)

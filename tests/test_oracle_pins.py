@@ -708,3 +708,98 @@ def test_cost_bound_hand_closed_form_and_bound():
                 [0.5, 0.0])
     _, dg, _ = O.edge_costs(st, [0], [1], np.zeros((1, 4), np.float32), mode=O.COST_BOUND)
     assert abs(dg[0]) < 1e-12
+
+
+def _brute_knn(c, k, rows, among=None):
+    """The definition: sort every other allowed row by (d^2, index)."""
+    c = np.asarray(c, dtype=np.float64)
+    among = np.arange(c.shape[0]) if among is None else np.asarray(among)
+    out = []
+    for i in rows:
+        cand = [j for j in among if j != i]
+        d = [((c[i, 0] - c[j, 0]) ** 2 + (c[i, 1] - c[j, 1]) ** 2) + (c[i, 2] - c[j, 2]) ** 2
+             for j in cand]
+        order = sorted(range(len(cand)), key=lambda t: (d[t], cand[t]))
+        out.append([cand[t] for t in order[:k]])
+    return np.array(out, dtype=np.int64).reshape(len(rows), k)
+
+
+def test_local_refresh_dirty_rows_exact_clean_rows_unchanged_neighbourhood():
+    """Dirty rows (formed by a merge, or with a merged splat in their last
+    list) get the exact kNN of the new set; every other row's list equals
+    the exact kNN among the rows no merge touched (its old neighbours did not
+    move and nothing else among those rows came closer)."""
+    rng = np.random.default_rng(5)
+    n, k = 240, 6
+    sc = gen_scene(n, 17, n_planes=2, n_spheres=1)
+    st = O.activate(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh)
+    prev = O.knn(st.mu, k)
+    # a few disjoint pairs among mutual neighbours
+    pairs, used = [], set()
+    for i in rng.permutation(n):
+        j = int(prev[i, 0])
+        if i not in used and j not in used and i < j:
+            pairs.append((i, j))
+            used |= {i, j}
+        if len(pairs) == 12:
+            break
+    pairs = np.array(pairs)
+    parent = O.merge_parents(n, pairs)
+    new = O.merge_pairs(st, pairs)
+    nbr, dirty = O.local_refresh(new.mu, k, prev, parent)
+    merged_new = {int(parent[a]) for a, _ in pairs}
+    merged_old = set(pairs.ravel().tolist())
+    # dirty set by its definition, old list by old list
+    want = set(merged_new)
+    for o in range(n):
+        if o not in merged_old and any(int(e) in merged_old for e in prev[o]):
+            want.add(int(parent[o]))
+    assert set(np.nonzero(dirty)[0].tolist()) == want
+    rows = sorted(want)
+    np.testing.assert_array_equal(nbr[rows], _brute_knn(new.mu, k, rows))
+    untouched = [v for v in range(new.n) if v not in merged_new]
+    clean = [v for v in range(new.n) if v not in want]
+    assert clean
+    np.testing.assert_array_equal(nbr[clean], _brute_knn(new.mu, k, clean, among=untouched))
+
+
+def test_local_refresh_misses_a_closer_merged_splat():
+    """Hand case: A's only neighbour B (at distance 2) did not merge, so A
+    keeps it, although the merge of C and D (each 2.1 away) formed a splat
+    1.48 away that a full rebuild finds."""
+    mu_old = np.array([[0, 0, 0], [2, 0, 0], [-2.1, 0, 0], [0, 2.1, 0]], float)  # A B C D
+    prev = _brute_knn(mu_old, 1, range(4))
+    assert prev[0, 0] == 1
+    parent = O.merge_parents(4, np.array([[2, 3]]))  # C, D -> new index 2
+    mu_new = np.array([[0, 0, 0], [2, 0, 0], [-1.05, 1.05, 0]], float)
+    nbr, dirty = O.local_refresh(mu_new, 1, prev, parent)
+    assert dirty.tolist() == [False, False, True]  # B's neighbour A did not merge either
+    assert nbr[0, 0] == 1                      # kept
+    assert O.knn(mu_new, 1)[0, 0] == 2         # full rebuild
+    np.testing.assert_array_equal(nbr[2], _brute_knn(mu_new, 1, [2])[0])
+
+
+def test_pass_budget_hand_values():
+    assert O.pass_budget(100, 10) == 90
+    assert O.pass_budget(100, 10, 0.1) == 10
+    assert O.pass_budget(100, 10, 0.001) == 1
+    assert O.pass_budget(100, 10, 0.95) == 90
+    assert O.pass_budget(1000, 999, 0.25) == 1
+
+
+def test_simplify_local_refresh_progressive():
+    """With a per-pass cap the loop takes several passes; the local refresh
+    queries every row in the first pass and fewer later, and reaches the
+    target exactly."""
+    sc = gen_scene(3000, 23)
+    q_local, q_full = [], []
+    a = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, 1500, 8, refresh="local",
+                   pass_frac=0.05, requeried=q_local)
+    b = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, 1500, 8, refresh="full",
+                   pass_frac=0.05, requeried=q_full)
+    assert a.n == b.n == 1500
+    assert len(q_local) == len(q_full) >= 10
+    assert q_local[0] == q_full[0] == 3000
+    assert all(ql < qf for ql, qf in zip(q_local[1:], q_full[1:]))
+    # the first pass is identical
+    assert np.sum(q_full) > 1.5 * np.sum(q_local)
