@@ -80,6 +80,16 @@ typedef struct {
 #define NANOGS_PREC_FP32 0  /* FP32 costs, FP64 for ill-conditioned pairs */
 #define NANOGS_PREC_FP64 1  /* every edge cost in FP64 */
 
+/* kNN graph of each pass (options.refresh).  FULL rebuilds it every pass.
+ * LOCAL (the local neighbourhood refresh of Sec. 3.4) rebuilds it in the
+ * first pass; later passes query only the splats a merge formed and those
+ * whose previous list named a splat that merged, and every other splat keeps
+ * its previous list carried to the new indices (its neighbours did not move;
+ * a merged splat that came closer is only seen from its own side, through
+ * the union of the lists).  Results differ from FULL by design. */
+#define NANOGS_REFRESH_FULL 0
+#define NANOGS_REFRESH_LOCAL 1
+
 /* Geometric term D_geo of the edge cost (options.cost_mode). */
 #define NANOGS_COST_MC 0     /* Appendix A's Monte Carlo estimate of KL(p || q_m):
                                 per draw the component is picked by u < pi */
@@ -111,6 +121,11 @@ typedef struct {
                          min(tau, median alpha); < 0 turns it off (-1) */
   int32_t cost_mode;  /* NANOGS_COST_MC (default), NANOGS_COST_STRAT or
                          NANOGS_COST_BOUND */
+  int32_t refresh;    /* NANOGS_REFRESH_FULL (default) or NANOGS_REFRESH_LOCAL
+                         (nanogs_simplify only) */
+  float pass_frac;    /* progressive collapses (Sec. 3.4): a pass takes at
+                         most max(1, floor(pass_frac * N)) pairs (the
+                         product in double); 0 = no cap (P = N - N_tgt) */
 } nanogs_options;
 
 /* Stages timed into nanogs_stats.stage_ms when options.timing is set. */
@@ -145,6 +160,9 @@ typedef struct {
   double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
   int32_t stage_launches[NANOGS_NTIMED];
   int64_t n_kept;  /* splats the opacity pre-filter kept (n when it is off) */
+  int64_t requery_per_round[NANOGS_MAX_ROUNDS]; /* rows whose kNN list was
+                                                   queried (N unless the local
+                                                   refresh kept some) */
 } nanogs_stats;
 
 /* Fills *opt with the defaults listed above. */

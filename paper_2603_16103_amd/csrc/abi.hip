@@ -35,6 +35,8 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
     r.timing = o->timing;
     r.tau = o->tau;
     r.cost_mode = o->cost_mode;
+    r.refresh = o->refresh;
+    r.pass_frac = o->pass_frac;
   }
   if (r.S < 1 || r.S > NANOGS_MAX_S) {
     set_error("options.S must be in [1, 16]");
@@ -63,6 +65,14 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
   if (r.cost_mode != NANOGS_COST_MC && r.cost_mode != NANOGS_COST_STRAT &&
       r.cost_mode != NANOGS_COST_BOUND) {
     set_error("options.cost_mode must be NANOGS_COST_MC, NANOGS_COST_STRAT or NANOGS_COST_BOUND");
+    return NANOGS_EINVAL;
+  }
+  if (r.refresh != NANOGS_REFRESH_FULL && r.refresh != NANOGS_REFRESH_LOCAL) {
+    set_error("options.refresh must be NANOGS_REFRESH_FULL or NANOGS_REFRESH_LOCAL");
+    return NANOGS_EINVAL;
+  }
+  if (!(r.pass_frac >= 0.0f && r.pass_frac <= 1.0f)) {
+    set_error("options.pass_frac must be in [0, 1]");
     return NANOGS_EINVAL;
   }
   *out = r;
@@ -352,6 +362,8 @@ void nanogs_default_options(nanogs_options* opt) {
   opt->timing = 0;
   opt->tau = -1.0f;
   opt->cost_mode = NANOGS_COST_MC;
+  opt->refresh = NANOGS_REFRESH_FULL;
+  opt->pass_frac = 0.0f;
 }
 
 const char* nanogs_last_error(void) { return g_error.c_str(); }
@@ -831,6 +843,11 @@ nanogs_status nanogs_batch_create(int64_t max_rows, int32_t max_k, int32_t max_j
     if (o.tau >= 0.0f) {
       set_error("the opacity pre-filter (options.tau) is applied by nanogs_simplify and "
                 "nanogs_prune, not by batches");
+      return NANOGS_EINVAL;
+    }
+    if (o.refresh != NANOGS_REFRESH_FULL) {
+      set_error("the local neighbourhood refresh (options.refresh) is applied by "
+                "nanogs_simplify, not by batches");
       return NANOGS_EINVAL;
     }
     NG_CHECK(check_ws(ws, ws_bytes, Engine::workspace_bytes(max_rows, max_k, max_jobs)));

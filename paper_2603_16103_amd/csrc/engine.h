@@ -31,6 +31,8 @@ struct Opts {
   int timing = 0;
   float tau = -1.0f;  // opacity pre-filter threshold (< 0: off)
   int cost_mode = NANOGS_COST_MC;
+  int refresh = NANOGS_REFRESH_FULL;
+  float pass_frac = 0.0f;  // per-pass pair cap (0: none)
 };
 
 enum JobState { JOB_QUEUED = 0, JOB_RUNNING = 1, JOB_DRAINING = 2, JOB_DONE = 3, JOB_FAILED = 4 };
@@ -65,6 +67,8 @@ struct Job {
   long long traced = 0;
   int lod_levels = 0;  // hierarchy levels written
   long long lod_used = 0;
+  long long prev_n = 0;  // rows of the last pass that merged (local refresh)
+  int prev_keff = 0;
   unsigned box[6] = {0, 0, 0, 0, 0, 0};
   nanogs_stats stats;
 };

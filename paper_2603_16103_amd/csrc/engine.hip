@@ -14,6 +14,7 @@
 // (seed, pass), so a job's result does not depend on what else is in the
 // batch.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -73,6 +74,10 @@ struct EngineWs {
   int* au;
   int* fb_list;
   int* partner;
+  int* nbr_log;  // local refresh: last lists by logical index, parent map, scratch
+  int* parent;
+  int* pcount;
+  int* dlist;
   unsigned* keys;
   int* perm;
   int* counters;
@@ -102,6 +107,10 @@ static EngineWs carve_engine(void* base, long long R, int K, int J) {
   s.au = c.take<int>(2 * R * K);
   s.fb_list = c.take<int>(R * K);
   s.partner = c.take<int>(R);
+  s.nbr_log = c.take<int>(R * K);
+  s.parent = c.take<int>(R);
+  s.pcount = c.take<int>(R);
+  s.dlist = c.take<int>(R);
   s.keys = c.take<unsigned>(R);
   s.perm = c.take<int>(R);
   s.counters = c.take<int>(64);
@@ -269,6 +278,11 @@ int Engine::step(StageTimer* T) {
       class_mask |= class_bit(S.kclass);
       S.next = next++;
       hP[i] = j.N - j.spec.target;
+      if (o_.pass_frac > 0.0f) {
+        // progressive collapses: at most max(1, floor(f N)) pairs per pass
+        const long long cap = (long long)std::floor((double)o_.pass_frac * (double)j.N);
+        hP[i] = std::min(hP[i], std::max(1ll, cap));
+      }
       ++searching;
     } else {
       S.next = -1;
@@ -308,7 +322,20 @@ int Engine::step(StageTimer* T) {
   fill_i32(W.counters + 2, 0, 1, st_);
   knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, st_);
   if (T) T->stop(tk);
-  knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, T, st_);
+  // local neighbourhood refresh (one scene): from the second pass on, only
+  // the splats a merge touched are queried
+  Job* j1 = (nseg == 1 && searching == 1) ? &jobs_[live_[0]] : nullptr;
+  const bool refresh_local = o_.refresh == NANOGS_REFRESH_LOCAL && j1;
+  const bool incremental = refresh_local && j1->round > 0 && j1->prev_n > 0 &&
+                           j1->prev_keff == hs[0].keff;
+  int* dcount = W.counters + 16;
+  if (incremental) {
+    knn_refresh(a.cen, (int)N, (int)j1->prev_n, K_, hs[0].keff, sg, W.seg, entries, W.temp,
+                W.parent, W.pcount, W.nbr_log, W.dlist, dcount, W.nbr, T, st_);
+  } else {
+    knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, T, st_);
+  }
+  if (refresh_local) knn_save_log(a.lg, W.nbr, (int)N, K_, hs[0].keff, W.nbr_log, st_);
   tk = T ? T->start(NANOGS_T_EDGES) : -1;
   const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
   launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
@@ -318,10 +345,13 @@ int Engine::step(StageTimer* T) {
   const int* kc = carve_knn(W.temp, N, entries, K_, nullptr).counters;
   NG_HIP(hipMemcpyAsync(host + 2, kc + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipMemcpyAsync(host + 3, kc + 8, sizeof(long long), hipMemcpyDeviceToHost, st_));
+  if (incremental)
+    NG_HIP(hipMemcpyAsync(host + 4, dcount, sizeof(int), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipStreamSynchronize(st_));
   const long long m = host[0];
   const long long knn_retries = *(int*)(host + 2);
   const long long knn_screens = host[3];
+  const long long requeried = incremental ? *(int*)(host + 4) : N;
   if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
 
   const CrnTab ct{W.crn, o_.S, sg, W.seg, o_.cost_mode};
@@ -370,6 +400,7 @@ int Engine::step(StageTimer* T) {
       j.stats.ld_iters_per_round[r] = sel.iters;
       j.stats.knn_retry_per_round[r] = searching == 1 ? knn_retries : 0;
       j.stats.knn_screens_per_round[r] = searching == 1 ? knn_screens : 0;
+      j.stats.requery_per_round[r] = searching == 1 ? requeried : 0;
     }
   }
 
@@ -397,9 +428,17 @@ int Engine::step(StageTimer* T) {
     }
   }
   tk = T ? T->start(NANOGS_T_MERGE) : -1;
+  // the local refresh of the next pass needs the new index of every splat
+  int* par = parent ? parent : (refresh_local ? W.parent : nullptr);
   const long long nn = merge_compact(a.cen, a.lg, a.shp, a.sh, a.org, (int)N, W.partner, b.cen,
                                      b.lg, b.shp, b.sh, b.org, trace, W.temp, st_, nullptr, sg,
-                                     b.sg, W.seg, nseg, parent);
+                                     b.sg, W.seg, nseg, par);
+  if (refresh_local && par != W.parent)
+    NG_HIP(hipMemcpyAsync(W.parent, par, N * sizeof(int), hipMemcpyDeviceToDevice, st_));
+  if (refresh_local) {
+    j1->prev_n = N;
+    j1->prev_keff = hs[0].keff;
+  }
   if (T) T->stop(tk);
   cur_ ^= 1;
   Ntot_ = nn;

@@ -239,6 +239,21 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
 void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
                unsigned class_mask, long long entries, void* mem, bool use_inv, int rows_logical,
                int* nbr, StageTimer* T, hipStream_t st);
+// Local neighbourhood refresh (Sec. 3.4) of a one-segment working set of
+// n_new rows after a pass over n_old rows: parent[o] = new logical index of
+// old logical index o, nbr_log[o][t] = its old list (old logical indices,
+// t < keff; keff unchanged).  A new splat formed by a merge, or whose old list
+// names a splat that merged, gets its exact kNN (as knn_query; the rows go
+// to dlist, their count to device *dcount); every other row's list is its
+// old list carried to the new indices.  Entries are working rows.  Needs
+// knn_build of the new set first.  pcount: scratch [n_new].
+void knn_refresh(const float4* cen, int n_new, int n_old, int k_out, int keff, const int* sg,
+                 const SegInfo* dseg, long long entries, void* mem, const int* parent,
+                 int* pcount, const int* nbr_log, int* dlist, int* dcount, int* nbr, StageTimer* T,
+                 hipStream_t st);
+// nbr_log[lg[p]][t] = lg[nbr[p][t]] for t < keff, -1 after (lists by logical index).
+void knn_save_log(const int* lg, const int* nbr, int n, int k_out, int keff, int* nbr_log,
+                  hipStream_t st);
 // Exact kNN of centres given in caller order (mu[n][3]); rows by caller index.
 size_t knn_plain_bytes(long long n, int k);
 void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipStream_t st);

@@ -596,14 +596,18 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   return nb;
 }
 
+// list (nullable): query only the rows list[0, *d_count)
 template <int K>
 __global__ void __launch_bounds__(256)
 k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
             const SegInfo* __restrict__ seg, const int* __restrict__ table, int block_min,
             int lane_rows, int* __restrict__ gbuf, int2* __restrict__ ginfo,
-            unsigned long long* __restrict__ screens) {
+            unsigned long long* __restrict__ screens, const int* __restrict__ list,
+            const int* __restrict__ d_count) {
   extern __shared__ unsigned s_hist[];  // [16][bs]: two 16-bit bin counts per word
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cnt = list ? *d_count : n;
+  const int p = idx < cnt ? (list ? list[idx] : idx) : n;
   int ns = 0;
   if (p < n) {
     const SegInfo& S = seg[sg ? sg[p] : 0];
@@ -665,8 +669,11 @@ k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restr
             const SegInfo* __restrict__ seg, const int* __restrict__ table,
             const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
             const int* __restrict__ gbuf, const int2* __restrict__ ginfo,
-            int2* __restrict__ retry, int* __restrict__ n_retry) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+            int2* __restrict__ retry, int* __restrict__ n_retry, const int* __restrict__ list,
+            const int* __restrict__ d_count) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cnt = list ? *d_count : n;
+  const int p = idx < cnt ? (list ? list[idx] : idx) : n;
   int res = -1;
   if (p < n) {
     const SegInfo& S = seg[sg ? sg[p] : 0];
@@ -1018,6 +1025,69 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
   }
 }
 
+// ---- local neighbourhood refresh (Sec. 3.4) -----------------------------------
+// After a pass, parent[o] is the new logical index of old logical index o (both
+// ends of a merged pair name the merged splat), nbr_log[o][t] the old list in
+// old logical indices.  A new splat is dirty when it was formed by a merge or
+// when its old list names a splat that merged; every other splat takes its
+// old list carried to the new indices (nothing it listed moved, and the
+// entries keep their order, since surviving indices keep theirs).
+
+__global__ void k_refresh_count(const int* __restrict__ parent, int n_old,
+                                int* __restrict__ pcount) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o < n_old) atomicAdd(&pcount[parent[o]], 1);
+}
+
+// append row to list (one atomic per wave)
+NG_DEV void append_row(bool take, int row, int* __restrict__ list, int* __restrict__ count) {
+  const unsigned long long m = __ballot(take);
+  if (!m) return;
+  const int lane = lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int at = 0;
+  if (lane == leader) at = atomicAdd(count, __popcll(m));
+  at = __shfl(at, leader, 64);
+  if (take) list[at + __popcll(m & ((1ull << lane) - 1ull))] = row;
+}
+
+// pcount[v] & 3 = old splats that became v (1 or 2); the bits above count
+// the ends of a merged pair that have been seen, so that one lists it.
+__global__ void k_refresh_rows(const int* __restrict__ parent, int n_old,
+                               int* __restrict__ pcount, const int* __restrict__ nbr_log,
+                               int k_out, int keff, const int* __restrict__ inv,
+                               int* __restrict__ nbr, int* __restrict__ dlist,
+                               int* __restrict__ dcount) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  bool dirty = false;
+  int row = 0;
+  if (o < n_old) {
+    const int v = parent[o];
+    row = inv[v];
+    if ((pcount[v] & 3) == 1) {
+      const int* old = nbr_log + (long long)o * k_out;
+      for (int t = 0; t < keff; ++t) dirty = dirty || (pcount[parent[old[t]]] & 3) != 1;
+      if (!dirty) {
+        int* out = nbr + (long long)row * k_out;
+        for (int t = 0; t < k_out; ++t) out[t] = t < keff ? inv[parent[old[t]]] : -1;
+      }
+    } else {
+      dirty = atomicAdd(&pcount[v], 4) < 4;  // the first end seen lists it
+    }
+  }
+  append_row(dirty, row, dlist, dcount);
+}
+
+// nbr_log[lg[p]][t] = lg[nbr[p][t]] (t < keff), -1 after
+__global__ void k_save_log(const int* __restrict__ lg, const int* __restrict__ nbr, int n,
+                           int k_out, int keff, int* __restrict__ nbr_log) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * k_out) return;
+  const int p = (int)(i / k_out), t = (int)(i % k_out);
+  const int e = nbr[i];
+  nbr_log[(long long)lg[p] * k_out + t] = t < keff && e >= 0 ? lg[e] : -1;
+}
+
 __global__ void k_invert(const float4* __restrict__ cen, int n, int* __restrict__ inv) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) inv[__float_as_int(cen[p].w)] = p;
@@ -1088,22 +1158,24 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
   NG_LAUNCH_CHECK();
 }
 
+// list (device, nullable): query only the rows list[0, *d_count) (the grids
+// cover n rows)
 template <int K>
 void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* dseg,
              const KnnMem& m, const int* inv, int rows_logical, int* nbr, StageTimer* T,
-             hipStream_t st) {
+             hipStream_t st, const int* list = nullptr, const int* d_count = nullptr) {
   const Tuning& t = tuning_for(n);
   const int bs = t.knn_block;
   int tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
   k_knn_block<K><<<blocks_for(n, bs), bs, (size_t)16 * bs * sizeof(unsigned), st>>>(
       cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf, m.ginfo,
-      (unsigned long long*)(m.counters + 8));
+      (unsigned long long*)(m.counters + 8), list, d_count);
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_EXACT) : -1;
   k_knn_exact<K><<<blocks_for(n, 256), 256, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
                                                       rows_logical, nbr, m.gbuf, m.ginfo,
-                                                      m.retry, m.counters + 1);
+                                                      m.retry, m.counters + 1, list, d_count);
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
 }
@@ -1141,6 +1213,42 @@ void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo
   if (class_mask & 2u) query_wave_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   if (class_mask & 4u) query_wave_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   if (class_mask & 8u) query_wave_k<32>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
+}
+
+void knn_refresh(const float4* cen, int n_new, int n_old, int k_out, int keff, const int* sg,
+                 const SegInfo* dseg, long long entries, void* mem, const int* parent,
+                 int* pcount, const int* nbr_log, int* dlist, int* dcount, int* nbr, StageTimer* T,
+                 hipStream_t st) {
+  KnnMem m = carve_knn(mem, n_new, entries, k_out, nullptr);
+  fill_i32(pcount, 0, n_new, st);
+  fill_i32(dcount, 0, 1, st);
+  fill_i32(m.counters + 1, 0, 1, st);
+  fill_i32(m.counters + 8, 0, 2, st);
+  if (n_old > 0) {
+    k_refresh_count<<<blocks_for(n_old, 256), 256, 0, st>>>(parent, n_old, pcount);
+    NG_LAUNCH_CHECK();
+    k_refresh_rows<<<blocks_for(n_old, 256), 256, 0, st>>>(parent, n_old, pcount, nbr_log, k_out,
+                                                          keff, m.inv, nbr, dlist, dcount);
+    NG_LAUNCH_CHECK();
+  }
+  switch (kclass_of(keff)) {
+    case 8: query_k<8>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st, dlist, dcount);
+            query_wave_k<8>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st); break;
+    case 16: query_k<16>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st, dlist, dcount);
+             query_wave_k<16>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st); break;
+    case 24: query_k<24>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st, dlist, dcount);
+             query_wave_k<24>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st); break;
+    default: query_k<32>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st, dlist, dcount);
+             query_wave_k<32>(cen, n_new, k_out, sg, dseg, m, m.inv, 0, nbr, T, st); break;
+  }
+}
+
+void knn_save_log(const int* lg, const int* nbr, int n, int k_out, int keff, int* nbr_log,
+                  hipStream_t st) {
+  if (n <= 0) return;
+  k_save_log<<<blocks_for((long long)n * k_out, 256), 256, 0, st>>>(lg, nbr, n, k_out, keff,
+                                                                     nbr_log);
+  NG_LAUNCH_CHECK();
 }
 
 unsigned class_bit(int kclass) {

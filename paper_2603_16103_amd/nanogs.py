@@ -25,6 +25,8 @@ PREC_FP64 = 1
 COST_MC = 0
 COST_STRAT = 1
 COST_BOUND = 2
+REFRESH_FULL = 0
+REFRESH_LOCAL = 1
 STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "select",
           "merge", "setup", "output", "knn_exact", "knn_wave")
 NTIMED = len(STAGES)
@@ -58,7 +60,8 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
                 ("d_trace", ctypes.c_void_p), ("d_origin", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("tau", ctypes.c_float),
-                ("cost_mode", ctypes.c_int32)]
+                ("cost_mode", ctypes.c_int32), ("refresh", ctypes.c_int32),
+                ("pass_frac", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +76,8 @@ class Stats(ctypes.Structure):
                 ("knn_screens_per_round", ctypes.c_int64 * MAX_ROUNDS),
                 ("stage_ms", ctypes.c_double * NTIMED),
                 ("stage_launches", ctypes.c_int32 * NTIMED),
-                ("n_kept", ctypes.c_int64)]
+                ("n_kept", ctypes.c_int64),
+                ("requery_per_round", ctypes.c_int64 * MAX_ROUNDS)]
 
     def as_dict(self):
         r = self.rounds + (1 if self.early_exit else 0)
@@ -87,6 +91,7 @@ class Stats(ctypes.Structure):
                 "ld_iters_per_round": list(self.ld_iters_per_round[:r]),
                 "knn_retry_per_round": list(self.knn_retry_per_round[:r]),
                 "knn_screens_per_round": list(self.knn_screens_per_round[:r]),
+                "requery_per_round": list(self.requery_per_round[:r]),
                 "stage_ms": dict(zip(STAGES, self.stage_ms)),
                 "stage_launches": dict(zip(STAGES, self.stage_launches)),
                 "n_kept": self.n_kept}
@@ -226,7 +231,8 @@ def _workspace(nbytes: int):
 
 
 def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
-            d_trace=None, d_origin=None, timing=False, tau=-1.0, cost_mode=COST_MC) -> Options:
+            d_trace=None, d_origin=None, timing=False, tau=-1.0, cost_mode=COST_MC,
+            refresh=REFRESH_FULL, pass_frac=0.0) -> Options:
     o = Options()
     load().nanogs_default_options(ctypes.byref(o))
     o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
@@ -236,6 +242,8 @@ def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, m
     o.timing = 1 if timing else 0
     o.tau = tau
     o.cost_mode = cost_mode
+    o.refresh = refresh
+    o.pass_frac = pass_frac
     return o
 
 
