@@ -35,25 +35,39 @@ def src_hash(name):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-# Roofline terms of the single-kernel stages, per pass: (bound, algorithmic
-# work, unit).  n = splats in the pass, e = edges, k = kNN size, screens =
-# float distance screens the kNN block gather made (library statistics).
+# Roofline terms per pass: (bound, algorithmic work).  n = splats in the
+# pass, e = edges, k = kNN size, screens = float distance screens of the kNN
+# block gather (library statistics).  Algorithmic bytes are what the step
+# must move at least: kNN reads the centres (12 B) and writes k indices
+# (4k B) per splat; the edge cost reads the activated attributes (mu 12, s 12,
+# q 16, alpha 4, SH 192 = 236 B) per splat and each edge's ends (8 B) and
+# writes its cost (4 B); the selection reads ends and cost (12 B per edge)
+# and writes a partner per splat (4 B); the factor precompute reads the
+# shape (32 B) and writes the factors and the weight (40 B) per splat.
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
-FLOPS_PER_SCREEN = 8      # 3 sub, 1 mul, 2 fma
+FLOPS_PER_SCREEN = 8      # 3 sub, 1 mul, 2 fma (+2 for the bin/compare)
 
 
 def stage_work(stage, n, e, k, screens):
-    if stage == "knn_query":   # block gather: distance screens (FP32 ALU)
+    if stage == "knn_query":   # k_knn_block: the kNN's bytes
+        return "hbm", (12 + 4 * k) * n
+    if stage == "knn_alu":     # the same kernel on the FP32 ALU roof
         return "alu", FLOPS_PER_SCREEN * screens
-    if stage == "cost":        # cen 16 + factors 32 + SH 192 per splat; ends 8 + cost 4 +
-        return "hbm", 240 * n + 36 * e  # two adjacency entries 24 per edge
-    if stage == "precompute":  # shape 32 in, factors 32 out
-        return "hbm", 64 * n
+    if stage == "cost":
+        return "hbm", 236 * n + 12 * e
+    if stage == "select":      # a stage of several kernels
+        return "hbm", 12 * e + 4 * n
+    if stage == "precompute":
+        return "hbm", 72 * n
     return None, None
 
 
-KERNEL_OF = {"knn_query": "k_knn_block<16>", "cost": "k_edge_cost", "precompute": "k_precompute"}
-SOURCE_OF = {"knn_query": "knn.hip", "cost": "cost.hip", "precompute": "cost.hip"}
+KERNEL_OF = {"knn_query": "k_knn_block<16>", "cost": "k_edge_cost", "precompute": "k_precompute",
+             "select": "select stage (k_ld_pick, k_ld_match, k_ld_tail, k_topp_seg)",
+             "knn_alu": "k_knn_block<16>"}
+SOURCE_OF = {"knn_query": "knn.hip", "cost": "cost.hip", "precompute": "cost.hip",
+             "select": "select.hip", "knn_alu": "knn.hip"}
+STAGE_OF = {"knn_alu": "knn_query"}  # timed stage of a roofline entry
 
 
 def traffic_for(stage):
@@ -65,14 +79,17 @@ def traffic_for(stage):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = t.get("kernels", {}).get(KERNEL_OF[stage])
+    ent = t.get("kernels", {}).get(KERNEL_OF[stage].split()[0])
     if not ent or ent.get("source_sha") != src_hash(SOURCE_OF[stage]):
         return None
     return ent["bytes_per_launch"]
 
 
-def cpu_baseline(sample_n):
-    import numpy as np
+def cpu_baseline(sample_n, workers):
+    """The FP64 oracle simplifying a bounded sample of the same workload
+    (same generator, 10% target, k=16) on the host: once with `workers`
+    threads for its per-query and per-edge steps (the reported baseline),
+    once on one thread.  BLAS threads are pinned to one in both."""
     try:
         from threadpoolctl import threadpool_limits
         lim = threadpool_limits(1)
@@ -82,15 +99,20 @@ def cpu_baseline(sample_n):
     from paper_2603_16103_amd.synth import gen_scene
     sc = gen_scene(sample_n, 2)
     target = max(int(math.ceil(0.1 * sample_n)), 1)
-    t0 = time.perf_counter()
-    st = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, 16)
-    dt = time.perf_counter() - t0
-    assert st.n == target
-    del lim, np
-    return {"value": sample_n / dt, "unit": "Gaussians/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle (numpy, one thread), {sample_n} splats from the same "
-                      f"generator (seed 2) simplified to 10% with k=16, {dt:.1f} s",
-            "seconds": dt}
+    times = {}
+    for w in (workers, 1):
+        t0 = time.perf_counter()
+        st = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, 16, workers=w)
+        times[w] = time.perf_counter() - t0
+        assert st.n == target
+    del lim
+    return {"value": sample_n / times[workers], "unit": "Gaussians/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"FP64 oracle (numpy), {sample_n} splats from the same generator (seed 2) "
+                      f"simplified to 10% with k=16: {times[workers]:.1f} s on {workers} threads",
+            "seconds": round(times[workers], 2),
+            "single_thread": {"value": sample_n / times[1], "cores": 1,
+                              "seconds": round(times[1], 2)}}
 
 
 def main():
@@ -99,7 +121,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--flush-mib", type=int, default=0,
+                    help="cold-cache variant: copy this many MiB between steps (outside the "
+                         "timed calls) so no step finds its data in the caches; the value is "
+                         "then the sum of the per-step times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (the "
@@ -138,13 +165,25 @@ def main():
 
     stage_ms = {s: 0.0 for s in ng.STAGES}
     launches = {s: 0 for s in ng.STAGES}
-    work_by_stage = {s: 0.0 for s in ng.STAGES}
+    work_by_stage = {s: 0.0 for s in KERNEL_OF}
     edges_total = 0
     last = None
+    flush = None
+    if args.flush_mib:
+        flush = torch.empty(args.flush_mib << 18, dtype=torch.float32, device="cuda")
+        flush_dst = torch.empty_like(flush)
+    cold_s = 0.0
     t0 = time.perf_counter()
     for i in range(args.steps):
         st = ng.Stats()
+        if flush is not None:
+            flush_dst.copy_(flush)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
         n_out = simp(g, target, out, st)
+        if flush is not None:
+            torch.cuda.synchronize()
+            cold_s += time.perf_counter() - tc
         d = st.as_dict()
         for s in ng.STAGES:
             stage_ms[s] += d["stage_ms"][s]
@@ -152,7 +191,7 @@ def main():
         for n_r, e_r, sc_r in zip(d["n_per_round"], d["edges_per_round"],
                                   d["knn_screens_per_round"]):
             edges_total += e_r
-            for s in ng.STAGES:
+            for s in KERNEL_OF:
                 _, w = stage_work(s, n_r, e_r, k, sc_r)
                 if w is not None:
                     work_by_stage[s] += w
@@ -162,26 +201,33 @@ def main():
     dt = time.perf_counter() - t0
     assert n_out == target, (n_out, target)
 
+    if flush is not None:
+        dt = cold_s
     ms_step = 1000.0 * dt / args.steps
     value = args.n * args.steps / dt
     def roof(stage):
         bound, _ = stage_work(stage, 1, 1, k, 1)
-        avg_ms = stage_ms[stage] / launches[stage]
-        per_launch = work_by_stage[stage] / launches[stage]
+        ts = STAGE_OF.get(stage, stage)
+        avg_ms = stage_ms[ts] / launches[ts]
+        per_launch = work_by_stage[stage] / launches[ts]
         if bound == "hbm":
             achieved, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+            tr = traffic_for(stage)
         else:
             achieved, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+            tr = None
         return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 5), "traffic": traffic_for(stage),
+                "frac": round(achieved / peak, 5), "traffic": tr,
                 "kernel": KERNEL_OF[stage], "avg_launch_us": round(1000 * avg_ms, 2),
                 ("algo_bytes_per_launch" if bound == "hbm" else "algo_flops_per_launch"):
                     int(per_launch)}
 
-    single = [s for s in KERNEL_OF if launches[s] > 0]
-    dom = max(single, key=lambda s: stage_ms[s])  # the single-kernel stage with most time
+    # the dominant kernel: the single-kernel stage with most time
+    single = [s for s in ("knn_query", "cost", "precompute") if launches[s] > 0]
+    dom = max(single, key=lambda s: stage_ms[s])
     roof_dom = roof(dom)
-    others = {s: roof(s) for s in single if s != dom}
+    others = {s: roof(s) for s in KERNEL_OF
+              if s != dom and launches[STAGE_OF.get(s, s)] > 0}
     res = {
         "metric": "Gaussians simplified/s (1M→10%)",
         "value": round(value, 1),
@@ -202,7 +248,8 @@ def main():
                    "edges_per_pass": last["edges_per_round"],
                    "fp64_edges_per_pass": last["fallback_per_round"],
                    "knn_wave_retries_per_pass": last["knn_retry_per_round"],
-                   "knn_screens_per_pass": last["knn_screens_per_round"]},
+                   "knn_screens_per_pass": last["knn_screens_per_round"],
+                   "cold_cache_flush_mib": args.flush_mib or None},
         "edge_costs_per_s": round(edges_total / (stage_ms["cost"] * 1e-3), 1)
         if stage_ms["cost"] > 0 else None,
         "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 4) for s in ng.STAGES},
@@ -211,7 +258,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         eprint("cpu baseline (oracle) on", args.cpu_sample, "splats")
-        res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers)
     print(json.dumps(res), flush=True)
 
 

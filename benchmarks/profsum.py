@@ -3,6 +3,11 @@
 ``python benchmarks/profsum.py stats KERNEL_STATS_CSV OUT_MD TITLE CMD``
 writes a markdown table of a ``--kernel-trace --stats`` run.
 
+``python benchmarks/profsum.py occ OUT_MD CMD PMC_CSV TRACE_CSV KERNEL ...``
+tabulates an ``--pmc`` run of SQ counters (waves, VALU/LDS instructions, LDS
+bank conflicts, wave and busy cycles) with the register and LDS footprint of
+each named kernel from a ``--kernel-trace`` CSV.
+
 ``python benchmarks/profsum.py traffic OUT_JSON OUT_MD CMD
 FETCH_CSV WRITE_CSV CALIB_FETCH_CSV CALIB_WRITE_CSV CALIB_BYTES KERNEL[=SOURCE] ...``
 turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the benchmark
@@ -103,9 +108,47 @@ def traffic(out_json, out_md, cmd, fetch_csv, write_csv, cfetch_csv, cwrite_csv,
                      f"| {e['bytes_per_launch']:.4g} |\n")
 
 
+def occ(out_md, cmd, pmc_csv, trace_csv, kernels):
+    sums = defaultdict(lambda: defaultdict(float))
+    for r in csv.DictReader(open(pmc_csv)):
+        sums[short(r["Kernel_Name"])][r["Counter_Name"]] += float(r["Counter_Value"])
+    res = {}
+    for r in csv.DictReader(open(trace_csv)):
+        k = short(r["Kernel_Name"])
+        if k not in res:
+            res[k] = (int(r["VGPR_Count"]), int(r["Accum_VGPR_Count"]), int(r["LDS_Block_Size"]),
+                      int(r["Workgroup_Size_X"]))
+    with open(out_md, "w") as fh:
+        fh.write("# Occupancy, instruction mix and LDS bank conflicts (rocprofv3 --pmc)\n\n")
+        fh.write("Commands (from the repository root on one MI355X):\n\n```\n" + cmd + "\n```\n\n")
+        fh.write("Registers and LDS per workgroup from the kernel trace.  Waves/SIMD by "
+                 "registers: min(8, 512 / (VGPR + AGPR rounded up to 8)).  Resident waves "
+                 "per CU: SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES.  Per-wave counts: counter / "
+                 "SQ_WAVES.  Bank-conflict share: SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS.\n\n")
+        fh.write("| kernel | VGPR | AGPR | LDS B/WG | WG | waves/SIMD (regs) | waves | resident "
+                 "waves/CU | VALU/wave | VMEM rd/wave | LDS/wave | LDS conflict share |\n")
+        fh.write("|---|---|---|---|---|---|---|---|---|---|---|---|\n")
+        for k in kernels:
+            c = sums.get(k)
+            if not c:
+                continue
+            v, a, lds, wg = res.get(k, (0, 0, 0, 0))
+            regs = ((v + a + 7) // 8) * 8
+            lim = min(8, 512 // regs) if regs else 8
+            waves = c.get("SQ_WAVES", 0.0) or 1.0
+            resident = c.get("SQ_WAVE_CYCLES", 0.0) / max(c.get("SQ_BUSY_CU_CYCLES", 0.0), 1.0)
+            conf = c.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(c.get("SQ_ACTIVE_INST_LDS", 0.0), 1.0)
+            fh.write(f"| {k} | {v} | {a} | {lds} | {wg} | {lim} | {waves:.0f} | {resident:.1f} "
+                     f"| {c.get('SQ_INSTS_VALU', 0) / waves:.0f} "
+                     f"| {c.get('SQ_INSTS_VMEM_RD', 0) / waves:.0f} "
+                     f"| {c.get('SQ_INSTS_LDS', 0) / waves:.0f} | {conf:.3f} |\n")
+
+
 def main(argv):
     if argv[0] == "stats":
         stats(*argv[1:5])
+    elif argv[0] == "occ":
+        occ(argv[1], argv[2], argv[3], argv[4], argv[5:])
     elif argv[0] == "traffic":
         traffic(*argv[1:9], argv[9:])
     else:
