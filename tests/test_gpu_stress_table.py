@@ -12,6 +12,10 @@ oracle teacher-forced on that state:
 * merge: errors of 20,000 sampled merged splats, within 1e-5.
 The chained stages end at the same splats as the fused loop, bit for bit.
 
+With NANOGS_STRESS_E2E=<splats> the final outputs of the fused loop on a
+stress scene of that size are also compared with the oracle's own loop
+(provenance pairs per pass, per-field errors of the matched clusters).
+
 This runs for minutes, so it is skipped unless NANOGS_STRESS_TABLE is set
 (to the splat count, e.g. 6000000); NANOGS_STRESS_OUT names a JSON file for
 the error table.
@@ -50,8 +54,11 @@ def _state64(mu, s, q, al, f):
                    f.astype(np.float64), np.arange(mu.shape[0]))
 
 
-def _greedy_ok(a, b, c, pt):
-    """The selection is the greedy scan's result under (cost, i, j)."""
+def _greedy_ok(a, b, c, pt, P):
+    """The selection is the greedy scan's result under (cost, i, j) with at
+    most P picks: taken edges are disjoint, and every eligible edge that was
+    not taken is blocked by a taken edge of smaller rank, unless it ranks
+    after the P-th pick (the scan stopped there)."""
     m = a.size
     ok = np.isfinite(c)
     order = np.lexsort((b, a, np.where(ok, c, np.inf)))
@@ -64,7 +71,39 @@ def _greedy_ok(a, b, c, pt):
     vrank[a[taken]] = rank[taken]
     vrank[b[taken]] = rank[taken]
     blocked = np.minimum(vrank[a], vrank[b]) < rank
-    return bool(np.all(blocked[ok & ~taken])), int(taken.sum())
+    nt = int(taken.sum())
+    limit = int(rank[taken].max()) if nt == P and nt > 0 else big
+    must = ok & ~taken & (rank < limit)
+    return bool(np.all(blocked[must])), nt
+
+
+def _final_outputs(ng, n):
+    """The fused loop's final set against the oracle's loop on a stress
+    scene of n splats: identical provenance pairs per pass and the errors of
+    every output field over the matched clusters."""
+    import torch
+    from tests.e2e_compare import compare_clusters, gpu_merges, pair_identity
+    sc, k, _ = scene_precision_stress(n)
+    target = max(int(math.ceil(0.01 * n)), 1)
+    origin = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    trace = torch.full((n, 2), -1, dtype=torch.int32, device="cuda")
+    res, stats = ng.simplify(ng.GaussianTensors.from_scene(sc), target, k=k,
+                             opts=ng.options(d_origin=origin, d_trace=trace), return_stats=True)
+    log("final outputs: oracle loop on", n)
+    ref_trace = []
+    ref = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, k,
+                     trace=ref_trace, workers=16)
+    ppr = stats["pairs_per_round"][:stats["rounds"]]
+    tr = trace.cpu().numpy()
+    frac, per = pair_identity(ppr, tr, ref_trace)
+    org = origin.cpu().numpy()[:res.n]
+    err = compare_clusters(n, res.numpy(), org, gpu_merges(ppr, tr), ref, ref_trace)
+    assert res.n == ref.n == target and frac >= 0.99
+    return {"n": n, "target": target, "k": k, "passes": len(ppr),
+            "identical_pairs": frac, "identical_pairs_per_pass": per,
+            "fallback_per_pass": stats["fallback_per_round"][:len(ppr)],
+            **{key: (float(v) if isinstance(v, (float, np.floating)) else v)
+               for key, v in err.items()}}
 
 
 def test_precision_stress_table(gpu_lib):
@@ -123,9 +162,10 @@ def test_precision_stress_table(gpu_lib):
         P = N - target
         partner, npairs = ng.select(ei, ej, cost, N, P)
         pt = partner.cpu().numpy()
-        greedy, taken = _greedy_ok(a, b, c, pt)
+        greedy, taken = _greedy_ok(a, b, c, pt, P)
         row["pairs"] = int(npairs)
         row["greedy_characterisation"] = greedy
+        log("pass", r, "pairs", npairs, "taken", taken, "P", P, "greedy", greedy)
         assert greedy and taken == npairs <= P
         del a, b, c, c64, cost, cost64, ei, ej, nbr
         out = ng.merge(cur, partner)
@@ -177,6 +217,10 @@ def test_precision_stress_table(gpu_lib):
     same = res.n == N and all(np.array_equal(x, y) for x, y in zip(res.numpy(), chained.numpy()))
     table["chained_equals_fused"] = bool(same)
     log("chained stages == fused loop:", same)
+    e2e_n = int(os.environ.get("NANOGS_STRESS_E2E", "0"))
+    if e2e_n:
+        table["final_outputs"] = _final_outputs(ng, e2e_n)
+        log("final outputs", json.dumps(table["final_outputs"]))
     path = os.environ.get("NANOGS_STRESS_OUT")
     if path:
         with open(path, "w") as fh:
