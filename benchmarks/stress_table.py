@@ -24,7 +24,7 @@ def main(table_json, out_md, cmd, tree):
                 f"state ({t['sample']} sampled rows, edges and pairs per pass; the union edges "
                 "and the greedy characterisation over every edge).\n\n")
         f.write("| pass | N | kNN rows equal | edges | edges equal | cost max rel (FP32+fallback) "
-                "| cost max abs | within 1e-4|C|+1e-5 | cost max rel (FP64 mode) | pairs | greedy "
+                "| cost max abs | within 1e-4 abs(C) + 1e-5 | cost max rel (FP64 mode) | pairs | greedy "
                 "| mu max rel | Sigma max rel | scales max rel | alpha max abs | f max rel |\n")
         f.write("|" + "---|" * 16 + "\n")
         for r in t["passes"]:
@@ -45,7 +45,7 @@ def main(table_json, out_md, cmd, tree):
                     f"edges per pass {fo['fallback_per_pass']}; clusters with identical membership "
                     f"{fmt(fo['identical_clusters'])} of {fo['clusters']}.\n\n")
             f.write("| output | max | p99 |\n|---|---|---|\n")
-            for name, what in (("mu", "centre, relative to max(|mu|, 1)"),
+            for name, what in (("mu", "centre, relative to max(abs(mu), 1)"),
                                ("sigma", "covariance, Frobenius relative"),
                                ("alpha", "opacity, absolute"), ("f", "SH, relative")):
                 if name + "_max" in fo:
