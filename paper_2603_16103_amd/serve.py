@@ -18,10 +18,15 @@ each admitted job also holds its device input and output buffers; ``rows``
 is the largest count for which the engine workspace plus those buffers fit
 in the budget.
 
-Command line: ``python -m paper_2603_16103_amd.serve --duration 20 --rate 20``
-replays a Poisson trace (scene sizes log-uniform, targets from
+Command line: ``python -m paper_2603_16103_amd.serve --duration 120 --rate 20``
+replays a Poisson trace (scene sizes log-uniform in [1e4, 4e6], targets from
 {0.5, 0.1, 0.01}, k from {16, 24}) through both servers and prints one JSON
-line with throughput and p50/p99 latency of each.
+line with throughput and p50/p99 latency of each.  By default every request
+carries its own scene, drawn on the device from seed 20000 + request id when
+it is admitted (synth.gen_scene_device; the draw takes the place of the
+host-to-device copy of a client's upload); ``--scenes pool`` instead reuses a
+pool of host scenes copied in over PCIe.  The HBM budget defaults to the
+device's free memory minus a 16 GiB reserve.
 """
 from __future__ import annotations
 
@@ -39,7 +44,7 @@ if __package__ in (None, ""):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 from paper_2603_16103_amd import nanogs as ng  # noqa: E402
-from paper_2603_16103_amd.synth import gen_scene  # noqa: E402
+from paper_2603_16103_amd.synth import gen_scene, gen_scene_device, serving_trace  # noqa: E402
 
 IO_BYTES_PER_SPLAT = 4 * (3 + 3 + 4 + 1 + 48)  # stored form, one copy
 
@@ -48,10 +53,12 @@ IO_BYTES_PER_SPLAT = 4 * (3 + 3 + 4 + 1 + 48)  # stored form, one copy
 class Request:
     rid: int
     t_arrival: float     # seconds from the start of the replay
-    scene: object        # synth.Scene (host, float32)
+    scene: object        # synth.Scene (host, float32), or None: drawn on the device
     target: int
     k: int
     seed: int
+    scene_seed: int = -1  # device-drawn scene: its seed
+    size: int = 0         # device-drawn scene: its splat count
     # filled by the server
     t_admit: float = -1.0
     t_done: float = -1.0
@@ -60,7 +67,7 @@ class Request:
 
     @property
     def n(self) -> int:
-        return self.scene.n
+        return self.scene.n if self.scene is not None else self.size
 
 
 def _pin(a: np.ndarray):
@@ -130,8 +137,11 @@ class BatchServer:
         out = ng.GaussianTensors.empty(req.n)
         dev = (g.pos, g.log_scale, g.rot, g.opacity, g.sh)
         with torch.cuda.stream(self.copy):
-            for d, h in zip(dev, host.arrays):
-                d.copy_(h, non_blocking=True)
+            if host is None:
+                gen_scene_device(req.n, req.scene_seed, out=dev, stream=self.copy)
+            else:
+                for d, h in zip(dev, host.arrays):
+                    d.copy_(h, non_blocking=True)
         for d in dev:
             d.record_stream(self.copy)
         ev = torch.cuda.Event()
@@ -244,8 +254,12 @@ class PlainServer:
                 time.sleep(req.t_arrival - now)
             req.t_admit = time.perf_counter() - t0
             g = ng.GaussianTensors.empty(req.n)
-            for d, h in zip((g.pos, g.log_scale, g.rot, g.opacity, g.sh), hosts[i].arrays):
-                d.copy_(h, non_blocking=True)
+            dev = (g.pos, g.log_scale, g.rot, g.opacity, g.sh)
+            if hosts[i] is None:
+                gen_scene_device(req.n, req.scene_seed, out=dev)
+            else:
+                for d, h in zip(dev, hosts[i].arrays):
+                    d.copy_(h, non_blocking=True)
             out = ng.GaussianTensors.empty(req.n)
             sim = self._sim(req.k)
             sim.opts.seed = req.seed
@@ -306,15 +320,28 @@ def make_trace(rate: float, duration: float, seed: int, lo: float, hi: float,
     return reqs, pool
 
 
+def make_device_trace(rate: float, duration: float, seed: int):
+    """Poisson arrivals of synth.serving_trace, each request with its own
+    scene (seed 20000 + request id) drawn on the device at admission."""
+    reqs = []
+    for rid, (t, n, sseed, ratio, k) in enumerate(serving_trace(rate, duration, seed)):
+        reqs.append(Request(rid, t, None, max(int(math.ceil(ratio * n)), 1), k,
+                            seed=1000003 * rid + 7, scene_seed=sseed, size=n))
+    return reqs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--duration", type=float, default=20.0)
+    ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--lo", type=float, default=1e4)
     ap.add_argument("--hi", type=float, default=4e6)
     ap.add_argument("--pool", type=int, default=16)
-    ap.add_argument("--hbm-gb", type=float, default=96.0)
+    ap.add_argument("--hbm-gb", type=float, default=0.0,
+                    help="HBM budget in GiB (0: free device memory minus --reserve-gb)")
+    ap.add_argument("--reserve-gb", type=float, default=16.0)
+    ap.add_argument("--scenes", choices=("device", "pool"), default="device")
     ap.add_argument("--max-jobs", type=int, default=64)
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -326,28 +353,44 @@ def main():
     def eprint(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    eprint("generating the scene pool")
-    reqs, pool = make_trace(args.rate, args.duration, args.seed, args.lo, args.hi, args.pool)
-    host_of = {id(sc): _HostScene(sc) for sc in pool}
-    hosts = [host_of[id(r.scene)] for r in reqs]
-    eprint(f"{len(reqs)} requests, {sum(r.n for r in reqs)} splats")
-    srv = BatchServer(int(args.hbm_gb * 2**30), max_k=24, max_jobs=args.max_jobs)
+    free, total_mem = torch.cuda.mem_get_info()
+    budget = int(args.hbm_gb * 2**30) if args.hbm_gb > 0 else int(free - args.reserve_gb * 2**30)
+    if args.scenes == "pool":
+        eprint("generating the scene pool")
+        reqs, pool = make_trace(args.rate, args.duration, args.seed, args.lo, args.hi, args.pool)
+        host_of = {id(sc): _HostScene(sc) for sc in pool}
+        hosts = [host_of[id(r.scene)] for r in reqs]
+    else:
+        reqs = make_device_trace(args.rate, args.duration, args.seed)
+        hosts = [None] * len(reqs)
+    eprint(f"{len(reqs)} requests, {sum(r.n for r in reqs)} splats, budget {budget / 2**30:.1f} GiB")
+    srv = BatchServer(budget, max_k=24, max_jobs=args.max_jobs)
     # warm-up pass of the kernels, not timed
     w = ng.Batch(200000, 24, 4)
-    w.submit(ng.GaussianTensors.from_scene(pool[0] if pool[0].n <= 200000
-                                           else gen_scene(50000, 1)), 1000, k=24)
+    w.submit(ng.GaussianTensors.from_scene(gen_scene(50000, 1)), 1000, k=24)
     w.run()
     w.close()
+    gen_scene_device(1000, 1)
     res = {"batched": srv.serve(reqs, hosts, log=eprint)}
     srv.batch.close()
+    srv_rows = srv.rows
+    del srv
+    torch.cuda.empty_cache()
     if not args.no_plain:
         for r in reqs:
             r.t_done = -1.0
         plain = PlainServer(max(r.n for r in reqs), 24)
         res["plain"] = plain.serve(reqs, hosts, log=eprint)
-    res["trace"] = {"rate_per_s": args.rate, "duration_s": args.duration, "sizes": [args.lo, args.hi],
-                    "ratios": [0.5, 0.1, 0.01], "k": [16, 24], "pool_scenes": args.pool,
-                    "hbm_budget_gb": args.hbm_gb}
+    res["trace"] = {"rate_per_s": args.rate, "duration_s": args.duration,
+                    "sizes": [args.lo, args.hi] if args.scenes == "pool" else [1e4, 4e6],
+                    "ratios": [0.5, 0.1, 0.01], "k": [16, 24],
+                    "scenes": (f"pool of {args.pool} host scenes" if args.scenes == "pool" else
+                               "one per request, drawn on the device from seed 20000 + id"),
+                    "hbm_budget_gib": round(budget / 2**30, 2),
+                    "device_free_gib": round(free / 2**30, 2),
+                    "device_total_gib": round(total_mem / 2**30, 2),
+                    "working_set_rows": srv_rows,
+                    "working_set_row_limit": max_engine_rows(24)}
     print(json.dumps(res), flush=True)
 
 

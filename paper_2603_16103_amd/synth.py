@@ -139,6 +139,70 @@ def gen_scene(n: int, seed: int, n_planes: int = 8, n_spheres: int = 4,
                  sh[perm].astype(f32))
 
 
+def gen_scene_device(n: int, seed: int, out=None, stream=None):
+    """One scene of ``n`` splats drawn on the GPU with the recipe above, for
+    workloads with too many distinct scenes to draw on the host (a serving
+    trace of thousands of requests).  The surfaces (2..8 planes, 0..4
+    spheres, their centres, normals, extents and radii) come from
+    ``numpy.random.Generator(PCG64(seed))``; the per-splat draws come from a
+    CUDA ``torch.Generator`` seeded with ``seed`` and are made in float32, so
+    the scene is not the one gen_scene would draw for that seed.  ``out``:
+    optional stored-form tensors (pos, log_scale, rot, opacity, sh) of
+    capacity n to fill; returns those tensors."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_planes = int(rng.integers(2, 9))
+    n_spheres = int(rng.integers(0, 5))
+    surf = []
+    for _ in range(n_planes):
+        c = rng.uniform(-8.0, 8.0, 3)
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        surf.append(("plane", c, _plane_basis(nrm), rng.uniform(2.0, 8.0)))
+    for _ in range(n_spheres):
+        surf.append(("sphere", rng.uniform(-8.0, 8.0, 3), None, rng.uniform(1.0, 4.0)))
+    dev = torch.device("cuda")
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    if out is None:
+        out = (torch.empty((n, 3), device=dev), torch.empty((n, 3), device=dev),
+               torch.empty((n, 4), device=dev), torch.empty(n, device=dev),
+               torch.empty((n, SH_COEFFS), device=dev))
+    pos_o, ls_o, rot_o, op_o, sh_o = out
+    ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(
+        torch.cuda.current_stream())
+    with ctx:
+        n_clutter = int(round(0.10 * n))
+        n_struct = n - n_clutter
+        counts = [n_struct // len(surf)] * len(surf)
+        counts[0] += n_struct - sum(counts)
+        pos = torch.empty((n, 3), device=dev)
+        at = 0
+        f32 = torch.float32
+        for (kind, c, basis, ext), cnt in zip(surf, counts):
+            ct = torch.tensor(c, dtype=f32, device=dev)
+            if kind == "plane":
+                u = torch.tensor(basis[0], dtype=f32, device=dev)
+                v = torch.tensor(basis[1], dtype=f32, device=dev)
+                ab = (torch.rand((cnt, 2), generator=g, device=dev) * 2.0 - 1.0) * float(ext)
+                p = ct + ab[:, :1] * u + ab[:, 1:] * v
+            else:
+                d = torch.randn((cnt, 3), generator=g, device=dev)
+                p = ct + float(ext) * (d / d.norm(dim=1, keepdim=True))
+            p = p + 0.02 * torch.randn((cnt, 3), generator=g, device=dev)
+            pos[at:at + cnt] = p.clamp_(-10.0, 10.0)
+            at += cnt
+        pos[at:] = torch.rand((n_clutter, 3), generator=g, device=dev) * 20.0 - 10.0
+        perm = torch.randperm(n, generator=g, device=dev)
+        pos_o.copy_(pos[perm])
+        ls_o.copy_(torch.randn((n, 3), generator=g, device=dev) * 0.5 - 4.0)
+        rot_o.copy_(torch.randn((n, 4), generator=g, device=dev))
+        op_o.copy_(torch.randn(n, generator=g, device=dev) * 1.5)
+        sh_o[:, :3] = torch.rand((n, 3), generator=g, device=dev) * 2.0 - 1.0
+        sh_o[:, 3:] = torch.randn((n, SH_COEFFS - 3), generator=g, device=dev) * 0.05
+    return out
+
+
 # --- named workloads -------------------------------------------------------
 
 def scene_cpu_scale():
