@@ -107,6 +107,11 @@ class Engine {
 
   long long R_;
   int K_, J_;
+  // page-locked host memory: per-pass uploads (segment table, draws,
+  // budgets) and the readback of the pass's counts after its one
+  // synchronisation
+  char* stage_ = nullptr;
+  long long* hb_ = nullptr;
   Opts o_;
   hipStream_t st_;
   EngineWs* W_;

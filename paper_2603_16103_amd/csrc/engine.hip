@@ -135,12 +135,23 @@ size_t Engine::workspace_bytes(long long rows, int kmax, int jobs) {
   return carve_engine(nullptr, rows, kmax, jobs).bytes;
 }
 
+static size_t stage_bytes(int J) {
+  return (size_t)J * (sizeof(SegInfo) + NG_CRN_ROW * sizeof(float) + sizeof(long long)) + 256;
+}
+
 Engine::Engine(long long rows, int kmax, int jobs, const Opts& o, void* ws, hipStream_t st)
     : R_(rows < 2 ? 2 : rows), K_(kmax), J_(jobs), o_(o), st_(st) {
   W_ = new EngineWs(carve_engine(ws, R_, K_, J_));
+  NG_HIP(hipHostMalloc((void**)&stage_, stage_bytes(J_), hipHostMallocDefault));
+  NG_HIP(hipHostMalloc((void**)&hb_, (16 + (size_t)J_) * sizeof(long long),
+                       hipHostMallocDefault));
 }
 
-Engine::~Engine() { delete W_; }
+Engine::~Engine() {
+  (void)hipHostFree(stage_);
+  (void)hipHostFree(hb_);
+  delete W_;
+}
 
 int Engine::submit(const JobSpec& spec) {
   Job j;
@@ -223,7 +234,6 @@ void Engine::finish_job(Job& j, const Work& w) {
 // ---------------------------------------------------------------------------
 int Engine::step(StageTimer* T) {
   EngineWs& W = *W_;
-  long long* host = pinned_host();
   int tk;
   int finished = 0;
 
@@ -255,9 +265,14 @@ int Engine::step(StageTimer* T) {
   if (T) T->stop(tk);
 
   // 2. segment table: searching segments (running), draining ones (rows
-  // dropped by this pass's compaction)
-  std::vector<SegInfo> hs(live_.size());
-  std::vector<long long> hP(live_.size(), 0);
+  // dropped by this pass's compaction).  The table, the draws and the
+  // budgets go up from page-locked memory: no copy here waits for the
+  // device (the last pass ended with a synchronisation, so the device has
+  // read the previous contents).
+  SegInfo* hs = (SegInfo*)stage_;
+  float* hcrn = (float*)(stage_ + (size_t)J_ * sizeof(SegInfo));
+  long long* hP = (long long*)(stage_ + (size_t)J_ * (sizeof(SegInfo) + NG_CRN_ROW * sizeof(float)));
+  for (size_t i = 0; i < live_.size(); ++i) hP[i] = 0;
   long long entries = 0;
   unsigned class_mask = 0u;
   int searching = 0, next = 0;
@@ -299,16 +314,15 @@ int Engine::step(StageTimer* T) {
     NG_HIP(hipStreamSynchronize(st_));
     return finished;
   }
-  NG_HIP(hipMemcpyAsync(W.seg, hs.data(), hs.size() * sizeof(SegInfo), hipMemcpyHostToDevice,
-                        st_));
+  NG_HIP(hipMemcpyAsync(W.seg, hs, nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st_));
   // draws of every segment's current pass
-  std::vector<float> crn((size_t)nseg * NG_CRN_ROW, 0.f);
+  std::memset(hcrn, 0, (size_t)nseg * NG_CRN_ROW * sizeof(float));
   for (int i = 0; i < nseg; ++i) {
     const Job& j = jobs_[live_[i]];
-    crn_host(j.spec.seed, j.round, o_.S, &crn[(size_t)i * NG_CRN_ROW]);
+    crn_host(j.spec.seed, j.round, o_.S, &hcrn[(size_t)i * NG_CRN_ROW]);
   }
-  NG_HIP(hipMemcpyAsync(W.crn, crn.data(), crn.size() * sizeof(float), hipMemcpyHostToDevice,
-                        st_));
+  NG_HIP(hipMemcpyAsync(W.crn, hcrn, (size_t)nseg * NG_CRN_ROW * sizeof(float),
+                        hipMemcpyHostToDevice, st_));
 
   const Work& a = W.w[cur_];
   const Work& b = W.w[cur_ ^ 1];
@@ -336,23 +350,23 @@ int Engine::step(StageTimer* T) {
     knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, T, st_);
   }
   if (refresh_local) knn_save_log(a.lg, W.nbr, (int)N, K_, hs[0].keff, W.nbr_log, st_);
+  {
+    // the kNN's statistics (retries, screens) live in the temporary area the
+    // later stages reuse: keep copies for the end of the pass
+    const int* kc = carve_knn(W.temp, N, entries, K_, nullptr).counters;
+    NG_HIP(hipMemcpyAsync(W.counters + 8, kc + 1, sizeof(int), hipMemcpyDeviceToDevice, st_));
+    NG_HIP(hipMemcpyAsync(W.counters + 10, kc + 8, sizeof(long long), hipMemcpyDeviceToDevice,
+                          st_));
+  }
   tk = T ? T->start(NANOGS_T_EDGES) : -1;
   const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
   launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
   if (T) T->stop(tk);
-  NG_HIP(hipMemcpyAsync(host, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(host + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
-  const int* kc = carve_knn(W.temp, N, entries, K_, nullptr).counters;
-  NG_HIP(hipMemcpyAsync(host + 2, kc + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(host + 3, kc + 8, sizeof(long long), hipMemcpyDeviceToHost, st_));
-  if (incremental)
-    NG_HIP(hipMemcpyAsync(host + 4, dcount, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipStreamSynchronize(st_));
-  const long long m = host[0];
-  const long long knn_retries = *(int*)(host + 2);
-  const long long knn_screens = host[3];
-  const long long requeried = incremental ? *(int*)(host + 4) : N;
-  if (*(int*)(host + 1) != 0) throw HipError{"internal: working set not in Morton order"};
+  // the edge count stays on the device: the cost launches cover N * k
+  // edges and read it there
+  const int m_cap = (int)(N * K_);
+  int* mcount = W.counters + 3;
+  count_to_i32(W.d_m, m_cap, mcount, st_);
 
   const CrnTab ct{W.crn, o_.S, sg, W.seg, o_.cost_mode};
   const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
@@ -361,48 +375,30 @@ int Engine::step(StageTimer* T) {
   if (o_.precision == NANOGS_PREC_FP64) {
     tk = T ? T->start(NANOGS_T_COST_FP64) : -1;
     launch_edge_cost_fp64(a.cen, a.shp, a.sh, o_.app_dims, W.src, W.tgt, (int)N, true, nullptr,
-                          nullptr, (int)m, ct, W.cost, nullptr, adj_out, st_);
+                          mcount, m_cap, ct, W.cost, nullptr, adj_out, st_);
     if (T) T->stop(tk);
   } else {
     tk = T ? T->start(NANOGS_T_COST) : -1;
-    launch_edge_cost(a.cen, W.pre, a.sh, o_.app_dims, W.src, W.tgt, (int)m, (int)N, true, ct,
-                     o_.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, adj_out, st_);
+    launch_edge_cost(a.cen, W.pre, a.sh, o_.app_dims, W.src, W.tgt, m_cap, (int)N, true, ct,
+                     o_.fb_ratio, W.cost, nullptr, W.fb_list, fb_count, adj_out, st_, mcount);
     if (T) T->stop(tk);
     tk = T ? T->start(NANOGS_T_COST_FP64) : -1;
     launch_edge_cost_fp64(a.cen, a.shp, a.sh, o_.app_dims, W.src, W.tgt, (int)N, true, W.fb_list,
-                          fb_count, (int)m, ct, W.cost, nullptr, adj_out, st_);
+                          fb_count, m_cap, ct, W.cost, nullptr, adj_out, st_);
     if (T) T->stop(tk);
   }
 
   tk = T ? T->start(NANOGS_T_SELECT) : -1;
   const Adjacency adj{W.aoff, W.akey, W.au};
-  std::vector<long long> hM(nseg, 0);
-  SelectResult sel = select_pairs(adj, (int)N, a.lg, sg, nseg, hP.data(), W.partner, W.temp, st_,
-                                  nullptr, hM.data());
+  const int* d_mseg = nullptr;
+  const int* d_tail = nullptr;
+  const int grid_iters = select_pairs_async(adj, (int)N, a.lg, sg, nseg, hP, W.partner, W.temp,
+                                            st_, &d_mseg, &d_tail);
   if (T) T->stop(tk);
-  long long fb = m;
-  if (o_.precision != NANOGS_PREC_FP64) {
-    NG_HIP(hipMemcpyAsync(host, fb_count, sizeof(int), hipMemcpyDeviceToHost, st_));
-    NG_HIP(hipStreamSynchronize(st_));
-    fb = *(int*)host;
-  }
 
-  // per-job bookkeeping of the pass
-  for (int i = 0; i < nseg; ++i) {
-    Job& j = jobs_[live_[i]];
-    if (j.state != JOB_RUNNING) continue;
-    const int r = j.round;
-    if (r < NANOGS_MAX_ROUNDS) {
-      j.stats.n_per_round[r] = j.N;
-      j.stats.edges_per_round[r] = searching == 1 ? m : 0;
-      j.stats.pairs_per_round[r] = hM[i];
-      j.stats.fallback_per_round[r] = searching == 1 ? fb : 0;
-      j.stats.ld_iters_per_round[r] = sel.iters;
-      j.stats.knn_retry_per_round[r] = searching == 1 ? knn_retries : 0;
-      j.stats.knn_screens_per_round[r] = searching == 1 ? knn_screens : 0;
-      j.stats.requery_per_round[r] = searching == 1 ? requeried : 0;
-    }
-  }
+  // the pass's counts come back with the merge's synchronisation
+  long long* hb = hb_;
+  int* hbi = (int*)(hb + 8);  // per segment pairs
 
   // single running job with a trace buffer: provenance pairs of this pass
   int* trace = nullptr;
@@ -427,6 +423,14 @@ int Engine::step(StageTimer* T) {
       ++j.lod_levels;
     }
   }
+  NG_HIP(hipMemcpyAsync(hb + 0, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 2, W.counters + 8, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 3, W.counters + 10, sizeof(long long), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 4, dcount, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 5, fb_count, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hb + 6, d_tail, sizeof(int), hipMemcpyDeviceToHost, st_));
+  NG_HIP(hipMemcpyAsync(hbi, d_mseg, nseg * sizeof(int), hipMemcpyDeviceToHost, st_));
   tk = T ? T->start(NANOGS_T_MERGE) : -1;
   // the local refresh of the next pass needs the new index of every splat
   int* par = parent ? parent : (refresh_local ? W.parent : nullptr);
@@ -440,6 +444,34 @@ int Engine::step(StageTimer* T) {
     j1->prev_keff = hs[0].keff;
   }
   if (T) T->stop(tk);
+  // merge_compact synchronised the stream: the counts are in hb
+  const long long m = hb[0];
+  if (*(int*)(hb + 1) != 0) throw HipError{"internal: working set not in Morton order"};
+  const long long knn_retries = *(int*)(hb + 2);
+  const long long knn_screens = hb[3];
+  const long long requeried = incremental ? *(int*)(hb + 4) : N;
+  const long long fb = o_.precision != NANOGS_PREC_FP64 ? *(int*)(hb + 5) : m;
+  const int ld_iters = grid_iters + *(int*)(hb + 6);
+  std::vector<long long> hM(nseg, 0);
+  for (int i = 0; i < nseg; ++i) hM[i] = hbi[i];
+
+  // per-job bookkeeping of the pass
+  for (int i = 0; i < nseg; ++i) {
+    Job& j = jobs_[live_[i]];
+    if (j.state != JOB_RUNNING) continue;
+    const int r = j.round;
+    if (r < NANOGS_MAX_ROUNDS) {
+      j.stats.n_per_round[r] = j.N;
+      j.stats.edges_per_round[r] = searching == 1 ? m : 0;
+      j.stats.pairs_per_round[r] = hM[i];
+      j.stats.fallback_per_round[r] = searching == 1 ? fb : 0;
+      j.stats.ld_iters_per_round[r] = ld_iters;
+      j.stats.knn_retry_per_round[r] = searching == 1 ? knn_retries : 0;
+      j.stats.knn_screens_per_round[r] = searching == 1 ? knn_screens : 0;
+      j.stats.requery_per_round[r] = searching == 1 ? requeried : 0;
+    }
+  }
+
   cur_ ^= 1;
   Ntot_ = nn;
 

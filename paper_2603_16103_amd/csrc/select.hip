@@ -420,19 +420,22 @@ k_topp_seg(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
   }
 }
 
-// segment of every pair (sort key) and the identity payload
-__global__ void k_pair_seg(const int* __restrict__ pair_a, const int* __restrict__ sg, int M,
+// segment of every pair (sort key) and the identity payload, over cap
+// slots: slots at and past the pair count *d_M get key `pad` (sorted last)
+__global__ void k_pair_seg(const int* __restrict__ pair_a, const int* __restrict__ sg,
+                           const int* __restrict__ d_M, int cap, unsigned pad,
                            unsigned* __restrict__ key, int* __restrict__ idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  key[i] = (unsigned)sg[pair_a[i]];
+  if (i >= cap) return;
+  key[i] = i < *d_M ? (unsigned)sg[pair_a[i]] : pad;
   idx[i] = i;
 }
 
 // [pstart[s], pend[s]) = run of segment s in the sorted keys
-__global__ void k_seg_runs(const unsigned* __restrict__ key, int M, int* __restrict__ pstart,
-                           int* __restrict__ pend) {
+__global__ void k_seg_runs(const unsigned* __restrict__ key, const int* __restrict__ d_M,
+                           int* __restrict__ pstart, int* __restrict__ pend) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = *d_M;
   if (i >= M) return;
   const unsigned s = key[i];
   if (i == 0 || key[i - 1] != s) pstart[s] = i;
@@ -510,40 +513,17 @@ void build_adjacency(const int* ea, const int* eb, const float* cost, long long 
   }
 }
 
-SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
-                          const long long* hP, int* partner, void* temp, hipStream_t st,
-                          long long* d_npairs, long long* hM, const long long* dP) {
-  Carver c(temp);
-  int* pick = c.take<int>(n);
-  unsigned* pcost = c.take<unsigned>(n);
-  int* act[2] = {c.take<int>(n), c.take<int>(n)};
-  int* pair_a = c.take<int>(n / 2 + 1);
-  int* pair_b = c.take<int>(n / 2 + 1);
-  unsigned* pair_c = c.take<unsigned>(n / 2 + 1);
-  unsigned* pkey = c.take<unsigned>(n / 2 + 1);
-  int* pidx = c.take<int>(n / 2 + 1);
-  int* pstart = c.take<int>(nseg);
-  int* pend = c.take<int>(nseg);
-  long long* Pdev = c.take<long long>(nseg);
-  int* mseg = c.take<int>(nseg);
-  int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs, [3]: tail iterations
-  PickState ps;
-  ps.tkey = c.take<unsigned long long>((long long)n * kTop);
-  ps.tu = c.take<int>((long long)n * kTop);
-  ps.tn = c.take<int>(n);
-  void* stemp = (char*)temp + c.bytes();
-  long long* host = pinned_host();
-
-  fill_i32(partner, -1, n, st);
-  fill_i32(counters, 0, 64, st);
-  SelectResult r{0, 0};
-  // A fixed schedule: grid-wide iterations until about 2^11 vertices are
-  // left (each iteration leaves a bit over half of the active vertices on
-  // the synthetic scenes, about 1.2 iterations per halving), at least
-  // select_check of them, then one workgroup finishes the remaining ones on
-  // the device.  No host round trip happens before the end; the grids of
-  // later launches are sized for the expected active count (the kernels
-  // stride over the actual one).
+// The matching iterations on a fixed schedule: grid-wide iterations until
+// about 2^11 vertices are left (each iteration leaves a bit over half of the
+// active vertices on the synthetic scenes, about 1.2 iterations per
+// halving), at least select_check of them, then one workgroup finishes the
+// remaining ones on the device.  No host round trip happens; the grids of
+// later launches are sized for the expected active count (the kernels stride
+// over the actual one).  counters[2] receives the pairs, counters[3] the
+// iterations of the finish.  Returns the grid-wide iterations launched.
+int ld_iterations(const Adjacency& adj, int n, const int* lg, int* partner, int* pick,
+                  unsigned* pcost, int* const act[2], int* pair_a, int* pair_b,
+                  unsigned* pair_c, int* counters, const PickState& ps, hipStream_t st) {
   int grid_iters = (int)std::ceil(1.2 * std::log2(std::max((double)n, 2.0) / 2048.0));
   grid_iters = std::max(grid_iters, tuning_for(n).select_check);
   grid_iters = std::min(grid_iters, 24);
@@ -571,6 +551,38 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
                                        counters, (it - 1) & 1, pick, pcost, lg, pair_a, pair_b,
                                        pair_c, counters + 2, ps, counters + 3);
   NG_LAUNCH_CHECK();
+  return it;
+}
+
+SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
+                          const long long* hP, int* partner, void* temp, hipStream_t st,
+                          long long* d_npairs, long long* hM, const long long* dP) {
+  Carver c(temp);
+  int* pick = c.take<int>(n);
+  unsigned* pcost = c.take<unsigned>(n);
+  int* act[2] = {c.take<int>(n), c.take<int>(n)};
+  int* pair_a = c.take<int>(n / 2 + 1);
+  int* pair_b = c.take<int>(n / 2 + 1);
+  unsigned* pair_c = c.take<unsigned>(n / 2 + 1);
+  unsigned* pkey = c.take<unsigned>(n / 2 + 1);
+  int* pidx = c.take<int>(n / 2 + 1);
+  int* pstart = c.take<int>(nseg);
+  int* pend = c.take<int>(nseg);
+  long long* Pdev = c.take<long long>(nseg);
+  int* mseg = c.take<int>(nseg);
+  int* counters = c.take<int>(64);  // [0], [1]: active counts, [2]: pairs, [3]: tail iterations
+  PickState ps;
+  ps.tkey = c.take<unsigned long long>((long long)n * kTop);
+  ps.tu = c.take<int>((long long)n * kTop);
+  ps.tn = c.take<int>(n);
+  void* stemp = (char*)temp + c.bytes();
+  long long* host = pinned_host();
+
+  fill_i32(partner, -1, n, st);
+  fill_i32(counters, 0, 64, st);
+  SelectResult r{0, 0};
+  const int it = ld_iterations(adj, n, lg, partner, pick, pcost, act, pair_a, pair_b, pair_c,
+                               counters, ps, st);
   if (dP) {
     // device budget, single segment: keep the P smallest of the matching
     k_topp_seg<<<1, 1024, 0, st>>>(pair_a, pair_b, pair_c, nullptr, pstart, pend, counters + 2, dP,
@@ -593,12 +605,13 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
     fill_i32(pstart, 0, nseg, st);
     fill_i32(pend, 0, nseg, st);
     if (M > 0) {
-      k_pair_seg<<<blocks_for(M, 256), 256, 0, st>>>(pair_a, sg, (int)M, pkey, pidx);
+      k_pair_seg<<<blocks_for(M, 256), 256, 0, st>>>(pair_a, sg, counters + 2, (int)M,
+                                                     (unsigned)nseg, pkey, pidx);
       NG_LAUNCH_CHECK();
       int bits = 1;
       while ((1 << bits) < nseg) ++bits;
       sort_pairs_u32(pkey, pidx, M, bits, stemp, st);
-      k_seg_runs<<<blocks_for(M, 256), 256, 0, st>>>(pkey, (int)M, pstart, pend);
+      k_seg_runs<<<blocks_for(M, 256), 256, 0, st>>>(pkey, counters + 2, pstart, pend);
       NG_LAUNCH_CHECK();
     }
     idx = pidx;
@@ -629,6 +642,64 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   }
   r.pairs = total;
   return r;
+}
+
+// As select_pairs, with nothing read back and no synchronisation: the
+// budgets come from hP in page-locked host memory (copied asynchronously;
+// the caller keeps them unchanged until the stream reaches this point), the
+// pairs kept per segment stay in device memory (*d_mseg, nseg ints) and so
+// does the number of matching iterations the single-workgroup finish ran
+// (*d_tail_iters).  Returns the grid-wide iterations launched.  Launches
+// that depend on the pair count cover its capacity (n / 2 + 1).
+int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
+                       const long long* hP_pinned, int* partner, void* temp, hipStream_t st,
+                       const int** d_mseg, const int** d_tail_iters) {
+  Carver c(temp);
+  int* pick = c.take<int>(n);
+  unsigned* pcost = c.take<unsigned>(n);
+  int* act[2] = {c.take<int>(n), c.take<int>(n)};
+  int* pair_a = c.take<int>(n / 2 + 1);
+  int* pair_b = c.take<int>(n / 2 + 1);
+  unsigned* pair_c = c.take<unsigned>(n / 2 + 1);
+  unsigned* pkey = c.take<unsigned>(n / 2 + 1);
+  int* pidx = c.take<int>(n / 2 + 1);
+  int* pstart = c.take<int>(nseg);
+  int* pend = c.take<int>(nseg);
+  long long* Pdev = c.take<long long>(nseg);
+  int* mseg = c.take<int>(nseg);
+  int* counters = c.take<int>(64);
+  PickState ps;
+  ps.tkey = c.take<unsigned long long>((long long)n * kTop);
+  ps.tu = c.take<int>((long long)n * kTop);
+  ps.tn = c.take<int>(n);
+  void* stemp = (char*)temp + c.bytes();
+
+  fill_i32(partner, -1, n, st);
+  fill_i32(counters, 0, 64, st);
+  NG_HIP(hipMemcpyAsync(Pdev, hP_pinned, nseg * sizeof(long long), hipMemcpyHostToDevice, st));
+  const int it = ld_iterations(adj, n, lg, partner, pick, pcost, act, pair_a, pair_b, pair_c,
+                               counters, ps, st);
+  const int* idx = nullptr;
+  if (nseg > 1) {
+    const int cap = n / 2 + 1;
+    fill_i32(pstart, 0, nseg, st);
+    fill_i32(pend, 0, nseg, st);
+    k_pair_seg<<<blocks_for(cap, 256), 256, 0, st>>>(pair_a, sg, counters + 2, cap,
+                                                     (unsigned)nseg, pkey, pidx);
+    NG_LAUNCH_CHECK();
+    int bits = 1;
+    while ((1 << bits) <= nseg) ++bits;  // the padding key nseg included
+    sort_pairs_u32(pkey, pidx, cap, bits, stemp, st);
+    k_seg_runs<<<blocks_for(cap, 256), 256, 0, st>>>(pkey, counters + 2, pstart, pend);
+    NG_LAUNCH_CHECK();
+    idx = pidx;
+  }
+  k_topp_seg<<<nseg, 1024, 0, st>>>(pair_a, pair_b, pair_c, idx, pstart, pend, counters + 2, Pdev,
+                                     lg, partner, mseg);
+  NG_LAUNCH_CHECK();
+  *d_mseg = mseg;
+  *d_tail_iters = counters + 3;
+  return it;
 }
 
 }  // namespace ng
