@@ -31,6 +31,34 @@ __global__ void k_iota_e(int* v, int n) {
   if (i < n) v[i] = i;
 }
 
+// The counts of a pass, gathered into one block for a single readback:
+// out[0] edges, [1] order violation flag, [2] kNN retries, [3] kNN float
+// screens, [4] rows re-queried by the local refresh, [5] FP64-fallback
+// edges, [6] iterations of the matching's finish, [8 + s] pairs kept by
+// segment s.  The kNN's statistics are taken right after the search (the
+// temporary area that holds them is reused), the rest after the selection.
+__global__ void k_stats_knn(const int* __restrict__ unsorted, const int* __restrict__ kc,
+                            const int* __restrict__ dcount, long long* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[1] = *unsorted;
+    out[2] = kc[1];
+    out[3] = *(const long long*)(kc + 8);
+    out[4] = dcount ? *dcount : 0;
+  }
+}
+
+__global__ void k_stats_select(const long long* __restrict__ d_m, const int* __restrict__ fb,
+                               const int* __restrict__ tail, const int* __restrict__ mseg,
+                               int nseg, long long* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    out[0] = *d_m;
+    out[5] = *fb;
+    out[6] = *tail;
+  }
+  if (i < nseg) out[8 + i] = mseg[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -81,6 +109,7 @@ struct EngineWs {
   unsigned* keys;
   int* perm;
   int* counters;
+  long long* stats;  // a pass's counts (k_stats_knn / k_stats_select)
   long long* d_m;
   SegInfo* seg;
   float* crn;
@@ -114,6 +143,7 @@ static EngineWs carve_engine(void* base, long long R, int K, int J) {
   s.keys = c.take<unsigned>(R);
   s.perm = c.take<int>(R);
   s.counters = c.take<int>(64);
+  s.stats = c.take<long long>(8 + (size_t)J);
   s.d_m = c.take<long long>(8);
   s.seg = c.take<SegInfo>(J);
   s.crn = c.take<float>((size_t)J * NG_CRN_ROW);
@@ -350,14 +380,10 @@ int Engine::step(StageTimer* T) {
     knn_query(a.cen, (int)N, K_, sg, W.seg, class_mask, entries, W.temp, true, 0, W.nbr, T, st_);
   }
   if (refresh_local) knn_save_log(a.lg, W.nbr, (int)N, K_, hs[0].keff, W.nbr_log, st_);
-  {
-    // the kNN's statistics (retries, screens) live in the temporary area the
-    // later stages reuse: keep copies for the end of the pass
-    const int* kc = carve_knn(W.temp, N, entries, K_, nullptr).counters;
-    NG_HIP(hipMemcpyAsync(W.counters + 8, kc + 1, sizeof(int), hipMemcpyDeviceToDevice, st_));
-    NG_HIP(hipMemcpyAsync(W.counters + 10, kc + 8, sizeof(long long), hipMemcpyDeviceToDevice,
-                          st_));
-  }
+  // the kNN's statistics live in the temporary area the next stages reuse
+  k_stats_knn<<<1, 64, 0, st_>>>(W.counters + 2, carve_knn(W.temp, N, entries, K_, nullptr).counters,
+                                 incremental ? dcount : nullptr, W.stats);
+  NG_LAUNCH_CHECK();
   tk = T ? T->start(NANOGS_T_EDGES) : -1;
   const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
   launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
@@ -398,7 +424,6 @@ int Engine::step(StageTimer* T) {
 
   // the pass's counts come back with the merge's synchronisation
   long long* hb = hb_;
-  int* hbi = (int*)(hb + 8);  // per segment pairs
 
   // single running job with a trace buffer: provenance pairs of this pass
   int* trace = nullptr;
@@ -423,14 +448,11 @@ int Engine::step(StageTimer* T) {
       ++j.lod_levels;
     }
   }
-  NG_HIP(hipMemcpyAsync(hb + 0, W.d_m, sizeof(long long), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 1, W.counters + 2, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 2, W.counters + 8, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 3, W.counters + 10, sizeof(long long), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 4, dcount, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 5, fb_count, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hb + 6, d_tail, sizeof(int), hipMemcpyDeviceToHost, st_));
-  NG_HIP(hipMemcpyAsync(hbi, d_mseg, nseg * sizeof(int), hipMemcpyDeviceToHost, st_));
+  k_stats_select<<<blocks_for(nseg, 256), 256, 0, st_>>>(W.d_m, fb_count, d_tail, d_mseg, nseg,
+                                                          W.stats);
+  NG_LAUNCH_CHECK();
+  NG_HIP(hipMemcpyAsync(hb, W.stats, (8 + (size_t)nseg) * sizeof(long long),
+                        hipMemcpyDeviceToHost, st_));
   tk = T ? T->start(NANOGS_T_MERGE) : -1;
   // the local refresh of the next pass needs the new index of every splat
   int* par = parent ? parent : (refresh_local ? W.parent : nullptr);
@@ -446,14 +468,15 @@ int Engine::step(StageTimer* T) {
   if (T) T->stop(tk);
   // merge_compact synchronised the stream: the counts are in hb
   const long long m = hb[0];
-  if (*(int*)(hb + 1) != 0) throw HipError{"internal: working set not in Morton order"};
-  const long long knn_retries = *(int*)(hb + 2);
+  if (hb[1] != 0) throw HipError{"internal: working set not in Morton order"};
+  const long long knn_retries = hb[2];
   const long long knn_screens = hb[3];
-  const long long requeried = incremental ? *(int*)(hb + 4) : N;
-  const long long fb = o_.precision != NANOGS_PREC_FP64 ? *(int*)(hb + 5) : m;
-  const int ld_iters = grid_iters + *(int*)(hb + 6);
+  const long long requeried = incremental ? hb[4] : N;
+  const long long fb = o_.precision != NANOGS_PREC_FP64 ? hb[5] : m;
+  if (hb[6] < 0) throw HipError{"internal: the matching did not converge"};
+  const int ld_iters = grid_iters + (int)hb[6];
   std::vector<long long> hM(nseg, 0);
-  for (int i = 0; i < nseg; ++i) hM[i] = hbi[i];
+  for (int i = 0; i < nseg; ++i) hM[i] = hb[8 + i];
 
   // per-job bookkeeping of the pass
   for (int i = 0; i < nseg; ++i) {

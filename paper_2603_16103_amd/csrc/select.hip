@@ -266,7 +266,11 @@ k_ld_match(const int* __restrict__ act, const int* __restrict__ act_count, int n
 // the active list (lists swap between A and B) until it is empty, with no
 // launch or host round trip per iteration.  cnt[0] / cnt[1]: the counts of
 // lists A / B; the list the last grid-wide match wrote is `in_sel`.
-// iters (device) receives the number of iterations run here.
+// iters (device) receives the number of iterations run here.  Every
+// iteration retires at least one active vertex (the smallest live edge is
+// both its ends' pick; a vertex with no free neighbour leaves), so more than
+// (first count + 1) iterations mean a broken adjacency: the loop stops there
+// and iters receives minus the count, which the callers report as an error.
 __global__ void __launch_bounds__(kMatchBlock)
 k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
           const int* __restrict__ au, int* __restrict__ partner, int* __restrict__ listA,
@@ -279,6 +283,8 @@ k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
   __shared__ int s_n;
   int sel = in_sel;
   int it = 0;
+  int limit = 0;
+  bool broken = false;
   while (true) {
     int* in = sel == 0 ? listA : listB;
     int* out = sel == 0 ? listB : listA;
@@ -288,6 +294,11 @@ k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
     __syncthreads();
     const int c = s_n;
     if (c == 0) break;
+    if (it == 0) limit = c + 1;
+    if (it > limit) {
+      broken = true;
+      break;
+    }
     for (int i = threadIdx.x; i < c; i += kMatchBlock) {
       const int v = in[i];
       unsigned long long best = KEY_MAX;
@@ -306,7 +317,7 @@ k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
     sel ^= 1;
     ++it;
   }
-  if (threadIdx.x == 0) *iters = it;
+  if (threadIdx.x == 0) *iters = broken ? -it : it;
 }
 
 // ---- budget: keep the P smallest (cost, i, j) of each segment's matching --
@@ -596,6 +607,7 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   }
   NG_HIP(hipMemcpyAsync(host, counters, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   NG_HIP(hipStreamSynchronize(st));
+  if (((const int*)host)[3] < 0) throw HipError{"internal: the matching did not converge"};
   r.iters = it + ((const int*)host)[3];
   const long long M = ((const int*)host)[2];
   // per-segment budgets (the matching of each segment, then its P smallest)

@@ -59,6 +59,64 @@ k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, long long n,
   }
 }
 
+// Two-kernel scan for up to kScanDirect tiles: the tile sums, then every
+// tile adds up the sums of the tiles before it (a few KB that all blocks
+// read from L2) and scans itself.  Reads the input twice and writes it
+// once, in two launches.
+constexpr int kScanDirect = 8192;
+
+__device__ int block_sum(int v) {
+  __shared__ int wsum[SCAN_BS / 64];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  if (lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_BS / 64; ++i) t += wsum[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_reduce(const int* __restrict__ in, long long n, int* __restrict__ sums) {
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const long long idx = base + i;
+    s += idx < n ? in[idx] : 0;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_apply(const int* __restrict__ in, int* __restrict__ out, long long n,
+             const int* __restrict__ sums, int* __restrict__ total) {
+  int pre = 0;
+  for (int t = threadIdx.x; t < (int)blockIdx.x; t += SCAN_BS) pre += sums[t];
+  pre = block_sum(pre);
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const long long idx = base + i;
+    v[i] = idx < n ? in[idx] : 0;
+    s += v[i];
+  }
+  int tot;
+  int run = block_exclusive_scan(s, &tot) + pre;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const long long idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += v[i];
+  }
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = pre + tot;
+}
+
 __global__ void __launch_bounds__(SCAN_BS)
 k_scan_add(int* __restrict__ out, long long n, const int* __restrict__ tile_off) {
   const int add = tile_off[blockIdx.x];
@@ -130,6 +188,13 @@ void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* 
   int* sums = c.take<int>(nt);
   int* offs = c.take<int>(nt);
   void* rest = (char*)temp + c.bytes();
+  if (nt <= kScanDirect) {
+    k_scan_reduce<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, n, sums);
+    NG_LAUNCH_CHECK();
+    k_scan_apply<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, out, n, sums, total);
+    NG_LAUNCH_CHECK();
+    return;
+  }
   k_scan_tiles<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, out, n, sums, nullptr);
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(sums, offs, nt, total, rest, st);
