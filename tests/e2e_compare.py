@@ -109,3 +109,52 @@ def gpu_merges(pairs_per_round, gpu_trace):
         out.append(gpu_trace[off:off + cnt])
         off += cnt
     return out
+
+
+def compare_by_origin(gpu_out, gpu_origin, ref):
+    """Final outputs matched by provenance (no merge trace needed): for every
+    oracle output splat whose origin also names a GPU output splat, the
+    per-field errors of that pair.  Returns the fraction of oracle splats
+    matched and the fraction of matched pairs within E2E_BARS on every
+    field."""
+    pos, ls, rot, op, sh = (np.asarray(a, dtype=np.float64) for a in gpu_out)
+    g_row = {int(o): i for i, o in enumerate(np.asarray(gpu_origin).tolist())}
+    ri = np.array([i for i, o in enumerate(ref.origin.tolist()) if int(o) in g_row], np.int64)
+    gi = np.array([g_row[int(ref.origin[i])] for i in ri], np.int64)
+    out = {"matched": ri.size / max(ref.n, 1)}
+    if ri.size == 0:
+        out["within"] = 0.0
+        return out
+    mu_r = ref.mu[ri]
+    e_mu = np.abs(pos[gi] - mu_r).max(1) / np.maximum(np.abs(mu_r).max(1), 1.0)
+    q_g = rot[gi] / np.linalg.norm(rot[gi], axis=1, keepdims=True)
+    Sg = O.covariance(np.exp(ls[gi]), q_g)
+    Sr = O.covariance(ref.s[ri], ref.q[ri])
+    e_sig = np.linalg.norm(Sg - Sr, axis=(1, 2)) / np.linalg.norm(Sr, axis=(1, 2))
+    e_al = np.abs(1.0 / (1.0 + np.exp(-op[gi])) - ref.alpha[ri])
+    f_r = ref.f[ri]
+    e_f = np.linalg.norm(sh[gi] - f_r, axis=1) / np.maximum(np.linalg.norm(f_r, axis=1), 1e-3)
+    ok = ((e_mu < E2E_BARS["mu"]) & (e_sig < E2E_BARS["sigma"]) & (e_al < E2E_BARS["alpha"])
+          & (e_f < E2E_BARS["f"]))
+    out["within"] = float(np.mean(ok))
+    return out
+
+
+def compare_by_position(gpu_out, ref):
+    """Final outputs matched by centre (for results that carry no
+    provenance): the fraction of oracle splats whose nearest GPU centre lies
+    within the centre bar and whose covariance, opacity and SH there are
+    within their bars."""
+    from scipy.spatial import cKDTree
+    pos, ls, rot, op, sh = (np.asarray(a, dtype=np.float64) for a in gpu_out)
+    d, gi = cKDTree(pos).query(ref.mu, k=1)
+    e_mu = d / np.maximum(np.abs(ref.mu).max(1), 1.0)
+    q_g = rot[gi] / np.linalg.norm(rot[gi], axis=1, keepdims=True)
+    Sg = O.covariance(np.exp(ls[gi]), q_g)
+    Sr = O.covariance(ref.s, ref.q)
+    e_sig = np.linalg.norm(Sg - Sr, axis=(1, 2)) / np.linalg.norm(Sr, axis=(1, 2))
+    e_al = np.abs(1.0 / (1.0 + np.exp(-op[gi])) - ref.alpha)
+    e_f = np.linalg.norm(sh[gi] - ref.f, axis=1) / np.maximum(np.linalg.norm(ref.f, axis=1), 1e-3)
+    ok = ((e_mu < E2E_BARS["mu"]) & (e_sig < E2E_BARS["sigma"]) & (e_al < E2E_BARS["alpha"])
+          & (e_f < E2E_BARS["f"]))
+    return {"within": float(np.mean(ok)), "n_gpu": int(pos.shape[0]), "n_ref": int(ref.n)}

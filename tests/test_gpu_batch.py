@@ -161,3 +161,32 @@ def test_batch_cancel_queued_and_running(gpu_lib):
     with pytest.raises(ng.NanoGSError):
         b.cancel(len(jobs) + 5)
     b.close()
+
+
+def test_batched_job_against_the_oracle(gpu_lib):
+    """One job of a batch (sharing its passes with three others) against the
+    oracle's own loop on the same scene: the same count, >= 97% of the
+    oracle's output splats found by provenance, and >= 97% of those within
+    the end-to-end field bars."""
+    import torch
+    import oracle as O
+    from tests.e2e_compare import compare_by_origin
+    ng = gpu_lib
+    scenes = [_scene(s) for s in SPECS]
+    b = ng.Batch(max_rows=sum(sc.n for sc, *_ in scenes), max_k=24, max_jobs=8)
+    sc, target, k, seed = scenes[1]
+    origin = torch.full((sc.n,), -1, dtype=torch.int32, device="cuda")
+    jobs = []
+    for i, (s_, t_, k_, sd_) in enumerate(scenes):
+        org = origin if i == 1 else None
+        jobs.append(b.submit(ng.GaussianTensors.from_scene(s_), t_, k=k_, seed=sd_, origin=org))
+    b.run()
+    res = b.result(jobs[1])
+    ref = O.simplify(sc.pos, sc.log_scale, sc.rot, sc.opacity, sc.sh, target, k, seed=seed)
+    assert res.n == ref.n == target
+    err = compare_by_origin([x.cpu().numpy() for x in (res.pos, res.log_scale, res.rot,
+                                                       res.opacity, res.sh)],
+                            origin[:res.n].cpu().numpy(), ref)
+    log("batched job vs oracle", err)
+    assert err["matched"] >= 0.97 and err["within"] >= 0.97
+    b.close()
