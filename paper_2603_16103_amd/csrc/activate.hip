@@ -123,15 +123,19 @@ __global__ void k_check_finite(const float* __restrict__ x, long long count,
 
 // thread per (row, 16-byte chunk): consecutive threads touch consecutive
 // 16-byte words of a row, so each row is read and written in full lines.
+// nonfinite (nullable): set to 1 if a copied value is NaN or infinite.
 __global__ void k_copy_sh_rows(const float4* __restrict__ src, const int* __restrict__ src_map,
                                float4* __restrict__ dst, const int* __restrict__ dst_map,
-                               int dst_base, int rows) {
+                               int dst_base, int rows, int* __restrict__ nonfinite) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)rows * 12) return;
   int r = (int)(t / 12), c = (int)(t % 12);
   int sr = src_map ? src_map[r] : r;
   int dr = dst_map ? dst_map[r] - dst_base : r;
-  dst[(long long)dr * 12 + c] = src[(long long)sr * 12 + c];
+  const float4 v = src[(long long)sr * 12 + c];
+  dst[(long long)dr * 12 + c] = v;
+  if (nonfinite && !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z) && isfinite(v.w)))
+    *nonfinite = 1;
 }
 
 __global__ void k_deactivate_work(const float4* __restrict__ cen, const int* __restrict__ lg,
@@ -241,10 +245,10 @@ void launch_check_finite(const float* x, long long count, int* nonfinite, hipStr
 }
 
 void launch_copy_sh_rows(const float* src, const int* src_map, float* dst, const int* dst_map,
-                         int dst_base, int rows, hipStream_t st) {
+                         int dst_base, int rows, hipStream_t st, int* nonfinite) {
   if (rows <= 0) return;
   k_copy_sh_rows<<<blocks_for((long long)rows * 12, 256), 256, 0, st>>>(
-      (const float4*)src, src_map, (float4*)dst, dst_map, dst_base, rows);
+      (const float4*)src, src_map, (float4*)dst, dst_map, dst_base, rows, nonfinite);
   NG_LAUNCH_CHECK();
 }
 

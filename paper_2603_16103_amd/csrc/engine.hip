@@ -230,8 +230,9 @@ bool Engine::setup_job(Job& j, int pos) {
   launch_activate_stored(j.spec.in.pos, j.spec.in.log_scale, j.spec.in.rot, j.spec.in.opacity,
                          W.perm, (int)n, (int)r0, a.cen + r0, a.lg + r0, a.shp + 2 * r0, a.org + r0,
                          a.sg + r0, pos, W.counters, st_);
-  launch_check_finite(j.spec.in.sh, n * NG_SH, W.counters, st_);
-  launch_copy_sh_rows(j.spec.in.sh, W.perm, a.sh + r0 * NG_SH, nullptr, 0, (int)n, st_);
+  // the SH rows are checked for non-finite values while they are copied
+  launch_copy_sh_rows(j.spec.in.sh, W.perm, a.sh + r0 * NG_SH, nullptr, 0, (int)n, st_,
+                      W.counters);
   NG_HIP(hipMemcpyAsync(host, W.counters, sizeof(int), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipMemcpyAsync(host + 1, box, 6 * sizeof(unsigned), hipMemcpyDeviceToHost, st_));
   NG_HIP(hipStreamSynchronize(st_));

@@ -182,9 +182,10 @@ void launch_activate_stored(const float* pos, const float* log_scale, const floa
 // Checks the SH rows for non-finite values.
 void launch_check_finite(const float* x, long long count, int* nonfinite, hipStream_t st);
 // Row copy of [rows][48] float arrays: dst[dst_row(r)] = src[src_row(r)],
-// dst_row = dst_map ? dst_map[r] - dst_base : r, src_row = src_map ? src_map[r] : r.
+// dst_row = dst_map ? dst_map[r] - dst_base : r, src_row = src_map ? src_map[r] : r;
+// *nonfinite (nullable) is set to 1 if a copied value is not finite.
 void launch_copy_sh_rows(const float* src, const int* src_map, float* dst, const int* dst_map,
-                         int dst_base, int rows, hipStream_t st);
+                         int dst_base, int rows, hipStream_t st, int* nonfinite = nullptr);
 // Working layout -> stored form at the logical positions minus lbase.
 void launch_deactivate_work(const float4* cen, const int* lg, const float4* shp, const int* org,
                             int n, int lbase, float* pos, float* log_scale, float* rot,
