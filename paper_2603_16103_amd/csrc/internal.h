@@ -76,6 +76,19 @@ NG_DEV uint32_t f2ord(float f) {
 
 NG_DEV int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Block index with each XCD's share of the grid contiguous.  Workgroups are
+// dispatched to the 8 XCDs in turn (dispatch index b runs on XCD b % 8), and
+// each XCD has its own L2; for kernels whose blocks cover consecutive rows
+// of the Morton-ordered working set, giving every XCD one contiguous range
+// keeps the rows a block shares with its neighbours in one L2.  A bijection
+// of [0, gridDim.x): XCD x takes blocks [x*per + min(x, rem), +count_x).
+constexpr unsigned kXcds = 8;
+NG_DEV unsigned xcd_block() {
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned per = G / kXcds, rem = G % kXcds, x = b % kXcds;
+  return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
 NG_DEV float ord2f(unsigned u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }

@@ -605,7 +605,7 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
             unsigned long long* __restrict__ screens, const int* __restrict__ list,
             const int* __restrict__ d_count) {
   extern __shared__ unsigned s_hist[];  // [16][bs]: two 16-bit bin counts per word
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = xcd_block() * blockDim.x + threadIdx.x;
   const int cnt = list ? *d_count : n;
   const int p = idx < cnt ? (list ? list[idx] : idx) : n;
   int ns = 0;
