@@ -267,7 +267,8 @@ size_t nanogs_knn_workspace_bytes(int64_t n, int32_t k);
  * t < k_eff = min(k, n-1) is the t-th element of {j != i} ordered by the key
  * (d2, j), d2 = ((dx*dx + dy*dy) + dz*dz) in double from the float centres,
  * no fused multiply-add; entries t >= k_eff are -1.  Exact (not
- * approximate).  mu[n][3] float, nbr[n][k] int32. */
+ * approximate).  mu[n][3] float, nbr[n][k] int32.  Reads nothing back and
+ * does not synchronise (capturable into a HIP graph). */
 nanogs_status nanogs_knn(const float* mu, int64_t n, int32_t k, int32_t* nbr,
                          void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -369,7 +370,9 @@ nanogs_status nanogs_select_dev(const int32_t* ei, const int32_t* ej,
  * positive, w >= 0).  Centre, covariance, opacity and the eigen-
  * decomposition are computed in double from the float inputs; f_m is formed
  * in float with the mixture weights rounded to float.  out must hold n
- * splats and must not alias in; the new count goes to device int64 *d_nout.  origin, when
+ * splats and must not alias in; the new count goes to device int64 *d_nout
+ * (nothing is read back: the call does not synchronise and can be captured
+ * into a HIP graph; rows past the count are left as they were).  origin, when
  * both in and out give one, becomes the smaller origin of a pair. */
 size_t nanogs_merge_workspace_bytes(int64_t n);
 nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,

@@ -334,6 +334,7 @@ size_t merge_ws_bytes(long long n) {
   Carver c(nullptr);
   take_packed(c, n);
   take_packed(c, n);
+  c.take<int>(64);
   return c.bytes() + merge_temp_bytes(n);
 }
 
@@ -770,15 +771,18 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n, const int32_t* pa
     Carver c(ws);
     Packed a = take_packed(c, n);
     Packed b = take_packed(c, n);
+    int* dcount = c.take<int>(64);
     void* temp = (char*)ws + c.bytes();
     launch_pack_splats(in->mu, in->scale, in->quat, in->alpha, in->origin, (int)n, a.cen, a.lg,
                        a.shp, a.org, stream);
-    const long long nout = merge_compact(a.cen, nullptr, a.shp, in->sh, a.org, (int)n, partner,
-                                         b.cen, b.lg, b.shp, out->sh, b.org, nullptr, temp,
-                                         stream, nullptr, nullptr, nullptr, nullptr, 1);
-    launch_unpack_splats(b.cen, b.shp, b.org, (int)nout, out->mu, out->scale, out->quat,
-                         out->alpha, (in->origin && out->origin) ? out->origin : nullptr, stream);
-    set_i64((long long*)d_nout, nout, stream);
+    // the new count stays on the device (no host read: capturable)
+    merge_compact(a.cen, nullptr, a.shp, in->sh, a.org, (int)n, partner, b.cen, b.lg, b.shp,
+                  out->sh, b.org, nullptr, temp, stream, dcount, nullptr, nullptr, nullptr, 1,
+                  nullptr, false);
+    launch_unpack_splats(b.cen, b.shp, b.org, (int)n, out->mu, out->scale, out->quat,
+                         out->alpha, (in->origin && out->origin) ? out->origin : nullptr, stream,
+                         dcount);
+    widen_i32(dcount, (long long*)d_nout, stream);
     return NANOGS_OK;
   });
 }

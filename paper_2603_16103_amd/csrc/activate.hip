@@ -204,8 +204,10 @@ __global__ void k_pack(const float* __restrict__ mu, const float* __restrict__ s
 __global__ void k_unpack(const float4* __restrict__ cen, const float4* __restrict__ shp,
                          const int* __restrict__ org, int n, float* __restrict__ mu,
                          float* __restrict__ scale, float* __restrict__ quat,
-                         float* __restrict__ alpha, int* __restrict__ origin) {
+                         float* __restrict__ alpha, int* __restrict__ origin,
+                         const int* __restrict__ d_n) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d_n) n = min(n, *d_n);
   if (p >= n) return;
   long long p3 = 3 * (long long)p, p4 = 4 * (long long)p;
   float4 c = cen[p], a = shp[2 * (long long)p], q = shp[2 * (long long)p + 1];
@@ -270,9 +272,11 @@ void launch_pack_splats(const float* mu, const float* scale, const float* quat, 
 }
 
 void launch_unpack_splats(const float4* cen, const float4* shp, const int* org, int n, float* mu,
-                          float* scale, float* quat, float* alpha, int* origin, hipStream_t st) {
+                          float* scale, float* quat, float* alpha, int* origin, hipStream_t st,
+                          const int* d_n) {
   if (n <= 0) return;
-  k_unpack<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, org, n, mu, scale, quat, alpha, origin);
+  k_unpack<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, org, n, mu, scale, quat, alpha, origin,
+                                               d_n);
   NG_LAUNCH_CHECK();
 }
 

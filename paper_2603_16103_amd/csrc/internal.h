@@ -174,6 +174,8 @@ void fill_i32(int* p, int v, long long n, hipStream_t st);
 void count_to_i32(const long long* d, long long cap, int* out, hipStream_t st);
 void fill_u64(unsigned long long* p, unsigned long long v, long long n, hipStream_t st);
 void set_i64(long long* d, long long v, hipStream_t st);
+// *d = *s (device int32 -> device int64, one thread).
+void widen_i32(const int* s, long long* d, hipStream_t st);
 // Small page-locked host buffer (64 int64 slots) for counts read back by the
 // host; one per calling thread, kept for the life of the process.
 long long* pinned_host();
@@ -208,7 +210,7 @@ void launch_pack_splats(const float* mu, const float* scale, const float* quat, 
                         const int* origin, int n, float4* cen, int* lg, float4* shp, int* org,
                         hipStream_t st);
 void launch_unpack_splats(const float4* cen, const float4* shp, const int* org, int n, float* mu,
-                          float* scale, float* quat, float* alpha, int* origin, hipStream_t st);
+                          float* scale, float* quat, float* alpha, int* origin, hipStream_t st, const int* d_n = nullptr);
 void launch_activate_plain(const float* pos, const float* log_scale, const float* rot,
                            const float* opacity, int n, float* mu, float* scale, float* quat,
                            float* alpha, int* nonfinite, hipStream_t st);
@@ -382,12 +384,14 @@ size_t merge_temp_bytes(long long n);
 // the lower logical index.
 // parent (nullable, indexed by logical index) receives the logical index of
 // the output splat each input splat becomes (both ends of a pair the same).
-// Synchronises st.
+// Synchronises st, unless host_count is false (only without seg): then
+// nothing is read back, the new count is left in *d_nout_i32 (required) and
+// the result is -1.
 long long merge_compact(const float4* cen, const int* lg, const float4* shp, const float* sh,
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
                         hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
-                        const SegInfo* seg, int nseg, int* parent = nullptr);
+                        const SegInfo* seg, int nseg, int* parent = nullptr, bool host_count = true);
 
 // prune.hip -- opacity pre-filter (tau' = min(tau, median alpha), keep alpha >= tau')
 size_t prune_temp_bytes(long long n);

@@ -1088,6 +1088,23 @@ __global__ void k_save_log(const int* __restrict__ lg, const int* __restrict__ n
   nbr_log[(long long)lg[p] * k_out + t] = t < keff && e >= 0 ? lg[e] : -1;
 }
 
+// The one-segment descriptor of the plain entry, written on the device (its
+// box from the bounds kernel), so the entry reads nothing back.
+__global__ void k_plain_seg(SegInfo* __restrict__ s, const unsigned* __restrict__ box, int n,
+                            int LT, int keff, int kclass) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int a = 0; a < 6; ++a) s->box[a] = box[a];
+    s->row0 = 0;
+    s->nrows = n;
+    s->LT = LT;
+    s->toff = 0;
+    s->keff = keff;
+    s->kclass = kclass;
+    s->crn = 0;
+    s->next = 0;
+  }
+}
+
 __global__ void k_invert(const float4* __restrict__ cen, int n, int* __restrict__ inv) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) inv[__float_as_int(cen[p].w)] = p;
@@ -1297,23 +1314,15 @@ void knn_plain(const float* mu, int n, int k, int keff, int* nbr, void* ws, hipS
   sort_pairs_u32(keys, perm, n, kSortKeyBits, rest, st);
   k_gather_cen<<<blocks_for(n, 256), 256, 0, st>>>(mu, perm, n, cen);
   NG_LAUNCH_CHECK();
-  SegInfo h;
-  std::memset(&h, 0, sizeof(h));
-  h.row0 = 0;
-  h.nrows = n;
-  h.LT = table_level(n);
-  h.toff = 0;
-  h.keff = keff;
-  h.kclass = kclass_of(keff);
-  NG_HIP(hipMemcpyAsync(dseg, &h, sizeof(h), hipMemcpyHostToDevice, st));
-  NG_HIP(hipMemcpyAsync(dseg->box, boxmem, 6 * sizeof(unsigned), hipMemcpyDeviceToDevice, st));
-  const long long entries = table_entries(h.LT);
+  const int LT = table_level(n);
+  const int kclass = kclass_of(keff);
+  k_plain_seg<<<1, 64, 0, st>>>(dseg, boxmem, n, LT, keff, kclass);
+  NG_LAUNCH_CHECK();
+  const long long entries = table_entries(LT);
   KnnMem m = carve_knn(rest, n, entries, k, nullptr);
   fill_i32(m.counters, 0, 1, st);  // order check: sorted above by the same keys
   knn_build(cen, n, nullptr, dseg, entries, rest, m.counters, st);
-  knn_query(cen, n, k, nullptr, dseg, class_bit(h.kclass), entries, rest, false, 1, nbr, nullptr, st);
-  // the host copy of h must outlive the async copy
-  NG_HIP(hipStreamSynchronize(st));
+  knn_query(cen, n, k, nullptr, dseg, class_bit(kclass), entries, rest, false, 1, nbr, nullptr, st);
 }
 
 }  // namespace ng

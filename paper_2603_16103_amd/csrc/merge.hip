@@ -226,8 +226,10 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
                               float4* __restrict__ cen_o, int* __restrict__ lg_o,
                               float4* __restrict__ shp_o, int* __restrict__ org_o,
                               float4* __restrict__ desc, int* __restrict__ trace,
-                              int* __restrict__ trace_count, int* __restrict__ parent) {
+                              int* __restrict__ trace_count, int* __restrict__ parent,
+                              const int* __restrict__ d_nout) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d_nout) nout = min(nout, *d_nout);
   if (q >= nout) return;
   const int p = order[q];
   const int lp = logical(lg, p);
@@ -285,8 +287,9 @@ __global__ void k_merge_attrs(const float4* __restrict__ cen, const int* __restr
 
 // thread per (output row, 16-byte chunk)
 __global__ void k_merge_sh(const float4* __restrict__ sh, const float4* __restrict__ desc, int nout,
-                           float4* __restrict__ sh_o) {
+                           float4* __restrict__ sh_o, const int* __restrict__ d_nout) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d_nout) nout = min(nout, *d_nout);
   if (t >= (long long)nout * 12) return;
   const int q = (int)(t / 12), c = (int)(t % 12);
   const float4 dq = desc[q];
@@ -321,7 +324,7 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
                         const int* org, int n, const int* partner, float4* cen_o, int* lg_o,
                         float4* shp_o, float* sh_o, int* org_o, int* trace, void* temp,
                         hipStream_t st, int* d_nout_i32, const int* sg, int* sg_o,
-                        const SegInfo* seg, int nseg, int* parent) {
+                        const SegInfo* seg, int nseg, int* parent, bool host_count) {
   Carver c(temp);
   int* keep = c.take<int>(n);
   int* newpos = c.take<int>(n);
@@ -342,9 +345,21 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   k_out_keys<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, n, partner, keep, newpos,
                                                  seg ? sg : nullptr, seg, keys, order);
   NG_LAUNCH_CHECK();
-  NG_HIP(hipMemcpyAsync(host, counters, sizeof(int), hipMemcpyDeviceToHost, st));
   if (d_nout_i32)
     NG_HIP(hipMemcpyAsync(d_nout_i32, counters, sizeof(int), hipMemcpyDeviceToDevice, st));
+  if (!host_count) {
+    // the count stays on the device: the launches cover n rows and read it
+    k_merge_attrs<<<blocks_for(n, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order, n,
+                                                      rsum, nullptr, nullptr, nullptr, cen_o,
+                                                      lg_o, shp_o, org_o, desc, trace,
+                                                      counters + 2, parent, counters);
+    NG_LAUNCH_CHECK();
+    k_merge_sh<<<blocks_for((long long)n * 12, 256), 256, 0, st>>>((const float4*)sh, desc, n,
+                                                                   (float4*)sh_o, counters);
+    NG_LAUNCH_CHECK();
+    return -1;
+  }
+  NG_HIP(hipMemcpyAsync(host, counters, sizeof(int), hipMemcpyDeviceToHost, st));
   NG_HIP(hipStreamSynchronize(st));
   const long long nout = *(int*)host;
   if (seg && nout > 0) {
@@ -363,10 +378,11 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
     k_merge_attrs<<<blocks_for(nout, 256), 256, 0, st>>>(cen, lg, shp, org, n, partner, order,
                                                          (int)nout, rsum, seg ? sg : nullptr,
                                                          sg_o, seg, cen_o, lg_o, shp_o, org_o,
-                                                         desc, trace, counters + 2, parent);
+                                                         desc, trace, counters + 2, parent,
+                                                         nullptr);
     NG_LAUNCH_CHECK();
     k_merge_sh<<<blocks_for(nout * 12, 256), 256, 0, st>>>((const float4*)sh, desc, (int)nout,
-                                                           (float4*)sh_o);
+                                                           (float4*)sh_o, nullptr);
     NG_LAUNCH_CHECK();
   }
   return nout;

@@ -141,6 +141,10 @@ __global__ void k_set_i64(long long* d, long long v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
 }
 
+__global__ void k_widen_i32(const int* __restrict__ s, long long* __restrict__ d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d = *s;
+}
+
 }  // namespace
 
 namespace {
@@ -153,6 +157,11 @@ void set_tuning(int bucket, const Tuning& t) { g_tuning[bucket] = t; }
 
 void set_i64(long long* d, long long v, hipStream_t st) {
   k_set_i64<<<1, 64, 0, st>>>(d, v);
+  NG_LAUNCH_CHECK();
+}
+
+void widen_i32(const int* s, long long* d, hipStream_t st) {
+  k_widen_i32<<<1, 64, 0, st>>>(s, d);
   NG_LAUNCH_CHECK();
 }
 

@@ -427,14 +427,14 @@ def deactivate(s: SplatTensors, g: GaussianTensors | None = None):
     return g
 
 
-def knn(mu, k: int):
-    """mu [n,3] float32 cuda -> nbr [n,k] int32."""
+def knn(mu, k: int, ws=None):
+    """mu [n,3] float32 cuda -> nbr [n,k] int32.  Reads nothing back."""
     torch = _torch()
     lib = load()
     n = int(mu.shape[0])
     nbr = torch.empty((n, k), dtype=torch.int32, device="cuda")
     nb = lib.nanogs_knn_workspace_bytes(n, k)
-    ws = _workspace(nb)
+    ws = ws if ws is not None else _workspace(nb)
     _check(lib.nanogs_knn(_ptr(mu), n, k, _ptr(nbr), _ptr(ws), nb, _stream()))
     return nbr
 
@@ -568,6 +568,37 @@ def select_dev(ei, ej, cost, d_m, n: int, d_max_pairs, ws=None):
                                  _ptr(d_max_pairs), _ptr(partner), _ptr(dn), _ptr(ws), nb,
                                  _stream()))
     return partner[:n], dn
+
+
+def edges_dev(nbr, ws=None):
+    """edges with the count left on the device: (ei, ej) of capacity n*k and
+    d_m (int64 [1] cuda).  Reads nothing back."""
+    torch = _torch()
+    lib = load()
+    n, k = int(nbr.shape[0]), int(nbr.shape[1])
+    ei = torch.empty(max(n * k, 1), dtype=torch.int32, device="cuda")
+    ej = torch.empty(max(n * k, 1), dtype=torch.int32, device="cuda")
+    dm = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_edges_workspace_bytes(n, k)
+    ws = ws if ws is not None else _workspace(nb)
+    _check(lib.nanogs_edges(_ptr(nbr), n, k, _ptr(ei), _ptr(ej), _ptr(dm), _ptr(ws), nb,
+                            _stream()))
+    return ei, ej, dm
+
+
+def merge_dev(s: SplatTensors, partner, ws=None):
+    """merge with the new count left on the device: (SplatTensors of capacity
+    n, d_nout int64 [1] cuda).  Reads nothing back."""
+    torch = _torch()
+    lib = load()
+    out = SplatTensors.empty(s.n, with_origin=s.origin is not None)
+    dn = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb = lib.nanogs_merge_workspace_bytes(s.n)
+    ws = ws if ws is not None else _workspace(nb)
+    si, so = s.struct(), out.struct()
+    _check(lib.nanogs_merge(ctypes.byref(si), s.n, _ptr(partner), ctypes.byref(so), _ptr(dn),
+                            _ptr(ws), nb, _stream()))
+    return out, dn
 
 
 def merge(s: SplatTensors, partner):
