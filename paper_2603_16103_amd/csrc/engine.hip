@@ -315,9 +315,11 @@ int Engine::step(StageTimer* T) {
     S.row0 = (int)j.row0;
     S.nrows = (int)j.N;
     S.crn = (int)i;
+    // a segment without a table keeps the next table's offset (the cell
+    // table build orders rows by it)
+    S.toff = (int)entries;
     if (j.state == JOB_RUNNING) {
       S.LT = table_level(j.N);
-      S.toff = (int)entries;
       entries += table_entries(S.LT);
       S.keff = (int)std::min<long long>(std::max(1, j.spec.k), j.N - 1);
       S.kclass = kclass_of(S.keff);

@@ -232,14 +232,12 @@ long long table_entries(int LT);
 // inverse, sparse-query list.
 struct StageTimer;
 struct KnnMem {
-  int* hist;
   int* table;
   int* inv;      // logical index -> working row
   int2* retry;   // (row, 0) of the queries the wave search finishes
   int2* ginfo;   // per query: (rows buffered by the block gather or -1, level)
   int* counters;  // [1]: retry count
   int* gbuf;     // [slot][n] rows buffered by the block gather
-  void* scan_temp;
 };
 KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* bytes);
 // Cell tables of every segment with LT > 0 (rows sorted by Morton key within

@@ -105,39 +105,101 @@ __global__ void k_iota(int* v, int n) {
 // ---- cell table ------------------------------------------------------------
 // The working array is sorted by level-8 cell of the 30-bit Morton key of the
 // centres, so every octree cell of level L <= 8 (a Morton prefix of 3L bits)
-// is a contiguous range of rows.  The table holds, for every cell c of level LT, the first row
-// whose level-LT cell is >= c (cstart[ncells] = n); a cell of a coarser level
-// L is the range [cstart[c << 3(LT-L)], cstart[(c+1) << 3(LT-L)]).
+// is a contiguous range of rows.  A segment's table holds, for every cell c
+// of level LT, the first row whose level-LT cell is >= c (cstart[8^LT] = the
+// segment's end); a cell of a coarser level L is the range
+// [cstart[c << 3(LT-L)], cstart[(c+1) << 3(LT-L)]).
+//
+// Built without a histogram: every row gets the global code toff + cell (rows
+// of segments without a table take their successor's toff - 1), which does
+// not decrease along the rows because the segments' tables follow their rows'
+// order; then entry e of the concatenated tables is the first row whose code
+// is >= e.
 
-// hist[toff + c] = rows of segment sid in its level-LT cell c, from the run
-// boundaries of the sorted keys (each run adds its end and subtracts its
-// start); flags a row whose cell is smaller than its predecessor's.
-// Segments without a table (LT = 0) are skipped.
-__global__ void k_cell_runs(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
-                            const SegInfo* __restrict__ seg, int* __restrict__ hist,
-                            int* __restrict__ unsorted) {
+// code[i] as above, inv[logical] = i, and *unsorted |= 1 if a row's cell is
+// smaller than its predecessor's in the same segment.
+__global__ void k_cell_codes(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
+                             const SegInfo* __restrict__ seg, int* __restrict__ code,
+                             int* __restrict__ inv, int* __restrict__ unsorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const SegInfo& S = seg[sg ? sg[i] : 0];
-  if (S.LT <= 0) return;
-  const int shift = 3 * (10 - S.LT);
   const float4 c = cen[i];
-  const unsigned key = morton_key(c.x, c.y, c.z, S.box);
-  const unsigned cell = key >> shift;
-  const bool first = i == S.row0;
-  const bool last = i + 1 == S.row0 + S.nrows;
-  unsigned prev_key = 0u, next_cell = ~0u;
-  if (!first) {
+  inv[__float_as_int(c.w)] = i;
+  const SegInfo& S = seg[sg ? sg[i] : 0];
+  if (S.LT <= 0) {
+    code[i] = S.toff - 1;
+    return;
+  }
+  const int shift = 3 * (10 - S.LT);
+  const unsigned cell = morton_key(c.x, c.y, c.z, S.box) >> shift;
+  code[i] = S.toff + (int)cell;
+  if (i != S.row0) {
     const float4 a = cen[i - 1];
-    prev_key = morton_key(a.x, a.y, a.z, S.box);
+    if ((morton_key(a.x, a.y, a.z, S.box) >> shift) > cell) atomicOr(unsorted, 1);
   }
-  if (!last) {
-    const float4 b = cen[i + 1];
-    next_cell = morton_key(b.x, b.y, b.z, S.box) >> shift;
+}
+
+// First index in [lo, hi) whose code is >= key, hi if none (code sorted; a
+// wave-uniform call): each step samples 64 evenly spaced positions and keeps
+// the gap where the predicate turns, so the range shrinks 64-fold.
+NG_DEV int lower_bound_wave(const int* __restrict__ code, int lo, int hi, int key) {
+  const int lane = lane_id();
+  while (lo < hi) {
+    const int step = (hi - lo + 63) >> 6;
+    const long long p = lo + (long long)lane * step;
+    const unsigned long long below = __ballot(p < hi && code[p] < key);
+    if (!below) return lo;
+    const int t = 63 - __clzll((long long)below);  // last sample below the key
+    const long long pt = lo + (long long)t * step;
+    lo = (int)pt + 1;
+    if (t < 63 && pt + step < hi) hi = (int)(pt + step);
   }
-  if (!first && (prev_key >> shift) > cell) atomicOr(unsorted, 1);  // rows ordered by cell
-  if (first || (prev_key >> shift) != cell) atomicAdd(&hist[S.toff + cell], -(i - S.row0));
-  if (last || next_cell != cell) atomicAdd(&hist[S.toff + cell], i - S.row0 + 1);
+  return lo;
+}
+
+// table[e] = first row i with code[i] >= e, for e in [0, m].  Each wave fills
+// kTableWindows windows of 64 consecutive entries, one entry per lane (the
+// stores coalesce).  A window loads the 64 rows from the first one that can
+// answer it and every lane finds its answer among them by a binary search
+// over the lanes; lanes whose entry lies beyond all 64 rows jump, by a 64-way
+// search, to the lower bound of the smallest such entry, which answers it on
+// the next load: at most 65 loads per window, whatever the rows' density.
+constexpr int kTableWindows = 32;
+
+__global__ void __launch_bounds__(256)
+k_table_fill(const int* __restrict__ code, int n, int m, int* __restrict__ table) {
+  const int lane = lane_id();
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long e0 = wave * (64 * kTableWindows);
+  if (e0 > m) return;
+  int r = lower_bound_wave(code, 0, n, (int)e0);
+  for (int w = 0; w < kTableWindows; ++w) {
+    const long long ew = e0 + 64ll * w;
+    if (ew > m) break;
+    const long long e = ew + lane;
+    bool done = e > m;
+    int ans = n;
+    int rw = r;
+    for (;;) {
+      const int row = rw + lane;
+      const int v = row < n ? code[row] : INT_MAX;
+      int pos = 0;
+#pragma unroll
+      for (int s = 32; s > 0; s >>= 1)
+        if ((long long)__shfl(v, pos + s - 1, 64) < e) pos += s;
+      if ((long long)__shfl(v, pos, 64) < e) ++pos;
+      if (!done && pos < 64) {
+        ans = rw + pos;
+        done = true;
+      }
+      const unsigned long long open = __ballot(!done);
+      if (!open) break;
+      const int first = __ffsll((long long)open) - 1;
+      rw = lower_bound_wave(code, rw + 64 < n ? rw + 64 : n, n, (int)(ew + first));
+    }
+    if (e <= m) table[e] = ans;
+    r = __shfl(ans, 63, 64);
+  }
 }
 
 // Rows of segments without a search (inert): empty lists.
@@ -364,7 +426,6 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   const int keff = S.keff;
   const int LT = S.LT;
   const int* cstart = table + S.toff;
-  const int rb = S.row0 - cstart[0];  // table values -> rows
   const QueryGeo q = query_geo(cen[p], S);
   const float qxf = q.qxf, qyf = q.qyf, qzf = q.qzf;
 
@@ -431,8 +492,8 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   auto range = [&](int c, int& a, int& b) {
     const unsigned f = ((dil_pick(dx, blk(kBlkX, c)) << 2) | (dil_pick(dy, blk(kBlkY, c)) << 1) |
                         dil_pick(dz, blk(kBlkZ, c))) << sub;
-    a = cstart[f] + rb;
-    b = cstart[f + (1u << sub)] + rb;
+    a = cstart[f];
+    b = cstart[f + (1u << sub)];
   };
   // upper edge of the bin that holds the keff-th distance (+inf if unknown)
   auto kth_edge = [&]() {
@@ -563,8 +624,8 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
         const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
         const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                             spread10((unsigned)z)) << sub;
-        a = cstart[f] + rb;
-        b = cstart[f + (1u << sub)] + rb;
+        a = cstart[f];
+        b = cstart[f + (1u << sub)];
       };
       // as in for_cells: the next cell's range is loaded before a cell is scanned
       int i = emask ? __ffsll((long long)emask) - 1 : -1;
@@ -765,7 +826,6 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
     const int keff = S.keff;
     const int LT = S.LT;
     const int* cstart = table + S.toff;
-    const int rb = S.row0 - cstart[0];
     const Grid g = grid_from_box(S.box);
     float lof[3], hif[3];
 #pragma unroll
@@ -909,8 +969,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
           if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
             const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                                 spread10((unsigned)z)) << sub;
-            a = cstart[f] + rb;
-            b = cstart[f + (1u << sub)] + rb;
+            a = cstart[f];
+            b = cstart[f + (1u << sub)];
           }
         }
         int rows = b - a;
@@ -982,8 +1042,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
           if (!((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12))) {
             const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                                 spread10((unsigned)z)) << sub;
-            a = cstart[f] + rb;
-            b = cstart[f + (1u << sub)] + rb;
+            a = cstart[f];
+            b = cstart[f + (1u << sub)];
           }
         }
         const bool heavy = L < LT && b - a > kRefine;
@@ -1005,8 +1065,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
               if (!((gx * gx + gy * gy) + gz * gz > kd * (1.0 + 1e-12))) {
                 const unsigned f = ((spread10((unsigned)xc) << 2) | (spread10((unsigned)yc) << 1) |
                                     spread10((unsigned)zc)) << subc;
-                ca = cstart[f] + rb;
-                cb = cstart[f + (1u << subc)] + rb;
+                ca = cstart[f];
+                cb = cstart[f + (1u << subc)];
               }
             }
             add_cells(ca, cb);
@@ -1105,11 +1165,6 @@ __global__ void k_plain_seg(SegInfo* __restrict__ s, const unsigned* __restrict_
   }
 }
 
-__global__ void k_invert(const float4* __restrict__ cen, int n, int* __restrict__ inv) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) inv[__float_as_int(cen[p].w)] = p;
-}
-
 __global__ void k_gather_cen(const float* __restrict__ xyz3, const int* __restrict__ perm, int n,
                              float4* __restrict__ cen) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1150,7 +1205,6 @@ long long table_entries(int LT) { return LT > 0 ? (1ll << (3 * LT)) + 1 : 0; }
 KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* bytes) {
   Carver c(base);
   KnnMem m;
-  m.hist = c.take<int>(entries + 1);
   m.table = c.take<int>(entries + 1);
   m.inv = c.take<int>(n);
   m.retry = c.take<int2>(n);
@@ -1158,20 +1212,22 @@ KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* b
   m.counters = c.take<int>(64);
   // last: its size depends on kmax (builds carve with kmax = 0)
   m.gbuf = c.take<int>(n * (2 * (long long)kclass_of(kmax) + 1));
-  const size_t scan = std::max(scan_temp_bytes(entries + 1), scan_temp_bytes(n));
-  m.scan_temp = base ? (char*)base + c.bytes() : nullptr;
-  if (bytes) *bytes = c.bytes() + scan;
+  if (bytes) *bytes = c.bytes();
   return m;
 }
 
 void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, long long entries,
                void* mem, int* d_unsorted, hipStream_t st) {
   KnnMem m = carve_knn(mem, n, entries, 0, nullptr);
-  fill_i32(m.hist, 0, entries + 1, st);
-  k_cell_runs<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, m.hist, d_unsorted);
+  if (n <= 0) return;
+  if (entries >= INT_MAX) throw std::runtime_error("internal: cell tables exceed 2^31 entries");
+  // the codes live in the gather buffer (n ints at least), which the
+  // queries overwrite later
+  int* code = m.gbuf;
+  k_cell_codes<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, code, m.inv, d_unsorted);
   NG_LAUNCH_CHECK();
-  scan_exclusive_i32(m.hist, m.table, entries + 1, nullptr, m.scan_temp, st);
-  k_invert<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, m.inv);
+  const long long waves = entries / (64 * kTableWindows) + 1;
+  k_table_fill<<<blocks_for(waves * 64, 256), 256, 0, st>>>(code, n, (int)entries, m.table);
   NG_LAUNCH_CHECK();
 }
 
