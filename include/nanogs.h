@@ -13,7 +13,8 @@
  *    comment says "host".  The library never frees caller memory and never
  *    keeps a pointer after a call returns.
  *  - Arrays are row-major per splat: pos[n][3], sh[n][48], ...; float arrays
- *    must be 4-byte aligned, and ws / sh / rot / quat must be 16-byte aligned.
+ *    must be 4-byte aligned, sh / rot / quat 16-byte aligned, and every
+ *    workspace (ws) 256-byte aligned.
  *  - Every call returns a nanogs_status; on failure nanogs_last_error()
  *    (thread-local) describes it.  Argument checks happen before any launch,
  *    so a failed check leaves every output untouched.

@@ -46,6 +46,15 @@ struct Tri {
   T a00, a10, a11, a20, a21, a22;
 };
 
+// Reciprocal, square root and reciprocal square root: in float the
+// hardware's single-instruction forms (about 1 ulp; every float result is
+// checked against the fallback trigger and compared with a tolerance), in
+// double the correctly rounded ones.
+NG_DEV float rcp_of(float x) { return __builtin_amdgcn_rcpf(x); }
+NG_DEV double rcp_of(double x) { return 1.0 / x; }
+NG_DEV float sqrt_of(float x) { return __builtin_amdgcn_sqrtf(x); }
+NG_DEV double sqrt_of(double x) { return sqrt(x); }
+
 template <typename T>
 NG_DEV V3<T> tri_mul(const Tri<T>& L, const V3<T>& z) {
   return {L.a00 * z.x, L.a10 * z.x + L.a11 * z.y, L.a20 * z.x + L.a21 * z.y + L.a22 * z.z};
@@ -54,9 +63,9 @@ NG_DEV V3<T> tri_mul(const Tri<T>& L, const V3<T>& z) {
 template <typename T>
 NG_DEV V3<T> tri_solve(const Tri<T>& L, const V3<T>& y) {
   V3<T> v;
-  v.x = y.x / L.a00;
-  v.y = (y.y - L.a10 * v.x) / L.a11;
-  v.z = (y.z - L.a20 * v.x - L.a21 * v.y) / L.a22;
+  v.x = y.x * rcp_of(L.a00);
+  v.y = (y.y - L.a10 * v.x) * rcp_of(L.a11);
+  v.z = (y.z - L.a20 * v.x - L.a21 * v.y) * rcp_of(L.a22);
   return v;
 }
 
@@ -64,7 +73,7 @@ template <typename T>
 NG_DEV T tri_ratio(const Tri<T>& L) {
   T mn = fmin(fmin(L.a00, L.a11), L.a22);
   T mx = fmax(fmax(L.a00, L.a11), L.a22);
-  return mn / mx;
+  return mn * rcp_of(mx);
 }
 
 // Rotates columns (ci, cj) of the 3 x NC row-major matrix g so that
@@ -72,9 +81,10 @@ NG_DEV T tri_ratio(const Tri<T>& L) {
 template <typename T, int NC>
 NG_DEV void givens(T (&g)[3][NC], int row, int ci, int cj) {
   const T x = g[row][ci], y = g[row][cj];
-  const T r = sqrt(x * x + y * y);
+  const T r = sqrt_of(x * x + y * y);
   if (!(r > T(0))) return;
-  const T c = x / r, s = y / r;
+  const T ir = rcp_of(r);
+  const T c = x * ir, s = y * ir;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     if (i >= row) {
@@ -128,9 +138,9 @@ NG_DEV Tri<T> chol_from_scale_rot(T s0, T s1, T s2, T w, T x, T y, T z) {
 template <typename T>
 NG_DEV V3<T> tri_solve_t(const Tri<T>& L, const V3<T>& y) {
   V3<T> h;
-  h.z = y.z / L.a22;
-  h.y = (y.y - L.a21 * h.z) / L.a11;
-  h.x = (y.x - L.a10 * h.y - L.a20 * h.z) / L.a00;
+  h.z = y.z * rcp_of(L.a22);
+  h.y = (y.y - L.a21 * h.z) * rcp_of(L.a11);
+  h.x = (y.x - L.a10 * h.y - L.a20 * h.z) * rcp_of(L.a00);
   return h;
 }
 
@@ -154,12 +164,13 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
                    T ldLa, T ldLb, T pa, T pb, double pdec, const float* __restrict__ cv, int S,
                    int mode, T& ratio) {
   const V3<T> d = {mua.x - mub.x, mua.y - mub.y, mua.z - mub.z};
-  const Tri<T> LA = chol_of_mix(La, Lb, sqrt(pa), sqrt(pb));
+  const Tri<T> LA = chol_of_mix(La, Lb, sqrt_of(pa), sqrt_of(pb));
   ratio = fmin(fmin(tri_ratio(La), tri_ratio(Lb)), tri_ratio(LA));
   const V3<T> e = tri_solve(LA, d);
   const T ee = dot(e, e);
   const T c = pa * pb;
   const T den = T(1) + c * ee;
+  const T inv_den = rcp_of(den);
   const T half_logdet_m = log(LA.a00 * LA.a11 * LA.a22) + T(0.5) * log1p(c * ee);
   if (mode == NANOGS_COST_BOUND) {
     // KL(N_c || q_m) = 1/2 [tr(Sm^-1 Sc) + w_o^2 |e|^2 / den - 3] +
@@ -172,16 +183,16 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
       const V3<T> c2 = tri_solve(LA, V3<T>{T(0), T(0), Lc.a22});
       const T tr_a = dot(c0, c0) + dot(c1, c1) + dot(c2, c2);
       const V3<T> r = tri_mul_t(Lc, h);
-      const T tr = tr_a - c * dot(r, r) / den;
-      return T(0.5) * (tr + w_other * w_other * ee / den - T(3)) + half_logdet_m - ldc;
+      const T tr = tr_a - c * dot(r, r) * inv_den;
+      return T(0.5) * (tr + w_other * w_other * ee * inv_den - T(3)) + half_logdet_m - ldc;
     };
     const T ka = pa > T(0) ? pa * kl(La, ldLa, pb) : T(0);
     const T kb = pb > T(0) ? pb * kl(Lb, ldLb, pa) : T(0);
     return ka + kb;
   }
   const T lpa = log(pa), lpb = log(pb);
-  const T ne = sqrt(ee);
-  const T inv_ne = ne > T(0) ? T(1) / ne : T(0);
+  const T ne = sqrt_of(ee);
+  const T inv_ne = ne > T(0) ? rcp_of(ne) : T(0);
   const V3<T> eh = {e.x * inv_ne, e.y * inv_ne, e.z * inv_ne};
   // g = log p~(x) - log q_m(x) at x = mu_c + L_c z (c = a or b)
   auto g_at = [&](bool ca, const V3<T>& zz) {
@@ -201,7 +212,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
     const T we = dot(w, eh);
     const T perp = fmax(ww - we * we, T(0));
     const T par = beta * ne + we;
-    const T maha = perp + par * par / den;
+    const T maha = perp + par * par * inv_den;
     const T lnm = T(-0.5) * maha - half_logdet_m;
     const T la = lpa + (ca ? lnc : lno);
     const T lb = lpb + (ca ? lno : lnc);
@@ -221,25 +232,46 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
       acc += g_at((double)u < pdec, zz);
     }
   }
-  return acc / (T)S;
+  return S == 1 ? acc : acc * rcp_of((T)S);
 }
 
-NG_DEV float dapp_f32(const float* __restrict__ sh, long long a, long long b, int app_dims) {
-  const float* fa = sh + a * NG_SH;
-  const float* fb = sh + b * NG_SH;
-  float acc = 0.f;
-  const int n4 = app_dims >> 2;
-  for (int c = 0; c < n4; ++c) {
-    const float4 x = ((const float4*)fa)[c];
-    const float4 y = ((const float4*)fb)[c];
-    const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
-    acc += dx * dx + dy * dy + dz * dz + dw * dw;
+// D_app = ||f_s - f_t||^2 for the wave's 64 edges (lane j: edge j), 16
+// lanes per edge and 4 consecutive edges per step: each lane takes 3 of the
+// 48 coefficients of both rows, so a load instruction reads 4 whole rows per
+// side instead of 64 scattered 16-byte pieces of 64 rows.  Every lane of the
+// wave must call it.  The sum runs as a fixed tree over the 16 lanes.
+NG_DEV float dapp_wave(const float* __restrict__ sh, int s, int t, bool live, int app_dims) {
+  const int lane = lane_id();
+  const int g = lane >> 4, c0 = 3 * (lane & 15);
+  float mine = 0.f;
+#pragma unroll 4
+  for (int r = 0; r < 16; ++r) {
+    const int j = 4 * r + g;
+    const int sj = __shfl(s, j, 64), tj = __shfl(t, j, 64);
+    const bool lj = __shfl((int)live, j, 64) != 0;
+    float acc = 0.f;
+    if (lj) {
+      const float* fa = sh + (long long)sj * NG_SH + c0;
+      const float* fb = sh + (long long)tj * NG_SH + c0;
+      if (app_dims == NG_SH) {
+        const float dx = fa[0] - fb[0], dy = fa[1] - fb[1], dz = fa[2] - fb[2];
+        acc = dx * dx + dy * dy + dz * dz;
+      } else {
+        for (int c = 0; c < 3; ++c)
+          if (c0 + c < app_dims) {
+            const float d = fa[c] - fb[c];
+            acc += d * d;
+          }
+      }
+    }
+    acc += __shfl_xor(acc, 8, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 1, 64);
+    const float v = __shfl(acc, 16 * (lane & 3), 64);
+    if ((lane >> 2) == r) mine = v;
   }
-  for (int c = n4 * 4; c < app_dims; ++c) {
-    const float dc = fa[c] - fb[c];
-    acc += dc * dc;
-  }
-  return acc;
+  return mine;
 }
 
 NG_DEV double dapp_f64(const float* __restrict__ sh, long long a, long long b, int app_dims) {
@@ -326,33 +358,51 @@ k_edge_cost(const float4* __restrict__ cen, const float4* __restrict__ pre,
   if (d_mcount) m = min(m, *d_mcount);
   bool live = e < m;
   bool fb = false;
+  int s = 0, t = 0;
   if (live) {
-    const int a = ea[e], b = eb[e];
-    if (a < 0 || a >= n || b < 0 || b >= n) {
+    s = ea[e];
+    t = eb[e];
+    if (s < 0 || s >= n || t < 0 || t >= n) {
       cost[e] = __int_as_float(0x7fc00000);
       if (dgeo_out) dgeo_out[e] = __int_as_float(0x7fc00000);
       live = false;
     }
   }
+  // every per-endpoint load issues before the first use: both ends' factors
+  // come in before the orientation (which needs the centres) picks them
+  float4 cs{}, ct{}, ps0{}, ps1{}, pt0{}, pt1{};
+  double ws = 0.0, wt = 0.0;
+  int crow = 0;
   if (live) {
-    const int s = ea[e], t = eb[e];
-    const float4 cs = cen[s], ct = cen[t];
+    cs = cen[s];
+    ct = cen[t];
+    ps0 = pre[2 * (long long)s];
+    ps1 = pre[2 * (long long)s + 1];
+    pt0 = pre[2 * (long long)t];
+    pt1 = pre[2 * (long long)t + 1];
+    ws = wd[s];
+    wt = wd[t];
+    crow = sg ? seg[sg[s]].crn : 0;
+  }
+  // whole waves past the end skip the cooperative part
+  const bool wave_live = __ballot(live) != 0ull;
+  const float dapp = wave_live ? dapp_wave(sh, s, t, live, app_dims) : 0.f;
+  if (live) {
     const int ls = __float_as_int(cs.w), lt = __float_as_int(ct.w);
     const bool sw = orient && lt < ls;  // first component = smaller logical index
-    const int a = sw ? t : s, b = sw ? s : t;
     const float4 ca = sw ? ct : cs, cb = sw ? cs : ct;
-    const float4 pa0 = pre[2 * (long long)a], pa1 = pre[2 * (long long)a + 1];
-    const float4 pb0 = pre[2 * (long long)b], pb1 = pre[2 * (long long)b + 1];
+    const float4 pa0 = sw ? pt0 : ps0, pa1 = sw ? pt1 : ps1;
+    const float4 pb0 = sw ? ps0 : pt0, pb1 = sw ? ps1 : pt1;
     const Tri<float> La = {pa0.x, pa0.y, pa0.z, pa0.w, pa1.x, pa1.y};
     const Tri<float> Lb = {pb0.x, pb0.y, pb0.z, pb0.w, pb1.x, pb1.y};
     double pad, pbd;
-    mix_weights(wd[a], wd[b], pad, pbd);
+    mix_weights(sw ? wt : ws, sw ? ws : wt, pad, pbd);
     const float pa = (float)pad, pb = (float)pbd;
     float ratio;
-    const float* cv = crn + NG_CRN_ROW * (sg ? seg[sg[s]].crn : 0);
+    const float* cv = crn + NG_CRN_ROW * crow;
     const float dg = dgeo_pair<float>(v3(ca.x, ca.y, ca.z), v3(cb.x, cb.y, cb.z), La, Lb, pa1.z,
                                       pb1.z, pa, pb, pad, cv, S, mode, ratio);
-    const float c = dg + dapp_f32(sh, a, b, app_dims);
+    const float c = dg + dapp;
     fb = !(ratio >= fb_ratio) || !isfinite(c);
     cost[e] = c;
     if (dgeo_out) dgeo_out[e] = dg;

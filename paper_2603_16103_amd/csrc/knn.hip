@@ -139,66 +139,147 @@ __global__ void k_cell_codes(const float4* __restrict__ cen, int n, const int* _
   }
 }
 
-// First index in [lo, hi) whose code is >= key, hi if none (code sorted; a
-// wave-uniform call): each step samples 64 evenly spaced positions and keeps
-// the gap where the predicate turns, so the range shrinks 64-fold.
-NG_DEV int lower_bound_wave(const int* __restrict__ code, int lo, int hi, int key) {
+// First indices r0, r1 whose code is >= k0 and >= k1 (code sorted, n if
+// none; a wave-uniform call).  A 64-way search: each step samples 64 evenly
+// spaced positions of a range and keeps the gap where the predicate turns, so
+// the range shrinks 64-fold; the two searches share the steps so that their
+// loads overlap.
+NG_DEV void lower_bound_wave2(const int* __restrict__ code, int n, int k0, int k1, int& r0,
+                              int& r1) {
   const int lane = lane_id();
-  while (lo < hi) {
-    const int step = (hi - lo + 63) >> 6;
-    const long long p = lo + (long long)lane * step;
-    const unsigned long long below = __ballot(p < hi && code[p] < key);
-    if (!below) return lo;
-    const int t = 63 - __clzll((long long)below);  // last sample below the key
-    const long long pt = lo + (long long)t * step;
-    lo = (int)pt + 1;
-    if (t < 63 && pt + step < hi) hi = (int)(pt + step);
+  int lo[2] = {0, 0}, hi[2] = {n, n};
+  const int key[2] = {k0, k1};
+  while (lo[0] < hi[0] || lo[1] < hi[1]) {
+    unsigned long long below[2];
+    int step[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      step[s] = (hi[s] - lo[s] + 63) >> 6;
+      const long long p = lo[s] + (long long)lane * step[s];
+      below[s] = __ballot(lo[s] < hi[s] && p < hi[s] && code[p] < key[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (lo[s] >= hi[s]) continue;
+      if (!below[s]) {
+        hi[s] = lo[s];
+        continue;
+      }
+      const int t = 63 - __clzll((long long)below[s]);  // last sample below the key
+      const long long pt = lo[s] + (long long)t * step[s];
+      lo[s] = (int)pt + 1;
+      if (t < 63 && pt + step[s] < hi[s]) hi[s] = (int)(pt + step[s]);
+    }
   }
-  return lo;
+  r0 = lo[0];
+  r1 = lo[1];
 }
 
-// table[e] = first row i with code[i] >= e, for e in [0, m].  Each wave fills
-// kTableWindows windows of 64 consecutive entries, one entry per lane (the
-// stores coalesce).  A window loads the 64 rows from the first one that can
-// answer it and every lane finds its answer among them by a binary search
-// over the lanes; lanes whose entry lies beyond all 64 rows jump, by a 64-way
-// search, to the lower bound of the smallest such entry, which answers it on
-// the next load: at most 65 loads per window, whatever the rows' density.
-constexpr int kTableWindows = 32;
+// table[e] = first row i with code[i] >= e, for e in [0, m].  One wave per
+// chunk of kFillChunk entries [E, E + kFillChunk): the rows [r0, r1) whose
+// codes fall in the chunk come from one two-key search.  With at most
+// kFillRows of them, each row that starts its code marks that code's slot in
+// LDS with its index, and entry e is the smallest mark at or after e (r1 when
+// none): a suffix minimum, 32 entries per lane and across the lanes.  Denser
+// chunks search every entry among [r0, r1) (32 interleaved binary searches
+// per lane).  The table goes out in coalesced 16-byte stores.
+constexpr int kFillChunk = 2048;
+constexpr int kFillPer = kFillChunk / 64;
+constexpr int kFillRows = 1024;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_table_fill(const int* __restrict__ code, int n, int m, int* __restrict__ table) {
-  const int lane = lane_id();
-  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const long long e0 = wave * (64 * kTableWindows);
-  if (e0 > m) return;
-  int r = lower_bound_wave(code, 0, n, (int)e0);
-  for (int w = 0; w < kTableWindows; ++w) {
-    const long long ew = e0 + 64ll * w;
-    if (ew > m) break;
-    const long long e = ew + lane;
-    bool done = e > m;
-    int ans = n;
-    int rw = r;
-    for (;;) {
-      const int row = rw + lane;
-      const int v = row < n ? code[row] : INT_MAX;
-      int pos = 0;
+  __shared__ __align__(16) int mark[kFillChunk];
+  const int lane = threadIdx.x;
+  const int E = blockIdx.x * kFillChunk;  // <= m (grid)
+  int r0, r1;
+  lower_bound_wave2(code, n, E, E + kFillChunk, r0, r1);
+  const int cnt = r1 - r0;
+  if (cnt > kFillRows) {
+    int b[kFillPer];
 #pragma unroll
-      for (int s = 32; s > 0; s >>= 1)
-        if ((long long)__shfl(v, pos + s - 1, 64) < e) pos += s;
-      if ((long long)__shfl(v, pos, 64) < e) ++pos;
-      if (!done && pos < 64) {
-        ans = rw + pos;
-        done = true;
-      }
-      const unsigned long long open = __ballot(!done);
-      if (!open) break;
-      const int first = __ffsll((long long)open) - 1;
-      rw = lower_bound_wave(code, rw + 64 < n ? rw + 64 : n, n, (int)(ew + first));
+    for (int q = 0; q < kFillPer; ++q) b[q] = r0;
+    for (int len = cnt; len > 1;) {
+      const int half = len >> 1;
+#pragma unroll
+      for (int q = 0; q < kFillPer; ++q)
+        if (code[b[q] + half] < E + 64 * q + lane) b[q] += half;
+      len -= half;
     }
-    if (e <= m) table[e] = ans;
-    r = __shfl(ans, 63, 64);
+#pragma unroll
+    for (int q = 0; q < kFillPer; ++q) {
+      const int e = E + 64 * q + lane;
+      if (e <= m) table[e] = b[q] + (code[b[q]] < e ? 1 : 0);
+    }
+    return;
+  }
+  int4* m4 = reinterpret_cast<int4*>(mark);
+  const int4 none = make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX);
+#pragma unroll
+  for (int k = 0; k < kFillChunk / 256; ++k) m4[k * 64 + lane] = none;
+  __syncthreads();
+  // four loads in flight per lane; a row's predecessor comes from the lane
+  // below (lane 0: from lane 63 of the previous load, or none at r0)
+  int above = INT_MIN;
+  for (int base = r0; base < r1; base += 256) {
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = base + 64 * k + lane;
+      c[k] = j < r1 ? code[j] : INT_MAX;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = base + 64 * k + lane;
+      int prev = __shfl_up(c[k], 1, 64);
+      if (lane == 0) prev = above;
+      above = __shfl(c[k], 63, 64);
+      // (the range test only matters for unsorted rows, which the order flag reports)
+      if (j < r1 && c[k] != prev && c[k] >= E && c[k] - E < kFillChunk) mark[c[k] - E] = j;
+    }
+  }
+  __syncthreads();
+  int v[kFillPer];
+#pragma unroll
+  for (int k = 0; k < kFillPer / 4; ++k) {
+    const int4 t = m4[lane * (kFillPer / 4) + k];
+    v[4 * k] = t.x;
+    v[4 * k + 1] = t.y;
+    v[4 * k + 2] = t.z;
+    v[4 * k + 3] = t.w;
+  }
+  int x = v[0];
+#pragma unroll
+  for (int q = 1; q < kFillPer; ++q) x = min(x, v[q]);
+  // suffix minimum over the lanes, then the carry from the lanes above
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_down(x, d, 64);
+    if (lane + d < 64) x = min(x, y);
+  }
+  int carry = __shfl_down(x, 1, 64);
+  carry = lane < 63 ? min(carry, r1) : r1;
+#pragma unroll
+  for (int q = kFillPer - 1; q >= 0; --q) {
+    carry = min(carry, v[q]);
+    v[q] = carry;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kFillPer / 4; ++k)
+    m4[lane * (kFillPer / 4) + k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kFillChunk / 256; ++k) {
+    const int e = E + k * 256 + 4 * lane;
+    const int4 t = m4[k * 64 + lane];
+    if (e + 3 <= m) {
+      *reinterpret_cast<int4*>(table + e) = t;
+    } else {
+      if (e <= m) table[e] = t.x;
+      if (e + 1 <= m) table[e + 1] = t.y;
+      if (e + 2 <= m) table[e + 2] = t.z;
+    }
   }
 }
 
@@ -762,7 +843,7 @@ k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restr
 // buffer overflow, or a k-th ball spanning too many cells), one wave each.
 // The lanes share the work: cells are looked up one per lane, their rows are
 // dealt out 64 at a time, and the k best live one entry per lane (lanes
-// 0..K-1, sorted), so an insertion is a ballot and a shift.  First the block
+// 0..K-1, sorted).  First the block
 // search at the finest level whose 3x3x3 block holds bmin rows; if its k-th
 // key reaches beyond the block, a ball search over the cells of the range
 // [q - r, q + r] (r: that k-th distance) at the finest level where it spans at
@@ -817,6 +898,7 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
   __shared__ int s_start[MAXC];
   __shared__ int s_pref[MAXC + 1];
   __shared__ int s_hist[32];
+  __shared__ int s_cand[64];
   const int lane = threadIdx.x;
   const int count = *d_count;
   for (int qidx = blockIdx.x; qidx < count; qidx += gridDim.x) {
@@ -869,12 +951,14 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       ncell += added;
       __syncthreads();
     };
-    // f(j) for the lanes' rows j of the listed cells, 64 per step (j = -1:
-    // no row)
     // f(j, c) for the lanes' rows j (centre c) of the listed cells, 256 per
-    // step, four per lane with their loads issued together (j = -1: no row)
+    // step, four per lane with their loads issued together (j = -1: no row).
+    // A lane's rows advance 64 at a time, so its cell (the last one with
+    // s_pref <= t) is usually the one it had or the next; a binary search
+    // over the rest of the list covers longer jumps.
     auto for_rows = [&](auto&& f) {
       const int total = s_pref[ncell];
+      int cur = 0;
       for (int t0 = 0; t0 < total; t0 += 256) {
         int jj[4];
         float4 cc[4];
@@ -883,12 +967,15 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
           const int t = t0 + 64 * u + lane;
           jj[u] = -1;
           if (t < total) {
-            int lo = 0, hi = ncell - 1;  // last cell with s_pref <= t
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+            if (s_pref[cur + 1] <= t) {  // then cur + 1 < ncell (s_pref[ncell] = total)
+              int lo = cur + 1, hi = ncell - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+              }
+              cur = lo;
             }
-            jj[u] = s_start[lo] + (t - s_pref[lo]);
+            jj[u] = s_start[cur] + (t - s_pref[cur]);
           }
         }
 #pragma unroll
@@ -897,9 +984,15 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         for (int u = 0; u < 4; ++u) f(jj[u], cc[u]);
       }
     };
-    // exact k best among the listed cells' rows: a histogram of the float
-    // distances (32 quarter-octave bins from 2^base) gives tau, then the rows
-    // within tau (widened for rounding) are inserted one after another
+    // exact k best among the listed cells' rows.  A histogram of the float
+    // distances (32 quarter-octave bins from 2^base) gives a bound tau (the
+    // upper edge of the bin holding the keff-th distance); while the rows up
+    // to that bin outnumber the lanes, the bin is split 32 ways by the next 5
+    // bits of the float distance (another pass) and the bound moves to the
+    // upper edge of the sub-bin holding the keff-th.  Every row that can be
+    // among the k best has a float distance within the bound (widened for
+    // rounding).  Up to 64 such rows get one lane each, the exact key, and
+    // their rank by counting; more are inserted one after another.
     auto search = [&](int base) {
       best.init();
       if (lane < 32) s_hist[lane] = 0;
@@ -913,7 +1006,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         }
       });
       __syncthreads();
-      int cum = lane < 32 ? s_hist[lane] : 0;
+      int h = lane < 32 ? s_hist[lane] : 0;
+      int cum = h;
 #pragma unroll
       for (int d = 1; d < 32; d <<= 1) {
         const int y = __shfl_up(cum, d, 64);
@@ -924,28 +1018,98 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       float tau = INFINITY;
       if (bstar >= 0 && bstar < 31 && base + bstar + 1 < 1020)
         tau = __uint_as_float((unsigned)(base + bstar + 1) << 21);
-      const float adm = tau * kScreen;
-      for_rows([&](int j, const float4& c) {
-        bool pass = false;
-        double dme = 0.0;
-        int lme = 0;
-        if (j >= 0 && j != p) {
-          if (d2_screen(qxf, qyf, qzf, c) <= adm) {
-            pass = true;
-            dme = dist2(qx, qy, qz, c.x, c.y, c.z);
-            lme = __float_as_int(c.w);
+      // (bin 0 also holds every row below 2^base, so it is not split)
+      if (bstar > 0 && tau < INFINITY) {
+        int below = __shfl(cum - h, bstar, 64);  // rows in the bins before
+        int inbin = __shfl(h, bstar, 64);
+        unsigned key = (unsigned)(base + bstar);  // float bits >> sh of the bin
+        int sh = 21;
+        while (below + inbin > 64 && sh > 11) {
+          const int sh2 = sh - 5;
+          __syncthreads();
+          if (lane < 32) s_hist[lane] = 0;
+          __syncthreads();
+          for_rows([&](int j, const float4& cj) {
+            if (j >= 0 && j != p) {
+              const unsigned bits = __float_as_uint(d2_screen(qxf, qyf, qzf, cj));
+              if ((bits >> sh) == key) atomicAdd(&s_hist[(bits >> sh2) & 31], 1);
+            }
+          });
+          __syncthreads();
+          h = lane < 32 ? s_hist[lane] : 0;
+          cum = h;
+#pragma unroll
+          for (int d = 1; d < 32; d <<= 1) {
+            const int y = __shfl_up(cum, d, 64);
+            if (lane >= d) cum += y;
           }
+          // the sub-bins hold the bin's rows, so the keff-th is among them
+          const unsigned long long r2 = __ballot(lane < 32 && below + cum >= keff);
+          if (!r2) break;  // (not reached: keep the bound found so far)
+          const int sb = __ffsll((long long)r2) - 1;
+          below += __shfl(cum - h, sb, 64);
+          inbin = __shfl(h, sb, 64);
+          key = (key << 5) | (unsigned)sb;
+          sh = sh2;
+          tau = __uint_as_float((key + 1u) << sh);
         }
-        unsigned long long m = __ballot(pass);
-        while (m) {
-          const int src = __ffsll((long long)m) - 1;
-          m &= m - 1;
-          const int dlo = __shfl(__double2loint(dme), src, 64);
-          const int dhi = __shfl(__double2hiint(dme), src, 64);
-          const int ls = __shfl(lme, src, 64);
-          best.insert(__hiloint2double(dhi, dlo), ls);
-        }
+      }
+      const float adm = tau * kScreen;
+      int nc = 0;
+      for_rows([&](int j, const float4& c) {
+        const bool pass = j >= 0 && j != p && d2_screen(qxf, qyf, qzf, c) <= adm;
+        const unsigned long long m = __ballot(pass);
+        const int pos = nc + __popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+        if (pass && pos < 64) s_cand[pos] = j;
+        nc += __popcll(m);
       });
+      __syncthreads();
+      if (nc <= 64) {
+        const int jme = lane < nc ? s_cand[lane] : -1;
+        double dme = INFINITY;
+        int lme = INT_MAX;
+        if (jme >= 0) {
+          const float4 c = cen[jme];
+          dme = dist2(qx, qy, qz, c.x, c.y, c.z);
+          lme = __float_as_int(c.w);
+        }
+        int rank = 0;
+        for (int t = 0; t < nc; ++t) {
+          const double dt = __shfl(dme, t, 64);
+          const int lt = __shfl(lme, t, 64);
+          rank += (dt < dme || (dt == dme && lt < lme)) ? 1 : 0;
+        }
+        if (lane >= nc) rank = lane;  // the ranks are then a permutation
+        const int dlo = __builtin_amdgcn_ds_permute(rank << 2, __double2loint(dme));
+        const int dhi = __builtin_amdgcn_ds_permute(rank << 2, __double2hiint(dme));
+        const int lr = __builtin_amdgcn_ds_permute(rank << 2, lme);
+        if (lane < K) {
+          best.d = __hiloint2double(dhi, dlo);
+          best.l = lr;
+        }
+      } else {
+        for_rows([&](int j, const float4& c) {
+          bool pass = false;
+          double dme = 0.0;
+          int lme = 0;
+          if (j >= 0 && j != p) {
+            if (d2_screen(qxf, qyf, qzf, c) <= adm) {
+              pass = true;
+              dme = dist2(qx, qy, qz, c.x, c.y, c.z);
+              lme = __float_as_int(c.w);
+            }
+          }
+          unsigned long long m = __ballot(pass);
+          while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int dlo = __shfl(__double2loint(dme), src, 64);
+            const int dhi = __shfl(__double2hiint(dme), src, 64);
+            const int ls = __shfl(lme, src, 64);
+            best.insert(__hiloint2double(dhi, dlo), ls);
+          }
+        });
+      }
       __syncthreads();
     };
     auto bin_base = [](double len2) {
@@ -1220,14 +1384,15 @@ void knn_build(const float4* cen, int n, const int* sg, const SegInfo* dseg, lon
                void* mem, int* d_unsorted, hipStream_t st) {
   KnnMem m = carve_knn(mem, n, entries, 0, nullptr);
   if (n <= 0) return;
-  if (entries >= INT_MAX) throw std::runtime_error("internal: cell tables exceed 2^31 entries");
+  if (entries >= INT_MAX - 2 * kFillChunk)
+    throw std::runtime_error("internal: cell tables exceed 2^31 entries");
   // the codes live in the gather buffer (n ints at least), which the
   // queries overwrite later
   int* code = m.gbuf;
   k_cell_codes<<<blocks_for(n, 256), 256, 0, st>>>(cen, n, sg, dseg, code, m.inv, d_unsorted);
   NG_LAUNCH_CHECK();
-  const long long waves = entries / (64 * kTableWindows) + 1;
-  k_table_fill<<<blocks_for(waves * 64, 256), 256, 0, st>>>(code, n, (int)entries, m.table);
+  k_table_fill<<<(unsigned)(entries / kFillChunk + 1), 64, 0, st>>>(code, n, (int)entries,
+                                                                    m.table);
   NG_LAUNCH_CHECK();
 }
 
