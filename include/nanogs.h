@@ -390,8 +390,8 @@ nanogs_status nanogs_merge(const nanogs_splats* in, int64_t n,
 typedef struct {
   int32_t cost_block;     /* threads per workgroup, edge-cost kernel: 64, 128
                              or 256 (256) */
-  int32_t knn_block;      /* threads per workgroup, one-lane-per-query kNN
-                             block search: 64, 128 or 256 (128) */
+  int32_t knn_block;      /* threads per workgroup of the kNN block search
+                             (four lanes per query): 64, 128 or 256 (128) */
   int32_t knn_wave_grid;  /* workgroups striding over the kNN queries that the
                              wave search finishes (one wave each):
                              256..65536 (16384) */
@@ -404,7 +404,7 @@ typedef struct {
   int32_t knn_block_min;  /* rows the 3x3x3 block of cells around a query
                              must hold for the block search to use that
                              cell level: 17..1024 (32) */
-  int32_t knn_lane_rows;  /* largest block a lane searches alone; larger
+  int32_t knn_lane_rows;  /* largest block the block search takes; larger
                              ones go to the wave search: 64..4096 (256) */
 } nanogs_tuning;
 

@@ -6,12 +6,13 @@
 // range of rows; a table of cell starts at one level gives the range of any
 // cell at that level or coarser.
 //
-// Query, in three kernels.  The block gather (one lane per query) screens the
-// rows of the 3x3x3 block of cells around the query at a level chosen by the
-// block's row count, plus the cells of the k-th ball outside the block, and
-// buffers every row that may enter the list.  The exact pass gives the
+// Query, in three kernels.  The block gather (four lanes per query) screens
+// the rows of the 3x3x3 block of cells around the query at a level chosen by
+// the block's row count, plus the cells of the k-th ball outside the block,
+// and buffers every row that may enter the list.  The exact pass gives the
 // buffered rows the exact key and keeps the k best.  Queries the gather gives
-// up on (heavy blocks, wide balls, full buffers) are finished one wave each.
+// up on (heavy blocks, wide or full balls, full buffers) are finished one
+// wave each.
 // Candidates are screened in float against bounds widened for rounding (never
 // rejecting a point the exact key would keep); survivors get the exact key
 // (d2, logical index) with d2 = ((dx*dx + dy*dy) + dz*dz) in double without
@@ -390,27 +391,25 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
   return (unsigned)t;
 }
 
-// ---- block search, one lane per query ----------------------------------------
+// ---- block search, Q lanes per query -------------------------------------------
 // A query takes the finest level L whose 3x3x3 block of level-L cells around
 // its own cell holds at least `block_min` rows (or the segment's rows, if
 // fewer), and selects its k best within that block in three passes over the
 // block's rows, none of which inserts into a sorted list per candidate:
-//   A. a per-lane histogram of the float squared distances, 32 bins of a
-//      quarter octave each from (side/8)^2 to (2 side)^2 (side = cell side),
-//      giving tau = the upper edge of the bin holding the keff-th distance;
+//   A. a histogram of the float squared distances, 32 bins of a quarter
+//      octave each from (side/8)^2 to (2 side)^2 (side = cell side), giving
+//      tau = the upper edge of the bin holding the keff-th distance;
 //   B. the rows whose float distance is within tau (widened for rounding) go
-//      to a per-lane buffer (about keff of them);
+//      to a buffer (about keff of them);
 //   C. the buffered rows get the exact key (d2 in double, logical index) and
-//      a sorted insertion.
+//      their rank among the buffered keys.
 // Cells whose box is beyond the current tau are skipped in A and B (their
 // rows fall in bins above tau, so neither tau nor the buffer changes).  The
 // own cell and the six faces come first, so tau is usually known early.
-// Every row outside the block is at least rho away (rho = distance to the
-// block's faces, faces on the grid's outer boundary open).  If the exact k-th
-// key is closer than rho the list is the exact kNN; otherwise the query goes
-// to the retry list with its level (the wave search continues with ring 2
-// from this list); a block over the scan cap or a buffer overflow retries
-// from scratch.
+// Rows outside the block that may still enter the list lie in the cells of
+// the k-th ball's range [q - r, q + r] outside the block; those are screened
+// in pass B too.  A block over the scan cap, a range too wide or too full,
+// or a buffer overflow sends the query to the wave search.
 
 // the 3x3x3 block: own cell, 6 faces, 12 edges, 8 corners; the offsets are
 // packed two bits per cell and axis (offset + 1), so a lane decodes cell c
@@ -442,7 +441,9 @@ NG_DEV Dil3 dil3(unsigned v) {
 }
 NG_DEV unsigned dil_pick(const Dil3& d, int off) { return off < 0 ? d.m : (off > 0 ? d.p : d.c); }
 
-constexpr int kExtCells = 64;   // cells of the k-th ball's range a lane may screen itself
+constexpr int kKnnLanes = 4;     // lanes per query of the block search
+constexpr int kExtCells = 64;
+constexpr int kExtRows = 128;  // rows of those cells a query scans itself   // cells of the k-th ball's range a lane may screen itself
 // float screen: a point whose exact d2 is <= B has float d2 <= B * kScreen
 // (the float evaluation rounds at most five times, about 3e-7 relative)
 constexpr float kScreen = 1.000005f;
@@ -494,25 +495,55 @@ NG_DEV QueryGeo query_geo(const float4& cq, const SegInfo& S) {
   return q;
 }
 
-// Passes A and B of the block search for query p (see above).  Returns the
-// number of buffered rows (p itself included), written to gbuf[i * n + p],
-// or -1 when the block exceeds lane_rows or the buffer overflows (the wave
-// search starts from scratch); *level = the block's level.
-template <int K>
-NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegInfo& S,
-                        const int* __restrict__ table, int block_min, int lane_rows,
-                        unsigned* __restrict__ hist, int bs, int* __restrict__ gbuf, int* level,
-                        int* screens) {
+// Passes A and B for query p with Q lanes (Q = 2, 4 or 8, consecutive lanes
+// of one wave).  The lanes split the 27 level lookups, then the cells: lane
+// r scans the block's non-empty cells r, r + Q, ... (in block order) and the
+// same share of the k-th ball's range, so a query's chain of dependent loads
+// (a cell's range, then its rows) is about Q times shorter than with one
+// lane.  The Q lanes share one histogram; a lane refreshes its pruning bound
+// from it after each of its cells among the own cell and the faces (counts
+// only grow, so a bound read early is still an upper bound of the k-th
+// distance), and pass B starts once every lane is through pass A.  Pass B
+// takes buffer slots from a counter in LDS, so the order of the buffered rows
+// varies; the exact pass does not depend on it.  The query itself is not
+// counted in pass A (it is buffered in pass B and skipped by the exact pass).
+// Returns the number of buffered rows (written to gbuf[i * n + p]), or -1 when
+// the query goes to the wave search; *level = the block's level.
+template <int Q>
+NG_DEV int qsum(int v) {
+#pragma unroll
+  for (int d = 1; d < Q; d <<= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+template <int Q>
+NG_DEV unsigned long long qor64(unsigned long long v) {
+#pragma unroll
+  for (int d = 1; d < Q; d <<= 1) {
+    const unsigned lo = __shfl_xor((unsigned)v, d, 64);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), d, 64);
+    v |= ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+// drops the lowest set bits of m, `count` of them
+NG_DEV unsigned long long drop_bits(unsigned long long m, int count) {
+  for (int i = 0; i < count && m; ++i) m &= m - 1ull;
+  return m;
+}
+
+template <int K, int Q>
+NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const SegInfo& S,
+                          const int* __restrict__ table, int block_min, int lane_rows,
+                          unsigned* __restrict__ hist, int bs, int* __restrict__ slot,
+                          int* __restrict__ gbuf, int* level, int* screens) {
   constexpr int CAP = 2 * K;
+  const int r = lane_id() & (Q - 1);
   const int keff = S.keff;
   const int LT = S.LT;
   const int* cstart = table + S.toff;
   const QueryGeo q = query_geo(cen[p], S);
   const float qxf = q.qxf, qyf = q.qyf, qzf = q.qzf;
 
-  // level: finest L whose block holds >= bmin rows (level 1's block is the
-  // whole segment); bmin > keff, so the block holds keff rows besides p.
-  // mask: the block's non-empty cells (bit c: cell c of the block order)
   int bmin = block_min > keff + 1 ? block_min : keff + 1;
   if (bmin > S.nrows) bmin = S.nrows;
   int L = LT;
@@ -525,7 +556,9 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
     rows = 0;
     mask = 0u;
 #pragma unroll
-    for (int c = 0; c < 27; ++c) {
+    for (int i = 0; i < (27 + Q - 1) / Q; ++i) {
+      const int c = i * Q + r;
+      if (c >= 27) continue;
       const int ox = blk(kBlkX, c), oy = blk(kBlkY, c), oz = blk(kBlkZ, c);
       const int x = cx + ox, y = cy + oy, z = cz + oz;
       if (x < 0 || x >= G || y < 0 || y >= G || z < 0 || z >= G) continue;
@@ -535,23 +568,23 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
       rows += cnt;
       if (cnt > 0) mask |= 1u << c;
     }
+    rows = qsum<Q>(rows);
+    mask = (unsigned)qor64<Q>(mask);
     if (rows >= bmin || L <= 1) break;
   }
   *level = L;
   *screens = 0;
   if (rows > lane_rows) return -1;
-  int nscreen = 0;  // float distance screens (passes A and B)
+  int nscreen = 0;
 
   const int sl = 10 - L, sub = 3 * (LT - L);
   const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
-  const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;  // real units
-  const float side_g = (float)(1 << sl);                             // grid units
-  const float sc2 = q.sc * q.sc;  // real squared distance -> grid units
+  const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;
+  const float side_g = (float)(1 << sl);
+  const float sc2 = q.sc * q.sc;
   int base = (int)(__float_as_uint(side * side) >> 21) - 24;
   if (base < 0) base = 0;
   const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
-  // squared gap (grid units) from the query to the slabs of the three cell
-  // columns around it on each axis (faces widened by the grid slack)
   auto gaps = [&](int cc, float ta, float* g2) {
 #pragma unroll
     for (int o = -1; o <= 1; ++o) {
@@ -566,7 +599,6 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
   gaps(cy, q.tq[1], gy2);
   gaps(cz, q.tq[2], gz2);
   auto pick3 = [](const float* v, int off) { return off < 0 ? v[0] : (off > 0 ? v[2] : v[1]); };
-  // float distance from the query to the box of block cell c
   auto box_d2 = [&](int c) {
     return pick3(gx2, blk(kBlkX, c)) + pick3(gy2, blk(kBlkY, c)) + pick3(gz2, blk(kBlkZ, c));
   };
@@ -576,7 +608,6 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
     a = cstart[f];
     b = cstart[f + (1u << sub)];
   };
-  // upper edge of the bin that holds the keff-th distance (+inf if unknown)
   auto kth_edge = [&]() {
     int cum = 0, bstar = -1;
 #pragma unroll
@@ -590,65 +621,64 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
     if (bstar < 0 || bstar == 31 || base + bstar + 1 >= 1020) return INFINITY;
     return __uint_as_float((unsigned)(base + bstar + 1) << 21);
   };
-  // visits the non-empty cells in block order, the range of the next cell
-  // loaded before the current one is scanned; f(c, a, b, next) scans one
-  auto for_cells = [&](auto&& f) {
-    unsigned rem = mask;
-    int c = rem ? __ffs(rem) - 1 : -1;
+  // this lane's cells of a mask (every Q-th set bit from its r-th), the
+  // range of the next one loaded before the current one is scanned
+  auto for_my_cells = [&](unsigned long long msk, auto&& rng, auto&& f) {
+    unsigned long long rem = drop_bits(msk, r);
+    int c = rem ? __ffsll((long long)rem) - 1 : -1;
     int a = 0, b = 0;
-    if (c >= 0) range(c, a, b);
+    if (c >= 0) rng(c, a, b);
     while (c >= 0) {
-      rem &= rem - 1u;
-      const int cn = rem ? __ffs(rem) - 1 : -1;
+      rem = drop_bits(rem, Q);
+      const int cn = rem ? __ffsll((long long)rem) - 1 : -1;
       int an = 0, bn = 0;
-      if (cn >= 0) range(cn, an, bn);
-      f(c, a, b, cn);
+      if (cn >= 0) rng(cn, an, bn);
+      f(c, a, b);
       c = cn;
       a = an;
       b = bn;
     }
   };
 
-  // pass A (p itself is counted in bin 0 with the own cell, then removed)
+  // pass A
 #pragma unroll
-  for (int w = 0; w < 16; ++w) hist[w * bs] = 0u;
-  auto count = [&](const float4& cj) {
+  for (int w = 0; w < 16; ++w)
+    if ((w & (Q - 1)) == r) hist[w * bs] = 0u;
+  if (r == 0) *slot = 0;
+  auto count = [&](const float4& cj, int j) {
+    if (j == p) return;
     const float d2 = d2_screen(qxf, qyf, qzf, cj);
     int bin = (int)(__float_as_uint(d2) >> 21) - base;
     bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
     atomicAdd(&hist[(bin >> 1) * bs], 1u << ((bin & 1) << 4));
   };
   float tau = INFINITY;
-  for_cells([&](int c, int a, int b, int cn) {
+  for_my_cells(mask, range, [&](int c, int a, int b) {
     if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * sc2 * kPrune)) {
       nscreen += b - a;
       int j = a;
       for (; j + 4 <= b; j += 4) {
         const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
-        count(c0);
-        count(c1);
-        count(c2);
-        count(c3);
+        count(c0, j);
+        count(c1, j + 1);
+        count(c2, j + 2);
+        count(c3, j + 3);
       }
-      for (; j < b; ++j) count(cen[j]);
+      for (; j < b; ++j) count(cen[j], j);
     }
-    if (c == 0) hist[0] -= 1u;  // p, at distance 0
-    // refresh the bound after the own cell and after the faces
-    if (c == 0 || (c <= 6 && (cn < 0 || cn > 6))) tau = kth_edge();
+    if (c <= 6) tau = kth_edge();  // after the own cell and each face
   });
-  tau = kth_edge();
+  tau = kth_edge();  // (every lane of the query is through pass A here)
 
-  // pass B: rows within tau into the buffer (slot CAP takes the overflow);
-  // p itself (distance 0, own cell) is buffered too and skipped later
+  // pass B: rows within tau into the buffer, slots from the counter
   const float adm = tau * kScreen;
-  int nb = 0;
   auto keep = [&](const float4& cj, int j) {
-    const bool in = d2_screen(qxf, qyf, qzf, cj) <= adm;
-    gbuf[(long long)(nb < CAP ? nb : CAP) * n + p] = j;
-    nb += in ? 1 : 0;
+    if (d2_screen(qxf, qyf, qzf, cj) <= adm) {
+      const int pos = atomicAdd(slot, 1);
+      if (pos < CAP) gbuf[(long long)pos * n + p] = j;
+    }
   };
-  for_cells([&](int c, int a, int b, int) {
-    if (c > 0 && box_d2(c) > tau * sc2 * kPrune) return;
+  auto scan_rows = [&](int a, int b) {
     nscreen += b - a;
     int j = a;
     for (; j + 4 <= b; j += 4) {
@@ -659,18 +689,22 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
       keep(c3, j + 3);
     }
     for (; j < b; ++j) keep(cen[j], j);
+  };
+  for_my_cells(mask, range, [&](int c, int a, int b) {
+    if (c > 0 && box_d2(c) > tau * sc2 * kPrune) return;
+    scan_rows(a, b);
   });
 
   // Rows outside the block: the block's keff-th float distance bounds the
   // true k-th one (times the rounding factor), so every row that may enter
-  // the list lies within r of the query, in a level-L cell whose box
-  // (widened by the margin) meets that ball.  The cells of that range
-  // outside the block are screened here too, unless the range spans more
-  // than kExtCells cells (then the wave search takes the query).
-  if (q.sc > 0.f) {  // (a zero-extent grid has every row in the own cell)
+  // the list lies within r of the query, in a level-L cell whose box (widened
+  // by the margin) meets that ball.  The cells of that range outside the
+  // block are screened here too, unless the range spans more than kExtCells
+  // cells or holds more than kExtRows rows (then the wave search takes the
+  // query).
+  bool gave_up = false;
+  if (q.sc > 0.f) {
     const int G = 1 << L;
-    // ball radius in grid units, widened by the slack of the faces and of
-    // the subtraction below
     const float rg = sqrtf(adm) * q.sc * 1.000002f + 2.f * kGridSlack;
     const int c3[3] = {cx, cy, cz};
     int lo3[3], hi3[3];
@@ -686,68 +720,58 @@ NG_DEV int block_gather(const float4* __restrict__ cen, int p, int n, const SegI
       vol *= hi3[a] - lo3[a] + 1;
     }
     if (!inside) {
-      if (!(tau < INFINITY) || vol > kExtCells) return -1;
-      // the range's cells outside the block whose box is within the bound
-      // (bit i: cell i of the range in x-fastest order)
-      const int nx = hi3[0] - lo3[0] + 1, ny = hi3[1] - lo3[1] + 1;
-      unsigned long long emask = 0ull;
-      for (int i = 0; i < vol; ++i) {
-        const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
-        if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
-        auto gap = [&](int c, float ta) {
-          return fmaxf(fmaxf((float)c * side_g - kGridSlack - ta,
-                             ta - ((float)(c + 1) * side_g + kGridSlack)), 0.f);
-        };
-        const float gx = gap(x, q.tq[0]), gy = gap(y, q.tq[1]), gz = gap(z, q.tq[2]);
-        if (!(fmaf(gz, gz, fmaf(gy, gy, gx * gx)) > tau * sc2 * kPrune)) emask |= 1ull << i;
-      }
-      auto erange = [&](int i, int& a, int& b) {
-        const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
-        const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
-                            spread10((unsigned)z)) << sub;
-        a = cstart[f];
-        b = cstart[f + (1u << sub)];
-      };
-      // as in for_cells: the next cell's range is loaded before a cell is scanned
-      int i = emask ? __ffsll((long long)emask) - 1 : -1;
-      int a = 0, b = 0;
-      if (i >= 0) erange(i, a, b);
-      while (i >= 0) {
-        emask &= emask - 1ull;
-        const int in_ = emask ? __ffsll((long long)emask) - 1 : -1;
-        int an = 0, bn = 0;
-        if (in_ >= 0) erange(in_, an, bn);
-        nscreen += b - a;
-        int j = a;
-        for (; j + 4 <= b; j += 4) {
-          const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
-          keep(c0, j);
-          keep(c1, j + 1);
-          keep(c2, j + 2);
-          keep(c3, j + 3);
+      if (!(tau < INFINITY) || vol > kExtCells) {
+        gave_up = true;
+      } else {
+        const int nx = hi3[0] - lo3[0] + 1, ny = hi3[1] - lo3[1] + 1;
+        unsigned long long emask = 0ull;
+        for (int i = r; i < vol; i += Q) {
+          const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
+          if (abs(x - cx) <= 1 && abs(y - cy) <= 1 && abs(z - cz) <= 1) continue;
+          auto gap = [&](int c, float ta) {
+            return fmaxf(fmaxf((float)c * side_g - kGridSlack - ta,
+                               ta - ((float)(c + 1) * side_g + kGridSlack)), 0.f);
+          };
+          const float gx = gap(x, q.tq[0]), gy = gap(y, q.tq[1]), gz = gap(z, q.tq[2]);
+          if (!(fmaf(gz, gz, fmaf(gy, gy, gx * gx)) > tau * sc2 * kPrune)) emask |= 1ull << i;
         }
-        for (; j < b; ++j) keep(cen[j], j);
-        i = in_;
-        a = an;
-        b = bn;
+        emask = qor64<Q>(emask);
+        auto erange = [&](int i, int& a, int& b) {
+          const int x = lo3[0] + i % nx, y = lo3[1] + (i / nx) % ny, z = lo3[2] + i / (nx * ny);
+          const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
+                              spread10((unsigned)z)) << sub;
+          a = cstart[f];
+          b = cstart[f + (1u << sub)];
+        };
+        int erows = 0;
+        for_my_cells(emask, erange, [&](int, int a, int b) { erows += b - a; });
+        erows = qsum<Q>(erows);
+        if (erows > kExtRows)
+          gave_up = true;
+        else
+          for_my_cells(emask, erange, [&](int, int a, int b) { scan_rows(a, b); });
       }
     }
   }
   *screens = nscreen;
-  if (nb > CAP || nb < keff + 1) return -1;  // (nb >= keff + 1 by construction)
+  if (gave_up) return -1;
+  const int nb = *slot;  // (every lane of the query is through pass B here)
+  if (nb > CAP || nb < keff + 1) return -1;
   return nb;
 }
 
 // list (nullable): query only the rows list[0, *d_count)
-template <int K>
+// (Q lanes per query: the queries of a block are its threads / Q)
+template <int K, int Q>
 __global__ void __launch_bounds__(256)
 k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
             const SegInfo* __restrict__ seg, const int* __restrict__ table, int block_min,
             int lane_rows, int* __restrict__ gbuf, int2* __restrict__ ginfo,
             unsigned long long* __restrict__ screens, const int* __restrict__ list,
             const int* __restrict__ d_count) {
-  extern __shared__ unsigned s_hist[];  // [16][bs]: two 16-bit bin counts per word
-  const int idx = xcd_block() * blockDim.x + threadIdx.x;
+  // [16][bs / Q]: two 16-bit bin counts per word, then [bs / Q] slot counters
+  extern __shared__ unsigned s_hist[];
+  const int idx = (xcd_block() * blockDim.x + threadIdx.x) / Q;
   const int cnt = list ? *d_count : n;
   const int p = idx < cnt ? (list ? list[idx] : idx) : n;
   int ns = 0;
@@ -755,9 +779,11 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
     const SegInfo& S = seg[sg ? sg[p] : 0];
     if (S.kclass == K) {
       int L = 0;
-      const int nb = block_gather<K>(cen, p, n, S, table, block_min, lane_rows,
-                                     s_hist + threadIdx.x, blockDim.x, gbuf, &L, &ns);
-      ginfo[p] = make_int2(nb, L);
+      const int nb = block_gather_q<K, Q>(cen, p, n, S, table, block_min, lane_rows,
+                                          s_hist + threadIdx.x / Q, blockDim.x / Q,
+                                          (int*)s_hist + 16 * (blockDim.x / Q) + threadIdx.x / Q,
+                                          gbuf, &L, &ns);
+      if ((threadIdx.x & (Q - 1)) == 0) ginfo[p] = make_int2(nb, L);
     }
   }
   // the screens of the wave, one atomic
@@ -766,46 +792,13 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
   if (lane_id() == 0 && ns) atomicAdd(screens, (unsigned long long)ns);
 }
 
-// Pass C: the buffered rows get the exact key (d2 in double, logical index)
-// and a sorted insertion; the buffer holds every row that may enter the list,
-// so its keff best are the exact list.  Returns 0 (retry from scratch) when
-// the gather gave up, else -1.
-template <int K>
-NG_DEV int exact_query(const float4* __restrict__ cen, int p, int n, int k_out,
-                       const SegInfo& S, const int* __restrict__ inv, int rows_logical,
-                       int* __restrict__ nbr, const int* __restrict__ gbuf, int2 info) {
-  const int nb = info.x;
-  if (nb < 0) return 0;
-  const int keff = S.keff;
-  const float4 cq = cen[p];
-  const double qx = cq.x, qy = cq.y, qz = cq.z;
-  Best<K> best;
-  best.init();
-  // software pipeline: the next row's centre is loaded while one is inserted
-  int j = gbuf[p];
-  float4 c = cen[j];
-  for (int i = 0; i < nb; ++i) {
-    const int jn = i + 1 < nb ? gbuf[(long long)(i + 1) * n + p] : p;
-    const float4 cn = cen[jn];
-    if (j != p) best.consider(dist2(qx, qy, qz, c.x, c.y, c.z), __float_as_int(c.w));
-    j = jn;
-    c = cn;
-  }
-  const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
-  int* out = nbr + row * k_out;
-#pragma unroll
-  for (int t = 0; t < K; ++t) {
-    if (t < k_out) {
-      int o = -1;
-      if (t < keff) o = inv ? inv[best.l[t]] : best.l[t];
-      out[t] = o;
-    }
-  }
-  for (int t = K; t < k_out; ++t) out[t] = -1;
-  return -1;
-}
-
-template <int K>
+// Pass C with Q lanes per query (consecutive lanes): lane r takes the
+// buffered rows r, r + Q, ... (their loads issue together), gives them the
+// exact key, and ranks each against all buffered rows (keys broadcast from
+// the other lanes); a row of rank t < keff is entry t of the list (as its
+// working row when inv is given: the buffer holds working rows).  The keys
+// are distinct (logical indices are), so the ranks are the sorted order.
+template <int K, int Q>
 __global__ void __launch_bounds__(256)
 k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
             const SegInfo* __restrict__ seg, const int* __restrict__ table,
@@ -813,27 +806,75 @@ k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restr
             const int* __restrict__ gbuf, const int2* __restrict__ ginfo,
             int2* __restrict__ retry, int* __restrict__ n_retry, const int* __restrict__ list,
             const int* __restrict__ d_count) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int CAP = 2 * K;
+  constexpr int PER = CAP / Q;  // buffer slots per lane
+  const int lane = lane_id();
+  const int r = lane & (Q - 1), qb = lane & ~(Q - 1);
+  const int idx = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) / Q);
   const int cnt = list ? *d_count : n;
   const int p = idx < cnt ? (list ? list[idx] : idx) : n;
-  int res = -1;
+  bool need = false;
   if (p < n) {
     const SegInfo& S = seg[sg ? sg[p] : 0];
-    if (S.kclass == K)
-      res = exact_query<K>(cen, p, n, k_out, S, inv, rows_logical, nbr, gbuf, ginfo[p]);
+    const int nb = S.kclass == K ? ginfo[p].x : -2;
+    if (nb == -1 || (nb >= 0 && nb > CAP)) {
+      need = r == 0;  // the gather gave up: retry from scratch
+    } else if (nb >= 0) {
+      const int keff = S.keff;
+      const float4 cq = cen[p];
+      const double qx = cq.x, qy = cq.y, qz = cq.z;
+      int jj[PER];
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        const int i = t * Q + r;
+        jj[t] = i < nb ? gbuf[(long long)i * n + p] : -1;
+      }
+      double d[PER];
+      int l[PER];
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        d[t] = INFINITY;
+        l[t] = INT_MAX;
+        if (jj[t] >= 0 && jj[t] != p) {
+          const float4 c = cen[jj[t]];
+          d[t] = dist2(qx, qy, qz, c.x, c.y, c.z);
+          l[t] = __float_as_int(c.w);
+        }
+      }
+      int rank[PER];
+#pragma unroll
+      for (int t = 0; t < PER; ++t) rank[t] = 0;
+      // every buffered key against this lane's keys
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        if (u * Q >= nb) break;  // (the same for the Q lanes)
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+          const double dy = __shfl(d[u], qb + s, 64);
+          const int ly = __shfl(l[u], qb + s, 64);
+#pragma unroll
+          for (int t = 0; t < PER; ++t)
+            rank[t] += (dy < d[t] || (dy == d[t] && ly < l[t])) ? 1 : 0;
+        }
+      }
+      const long long row = rows_logical ? (long long)__float_as_int(cq.w) : (long long)p;
+      int* out = nbr + row * k_out;
+#pragma unroll
+      for (int t = 0; t < PER; ++t)
+        if (l[t] != INT_MAX && rank[t] < keff) out[rank[t]] = inv ? jj[t] : l[t];
+      for (int t = keff + r; t < k_out; t += Q) out[t] = -1;
+    }
   }
   // retries, appended with one atomic per wave
-  const bool need = res >= 0;
   const unsigned long long m = __ballot(need);
   if (m) {
-    const int lane = lane_id();
     const int leader = __ffsll((long long)m) - 1;
     int at = 0;
     if (lane == leader) at = atomicAdd(n_retry, __popcll(m));
     at = __shfl(at, leader, 64);
     if (need) {
       const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-      retry[at + __popcll(below)] = make_int2(p, res);
+      retry[at + __popcll(below)] = make_int2(p, 0);
     }
   }
 }
@@ -1405,15 +1446,16 @@ void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* 
   const Tuning& t = tuning_for(n);
   const int bs = t.knn_block;
   int tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
-  k_knn_block<K><<<blocks_for(n, bs), bs, (size_t)16 * bs * sizeof(unsigned), st>>>(
-      cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf, m.ginfo,
-      (unsigned long long*)(m.counters + 8), list, d_count);
+  constexpr int Q = kKnnLanes;
+  k_knn_block<K, Q><<<blocks_for((long long)n * Q, bs), bs, (size_t)17 * (bs / Q) * sizeof(unsigned),
+                      st>>>(cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf,
+                            m.ginfo, (unsigned long long*)(m.counters + 8), list, d_count);
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_EXACT) : -1;
-  k_knn_exact<K><<<blocks_for(n, 256), 256, 0, st>>>(cen, n, k_out, sg, dseg, m.table, inv,
-                                                      rows_logical, nbr, m.gbuf, m.ginfo,
-                                                      m.retry, m.counters + 1, list, d_count);
+  k_knn_exact<K, Q><<<blocks_for((long long)n * Q, 256), 256, 0, st>>>(
+      cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr, m.gbuf, m.ginfo, m.retry,
+      m.counters + 1, list, d_count);
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
 }
