@@ -1047,17 +1047,44 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         }
       });
       __syncthreads();
-      int h = lane < 32 ? s_hist[lane] : 0;
-      int cum = h;
+      int h = 0, cum = 0, bstar = -1;
+      auto scan_hist = [&]() {
+        h = lane < 32 ? s_hist[lane] : 0;
+        cum = h;
 #pragma unroll
-      for (int d = 1; d < 32; d <<= 1) {
-        const int y = __shfl_up(cum, d, 64);
-        if (lane >= d) cum += y;
+        for (int d = 1; d < 32; d <<= 1) {
+          const int y = __shfl_up(cum, d, 64);
+          if (lane >= d) cum += y;
+        }
+        const unsigned long long reach = __ballot(lane < 32 && cum >= keff);
+        bstar = reach ? __ffsll((long long)reach) - 1 : -1;
+      };
+      scan_hist();
+      // the keff-th in a crowded bin 0 (rows closer than the window's floor):
+      // the window moves down over those rows, 31 quarter octaves at a time;
+      // its top bin then ends where bin 0 did
+      bool closed = false;  // the top bin has an upper edge
+      while (bstar == 0 && __shfl(h, 0, 64) > 64 && base > 0) {
+        const int top = base, nbase = base > 31 ? base - 31 : 0;
+        __syncthreads();
+        if (lane < 32) s_hist[lane] = 0;
+        __syncthreads();
+        for_rows([&](int j, const float4& cj) {
+          if (j >= 0 && j != p) {
+            const int b21 = (int)(__float_as_uint(d2_screen(qxf, qyf, qzf, cj)) >> 21);
+            if (b21 <= top) {
+              const int bin = b21 - nbase;
+              atomicAdd(&s_hist[bin < 0 ? 0 : bin], 1);
+            }
+          }
+        });
+        __syncthreads();
+        base = nbase;
+        closed = true;
+        scan_hist();
       }
-      const unsigned long long reach = __ballot(lane < 32 && cum >= keff);
-      const int bstar = reach ? __ffsll((long long)reach) - 1 : -1;
       float tau = INFINITY;
-      if (bstar >= 0 && bstar < 31 && base + bstar + 1 < 1020)
+      if (bstar >= 0 && (bstar < 31 || closed) && base + bstar + 1 < 1020)
         tau = __uint_as_float((unsigned)(base + bstar + 1) << 21);
       // (bin 0 also holds every row below 2^base, so it is not split)
       if (bstar > 0 && tau < INFINITY) {
@@ -1189,7 +1216,8 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       add_cells(a, b);
       const int sl = 10 - L, G = 1 << L;
       const double sd = (double)(1 << sl) * g.inv_sc;
-      search(bin_base(sd * sd) - 24);
+      // (bins from (side/5.7)^2 up to 8 side^2, past the block's farthest row)
+      search(bin_base(sd * sd) - 20);
       kd = best.kth(keff);
       // exact if the k-th key is closer than the block's faces
       const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);

@@ -321,6 +321,54 @@ k_ld_tail(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
 }
 
 // ---- budget: keep the P smallest (cost, i, j) of each segment's matching --
+// Adds the lanes' valid bins to an LDS histogram.  Matched costs crowd a few
+// bins, and lanes of one instruction adding to one address serialise, so the
+// bin of the first valid lane (twice) is added once for all its lanes.
+NG_DEV void hist_add(int* hist, unsigned bin, bool valid) {
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+    const unsigned long long m = __ballot(valid);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const unsigned bl = (unsigned)__shfl((int)bin, leader, 64);
+    const bool same = valid && bin == bl;
+    const unsigned long long sm = __ballot(same);
+    if (lane_id() == leader) atomicAdd(&hist[bl], __popcll(sm));
+    valid = valid && !same;
+  }
+  if (valid) atomicAdd(&hist[bin], 1);
+}
+
+// The digit holding the need-th key of a 256-bin histogram (all threads of
+// the block; blockDim.x >= 256): an inclusive scan over the bins, then the
+// bin whose range of cumulative counts contains need.  Sets *s_digit,
+// *s_need (the rank within that digit) and *s_count (its keys).
+NG_DEV void pick_digit(const int* hist, int need, int* s_wsum, int* s_digit, int* s_need,
+                       int* s_count) {
+  const int t = threadIdx.x;
+  const int h = t < 256 ? hist[t] : 0;
+  int x = h;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane_id() >= d) x += y;
+  }
+  if (t < 256 && lane_id() == 63) s_wsum[t >> 6] = x;
+  __syncthreads();
+  if (t < 256) {
+    int off = 0;
+    for (int w = 0; w < (t >> 6); ++w) off += s_wsum[w];
+    const int incl = off + x, excl = incl - h;
+    // the last bin takes whatever is left (need never exceeds the keys)
+    if (excl < need && (incl >= need || t == 255)) {
+      *s_digit = t;
+      *s_need = need - excl;
+      *s_count = h;
+    }
+  }
+  __syncthreads();
+}
+
 // Pairs of segment b: idx[pstart[b] .. pend[b]) (idx null: pairs [0, M)).
 // One workgroup per segment runs a radix select when its matching exceeds
 // its budget P[b] (the matching of a segment's last pass only); mseg[b]
@@ -331,10 +379,11 @@ k_topp_seg(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
            const int* __restrict__ pstart, const int* __restrict__ pend,
            const int* __restrict__ d_M, const long long* __restrict__ Pseg,
            const int* __restrict__ lg, int* __restrict__ partner, int* __restrict__ mseg) {
+  constexpr int kTieCap = 2048;
   __shared__ int hist[256];
-  __shared__ unsigned s_prefix;
-  __shared__ int s_need, s_tie_count;
-  __shared__ unsigned long long s_prefix2;
+  __shared__ int s_wsum[4];
+  __shared__ int s_digit, s_need, s_count, s_ntie;
+  __shared__ unsigned long long s_k2[kTieCap];
   const int b = blockIdx.x;
   const int i0 = idx ? pstart[b] : 0;
   const int M = idx ? pend[b] - pstart[b] : *d_M;
@@ -345,12 +394,7 @@ k_topp_seg(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
   }
   const int P = (int)(Pll > 0 ? Pll : 0);
   auto at = [&](int i) { return idx ? idx[i0 + i] : i; };
-  if (threadIdx.x == 0) {
-    s_prefix = 0u;
-    s_need = P;
-    mseg[b] = P;
-  }
-  __syncthreads();
+  if (threadIdx.x == 0) mseg[b] = P;
   if (P == 0) {
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
       const int e = at(i);
@@ -359,74 +403,127 @@ k_topp_seg(const int* __restrict__ pair_a, const int* __restrict__ pair_b,
     }
     return;
   }
+  // (loops run over whole blocks of threads so that every lane of a wave
+  // reaches the ballots; eight keys per thread and step, their loads issued
+  // together)
+  constexpr int U = 8;
+  const int stride = U * (int)blockDim.x;
+  const int span = (M + stride - 1) / stride * stride;
+  unsigned prefix = 0u;
+  int need = P, tie_count = 0;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
     const unsigned hi_mask = pass == 0 ? 0u : (0xffffffffu << (shift + 8));
     for (int d = threadIdx.x; d < 256; d += blockDim.x) hist[d] = 0;
     __syncthreads();
-    const unsigned pref = s_prefix;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) {
-      const unsigned k = pair_c[at(i)];
-      if ((k & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k >> shift) & 255u], 1);
+    for (int i0 = threadIdx.x; i0 < span; i0 += stride) {
+      unsigned k[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        k[u] = i < M ? pair_c[at(i)] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        hist_add(hist, (k[u] >> shift) & 255u, i < M && (k[u] & hi_mask) == (prefix & hi_mask));
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int cum = 0, need = s_need, d = 0;
-      for (; d < 255; ++d) {
-        if (cum + hist[d] >= need) break;
-        cum += hist[d];
-      }
-      s_need = need - cum;
-      s_prefix = pref | ((unsigned)d << shift);
-      s_tie_count = hist[d];
-    }
+    pick_digit(hist, need, s_wsum, &s_digit, &s_need, &s_count);
+    prefix |= (unsigned)s_digit << shift;
+    need = s_need;
+    tie_count = s_count;
     __syncthreads();
   }
-  const unsigned T = s_prefix;
-  const bool all_ties = s_tie_count == s_need;
-  if (threadIdx.x == 0) s_prefix2 = all_ties ? ~0ull : 0ull;
-  __syncthreads();
+  const unsigned T = prefix;
+  const bool all_ties = tie_count == need;
+  unsigned long long prefix2 = all_ties ? ~0ull : 0ull;
   if (!all_ties) {
+    // several pairs share the cost T: rank them by (i, j), from an LDS copy
+    // of their keys when they fit (else straight from the pair arrays)
+    const bool in_lds = tie_count <= kTieCap;
+    if (in_lds) {
+      if (threadIdx.x == 0) s_ntie = 0;
+      __syncthreads();
+      for (int i0 = threadIdx.x; i0 < span; i0 += stride) {
+        int ee[U];
+        unsigned kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * (int)blockDim.x;
+          ee[u] = i < M ? at(i) : -1;
+          kk[u] = ee[u] >= 0 ? pair_c[ee[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (ee[u] >= 0 && kk[u] == T)
+            s_k2[atomicAdd(&s_ntie, 1)] =
+                ((unsigned long long)(unsigned)logical(lg, pair_a[ee[u]]) << 32) |
+                (unsigned long long)(unsigned)logical(lg, pair_b[ee[u]]);
+      }
+      __syncthreads();
+    }
+    const int tspan = (tie_count + (int)blockDim.x - 1) / (int)blockDim.x * (int)blockDim.x;
     for (int pass = 0; pass < 8; ++pass) {
       const int shift = 56 - 8 * pass;
       const unsigned long long hi_mask = pass == 0 ? 0ull : (~0ull << (shift + 8));
       for (int d = threadIdx.x; d < 256; d += blockDim.x) hist[d] = 0;
       __syncthreads();
-      const unsigned long long pref = s_prefix2;
-      for (int i = threadIdx.x; i < M; i += blockDim.x) {
-        const int e = at(i);
-        if (pair_c[e] != T) continue;
-        const unsigned long long k2 =
-            ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
-            (unsigned long long)(unsigned)logical(lg, pair_b[e]);
-        if ((k2 & hi_mask) == (pref & hi_mask)) atomicAdd(&hist[(k2 >> shift) & 255ull], 1);
+      if (in_lds) {
+        for (int i = threadIdx.x; i < tspan; i += blockDim.x) {
+          const unsigned long long k2 = i < tie_count ? s_k2[i] : 0ull;
+          hist_add(hist, (unsigned)((k2 >> shift) & 255ull),
+                   i < tie_count && (k2 & hi_mask) == (prefix2 & hi_mask));
+        }
+      } else {
+        for (int i = threadIdx.x; i < span; i += blockDim.x) {
+          bool v = false;
+          unsigned long long k2 = 0ull;
+          if (i < M) {
+            const int e = at(i);
+            if (pair_c[e] == T) {
+              k2 = ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
+                   (unsigned long long)(unsigned)logical(lg, pair_b[e]);
+              v = (k2 & hi_mask) == (prefix2 & hi_mask);
+            }
+          }
+          hist_add(hist, (unsigned)((k2 >> shift) & 255ull), v);
+        }
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int cum = 0, need = s_need, d = 0;
-        for (; d < 255; ++d) {
-          if (cum + hist[d] >= need) break;
-          cum += hist[d];
-        }
-        s_need = need - cum;
-        s_prefix2 = pref | ((unsigned long long)d << shift);
-      }
+      pick_digit(hist, need, s_wsum, &s_digit, &s_need, &s_count);
+      prefix2 |= (unsigned long long)s_digit << shift;
+      need = s_need;
       __syncthreads();
     }
   }
-  const unsigned long long T2 = s_prefix2;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const int e = at(i);
-    const unsigned k = pair_c[e];
-    bool kp = k < T;
-    if (k == T) {
-      const unsigned long long k2 = ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
-                                    (unsigned long long)(unsigned)logical(lg, pair_b[e]);
-      kp = k2 <= T2;
+  const unsigned long long T2 = prefix2;
+  for (int i0 = threadIdx.x; i0 < span; i0 += stride) {
+    int ee[U];
+    unsigned kk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      ee[u] = i < M ? at(i) : -1;
+      kk[u] = ee[u] >= 0 ? pair_c[ee[u]] : 0u;
     }
-    if (!kp) {
-      partner[pair_a[e]] = -1;
-      partner[pair_b[e]] = -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = ee[u];
+      if (e < 0) continue;
+      const unsigned k = kk[u];
+      bool kp = k < T;
+      if (k == T) {
+        const unsigned long long k2 =
+            ((unsigned long long)(unsigned)logical(lg, pair_a[e]) << 32) |
+            (unsigned long long)(unsigned)logical(lg, pair_b[e]);
+        kp = k2 <= T2;
+      }
+      if (!kp) {
+        partner[pair_a[e]] = -1;
+        partner[pair_b[e]] = -1;
+      }
     }
   }
 }

@@ -32,8 +32,8 @@ BUCKET_SIZES = (40_000, 250_000, 1_000_000)
 CANDIDATES = {
     "cost_block": ((64, 128, 256), ("cost",)),
     "knn_block": ((64, 128, 256), ("knn_query",)),
-    "knn_block_min": ((24, 32, 48), ("knn_query", "knn_exact", "knn_wave")),
-    "knn_lane_rows": ((192, 256, 384), ("knn_query", "knn_exact", "knn_wave")),
+    "knn_block_min": ((24, 32, 48, 64), ("knn_query", "knn_exact", "knn_wave")),
+    "knn_lane_rows": ((192, 256, 384, 512, 768), ("knn_query", "knn_exact", "knn_wave")),
     "knn_wave_grid": ((4096, 16384, 65536), ("knn_wave",)),
     "knn_level_bias": ((-1, 0), ("knn_tree", "knn_query", "knn_exact", "knn_wave")),
     "select_check": ((2, 4, 8), ("select",)),
