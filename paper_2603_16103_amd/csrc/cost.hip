@@ -54,6 +54,15 @@ NG_DEV float rcp_of(float x) { return __builtin_amdgcn_rcpf(x); }
 NG_DEV double rcp_of(double x) { return 1.0 / x; }
 NG_DEV float sqrt_of(float x) { return __builtin_amdgcn_sqrtf(x); }
 NG_DEV double sqrt_of(double x) { return sqrt(x); }
+// Logarithm and exponential: in float the hardware's base-2 forms (an
+// absolute error of a few 1e-7 on the logarithms that enter the cost), in
+// double the library's.
+NG_DEV float log_of(float x) { return __logf(x); }
+NG_DEV double log_of(double x) { return log(x); }
+NG_DEV float log1p_of(float x) { return __logf(1.0f + x); }
+NG_DEV double log1p_of(double x) { return log1p(x); }
+NG_DEV float exp_of(float x) { return __expf(x); }
+NG_DEV double exp_of(double x) { return exp(x); }
 
 template <typename T>
 NG_DEV V3<T> tri_mul(const Tri<T>& L, const V3<T>& z) {
@@ -171,7 +180,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
   const T c = pa * pb;
   const T den = T(1) + c * ee;
   const T inv_den = rcp_of(den);
-  const T half_logdet_m = log(LA.a00 * LA.a11 * LA.a22) + T(0.5) * log1p(c * ee);
+  const T half_logdet_m = log_of(LA.a00 * LA.a11 * LA.a22) + T(0.5) * log1p_of(c * ee);
   if (mode == NANOGS_COST_BOUND) {
     // KL(N_c || q_m) = 1/2 [tr(Sm^-1 Sc) + w_o^2 |e|^2 / den - 3] +
     // half log det Sm - log det L_c, with Sm^-1 = A^-1 - c A^-1 d d^T A^-1
@@ -190,7 +199,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
     const T kb = pb > T(0) ? pb * kl(Lb, ldLb, pa) : T(0);
     return ka + kb;
   }
-  const T lpa = log(pa), lpb = log(pb);
+  const T lpa = log_of(pa), lpb = log_of(pb);
   const T ne = sqrt_of(ee);
   const T inv_ne = ne > T(0) ? rcp_of(ne) : T(0);
   const V3<T> eh = {e.x * inv_ne, e.y * inv_ne, e.z * inv_ne};
@@ -217,7 +226,7 @@ NG_DEV T dgeo_pair(const V3<T>& mua, const V3<T>& mub, const Tri<T>& La, const T
     const T la = lpa + (ca ? lnc : lno);
     const T lb = lpb + (ca ? lno : lnc);
     const T mx = fmax(la, lb), mn = fmin(la, lb);
-    const T lse = mx + log1p(exp(mn - mx));
+    const T lse = mx + log1p_of(exp_of(mn - mx));
     return lse - lnm;
   };
   T acc = T(0);

@@ -183,8 +183,11 @@ long long* pinned_host();
 // sort.hip -- stable LSD radix sort of (uint32 key, int32 value) pairs
 size_t sort_temp_bytes(long long n);
 // Sorts keys/vals in place (using temp for the second buffers and counts).
+// With out_vals, an odd number of digit passes leaves the sorted pairs in
+// temp instead and *out_vals points at the sorted values there (the keys are
+// then not copied back either); otherwise *out_vals = vals.
 void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* temp,
-                    hipStream_t st);
+                    hipStream_t st, int** out_vals = nullptr);
 
 // activate.hip -- boundary conversions and packing
 // Stored form -> working layout; row p takes input row i = perm[p] (perm

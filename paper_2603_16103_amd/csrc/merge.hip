@@ -365,13 +365,17 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   if (seg && nout > 0) {
     // Morton order of the output centres within each segment (stable:
     // equal keys keep the compacted order), then grouped by segment
-    sort_pairs_u32(keys, order, nout, kSortKeyBits, stemp, st);
     if (nseg > 1) {
+      sort_pairs_u32(keys, order, nout, kSortKeyBits, stemp, st);
       k_order_seg<<<blocks_for(nout, 256), 256, 0, st>>>(order, sg, (int)nout, keys);
       NG_LAUNCH_CHECK();
       int bits = 1;
       while ((1 << bits) < nseg) ++bits;
       sort_pairs_u32(keys, order, nout, bits, stemp, st);
+    } else {
+      // (one segment: the sorted order is read where the sort left it; the
+      // sort's temp is not touched again before the gathers below)
+      sort_pairs_u32(keys, order, nout, kSortKeyBits, stemp, st, &order);
     }
   }
   if (nout > 0) {

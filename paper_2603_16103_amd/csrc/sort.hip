@@ -88,7 +88,8 @@ size_t sort_temp_bytes(long long n) {
 }
 
 void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* temp,
-                    hipStream_t st) {
+                    hipStream_t st, int** out_vals) {
+  if (out_vals) *out_vals = vals;
   if (n <= 1) return;
   long long nt = (n + STILE - 1) / STILE;
   Carver c(temp);
@@ -113,6 +114,10 @@ void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* 
     std::swap(va, vb);
   }
   if (ka != keys) {
+    if (out_vals) {  // the caller takes the values where they are
+      *out_vals = va;
+      return;
+    }
     NG_HIP(hipMemcpyAsync(keys, ka, n * sizeof(unsigned), hipMemcpyDeviceToDevice, st));
     NG_HIP(hipMemcpyAsync(vals, va, n * sizeof(int), hipMemcpyDeviceToDevice, st));
   }
