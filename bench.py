@@ -62,9 +62,9 @@ def stage_work(stage, n, e, k, screens):
     return None, None
 
 
-KERNEL_OF = {"knn_query": "k_knn_block<16>", "cost": "k_edge_cost", "precompute": "k_precompute",
+KERNEL_OF = {"knn_query": "k_knn_block<16,4>", "cost": "k_edge_cost", "precompute": "k_precompute",
              "select": "select stage (k_ld_pick, k_ld_match, k_ld_tail, k_topp_seg)",
-             "knn_alu": "k_knn_block<16>"}
+             "knn_alu": "k_knn_block<16,4>"}
 SOURCE_OF = {"knn_query": "knn.hip", "cost": "cost.hip", "precompute": "cost.hip",
              "select": "select.hip", "knn_alu": "knn.hip"}
 STAGE_OF = {"knn_alu": "knn_query"}  # timed stage of a roofline entry

@@ -31,9 +31,9 @@ HERE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 
 def short(name: str) -> str:
-    m = re.search(r"(k_\w+|__amd\w+)(<\d+>)?", name)
+    m = re.search(r"(k_\w+|__amd\w+)(<[\d, ]+>)?", name)
     if m:
-        return m.group(1) + (m.group(2) or "")
+        return m.group(1) + (m.group(2) or "").replace(" ", "")
     m = re.search(r"(\w*[Cc]opy\w*)", name)
     return m.group(1) if m else name[:48]
 
