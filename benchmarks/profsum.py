@@ -144,6 +144,50 @@ def occ(out_md, cmd, pmc_csv, trace_csv, kernels):
                      f"| {c.get('SQ_INSTS_LDS', 0) / waves:.0f} | {conf:.3f} |\n")
 
 
+def bench(out_md, default_json, cold_json, tree, traffic_json):
+    """Summary of two bench.py lines (default run and cold-cache run)."""
+    def last_json(path):
+        for line in reversed(open(path).read().splitlines()):
+            if line.startswith("{"):
+                return json.loads(line)
+        raise SystemExit(f"no JSON line in {path}")
+    d, c = last_json(default_json), last_json(cold_json)
+    tr = json.load(open(traffic_json)).get("kernels", {})
+    with open(out_md, "w") as fh:
+        fh.write("# bench.py on one MI355X: 1M synthetic splats -> 100k, k=16, S=1\n\n")
+        fh.write(f"Tree: {tree}.\n\nCommands (from the repository root):\n\n```\n"
+                 "python3 bench.py\n"
+                 "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --flush-mib 1024\n"
+                 f"python benchmarks/profsum.py bench {out_md} <default line> <cold line> {tree} "
+                 f"{traffic_json}\n```\n\n")
+        fh.write("| run | Gaussians/s | ms/step |\n|---|---|---|\n")
+        fh.write(f"| default ({d['steps']} steps) | {d['value']:.4g} | {d['ms_per_step']} |\n")
+        fh.write(f"| cold caches (1 GiB copied before each step, steps timed alone) "
+                 f"| {c['value']:.4g} | {c['ms_per_step']} |\n\n")
+        fh.write("Stage times per step (ms, HIP events on the call's stream):\n\n")
+        fh.write("| stage | default | cold |\n|---|---|---|\n")
+        for k, v in d["stage_ms_per_step"].items():
+            fh.write(f"| {k} | {v} | {c['stage_ms_per_step'].get(k)} |\n")
+        fh.write("\nRoofline of the dominant kernel and the others (algorithmic bytes per unit: "
+                 "kNN 12 + 4k B per splat; edge cost 236 B per splat + 12 B per edge; selection "
+                 "12 B per edge + 4 B per splat; factor precompute 72 B per splat):\n\n")
+        fh.write("| entry | kernel | avg launch us | algorithmic per launch | achieved | frac of peak "
+                 "| counted traffic per launch |\n|---|---|---|---|---|---|---|\n")
+        ents = [("dominant", d["roofline"])] + list(d.get("roofline_other_kernels", {}).items())
+        for name, r in ents:
+            algo = r.get("algo_bytes_per_launch") or r.get("algo_flops_per_launch")
+            unit = "B" if "algo_bytes_per_launch" in r else "flop"
+            t = tr.get(r["kernel"], {}).get("bytes_per_launch")
+            fh.write(f"| {name} | {r['kernel']} | {r['avg_launch_us']} | {algo:.4g} {unit} "
+                     f"| {r['achieved']} {r['unit']} | {r['frac']} "
+                     f"| {f'{t:.4g} B' if t else '-'} |\n")
+        cb = d.get("cpu_baseline")
+        if cb:
+            fh.write(f"\nCPU baseline (the FP64 oracle): {cb['sample']}; {cb['value']:.4g} "
+                     f"Gaussians/s on {cb['cores']} threads, "
+                     f"{cb['single_thread']['value']:.4g} on one thread.\n")
+
+
 def main(argv):
     if argv[0] == "stats":
         stats(*argv[1:5])
@@ -151,6 +195,8 @@ def main(argv):
         occ(argv[1], argv[2], argv[3], argv[4], argv[5:])
     elif argv[0] == "traffic":
         traffic(*argv[1:9], argv[9:])
+    elif argv[0] == "bench":
+        bench(*argv[1:6])
     else:
         raise SystemExit(__doc__)
 
