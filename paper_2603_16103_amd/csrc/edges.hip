@@ -51,9 +51,11 @@ k_edge_flags(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int
 
 // thread per row: emitted count (the row's flags are contiguous bytes)
 __global__ void __launch_bounds__(256)
-k_edge_count(const unsigned char* __restrict__ flag, int n, int k, int* __restrict__ cnt) {
+k_edge_count(const unsigned char* __restrict__ flag, int n, int k, int* __restrict__ cnt,
+             int* __restrict__ ideg) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > n) return;
+  if (ideg) ideg[p] = 0;  // the incoming counters of the emit pass
   int c = 0;
   if (p < n) {
     const unsigned char* f = flag + (long long)p * k;
@@ -186,10 +188,10 @@ void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es,
   const int vec4 = (k % 4 == 0) && ((uintptr_t)nbr % 16 == 0);
   k_edge_flags<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, lg, n, k, vec4, flag);
   NG_LAUNCH_CHECK();
-  k_edge_count<<<blocks_for(n + 1, 256), 256, 0, st>>>(flag, n, k, cnt);
+  k_edge_count<<<blocks_for(n + 1, 256), 256, 0, st>>>(flag, n, k, cnt,
+                                                       es.ioff ? ideg : nullptr);
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(cnt, es.eoff, n + 1, tot, stemp, st);
-  if (es.ioff) fill_i32(ideg, 0, n + 1, st);
   k_edge_emit<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, n, k, flag, es.eoff, es.src, es.tgt,
                                                   ideg, es.ioff ? es.islot : nullptr);
   NG_LAUNCH_CHECK();

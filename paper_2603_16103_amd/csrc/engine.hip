@@ -47,12 +47,12 @@ __global__ void k_stats_knn(const int* __restrict__ unsorted, const int* __restr
   }
 }
 
-__global__ void k_stats_select(const long long* __restrict__ d_m, const int* __restrict__ fb,
+__global__ void k_stats_select(const int* __restrict__ m, const int* __restrict__ fb,
                                const int* __restrict__ tail, const int* __restrict__ mseg,
                                int nseg, long long* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    out[0] = *d_m;
+    out[0] = *m;
     out[5] = *fb;
     out[6] = *tail;
   }
@@ -110,13 +110,19 @@ struct EngineWs {
   int* perm;
   int* counters;
   long long* stats;  // a pass's counts (k_stats_knn / k_stats_select)
-  long long* d_m;
   SegInfo* seg;
   float* crn;
+  long long* budget;  // pairs allowed this pass, per segment
   unsigned* boxes;  // [jobs][8]
   void* temp;
   size_t bytes;
 };
+
+static_assert((sizeof(SegInfo) + NG_CRN_ROW * sizeof(float)) % alignof(long long) == 0,
+              "the budgets of the staging layout must be aligned");
+static size_t stage_bytes(int J) {
+  return (size_t)J * (sizeof(SegInfo) + NG_CRN_ROW * sizeof(float) + sizeof(long long)) + 256;
+}
 
 static EngineWs carve_engine(void* base, long long R, int K, int J) {
   Carver c(base);
@@ -144,9 +150,12 @@ static EngineWs carve_engine(void* base, long long R, int K, int J) {
   s.perm = c.take<int>(R);
   s.counters = c.take<int>(64);
   s.stats = c.take<long long>(8 + (size_t)J);
-  s.d_m = c.take<long long>(8);
-  s.seg = c.take<SegInfo>(J);
-  s.crn = c.take<float>((size_t)J * NG_CRN_ROW);
+  // segment table, draws and budgets in the page-locked staging layout, so
+  // one copy uploads all three
+  char* up = c.take<char>(stage_bytes(J));
+  s.seg = (SegInfo*)up;
+  s.crn = (float*)(up + (size_t)J * sizeof(SegInfo));
+  s.budget = (long long*)(up + (size_t)J * (sizeof(SegInfo) + NG_CRN_ROW * sizeof(float)));
   s.boxes = c.take<unsigned>((size_t)J * 8);
   s.temp = base ? (char*)base + c.bytes() : nullptr;
   size_t kb = 0;
@@ -165,9 +174,6 @@ size_t Engine::workspace_bytes(long long rows, int kmax, int jobs) {
   return carve_engine(nullptr, rows, kmax, jobs).bytes;
 }
 
-static size_t stage_bytes(int J) {
-  return (size_t)J * (sizeof(SegInfo) + NG_CRN_ROW * sizeof(float) + sizeof(long long)) + 256;
-}
 
 Engine::Engine(long long rows, int kmax, int jobs, const Opts& o, void* ws, hipStream_t st)
     : R_(rows < 2 ? 2 : rows), K_(kmax), J_(jobs), o_(o), st_(st) {
@@ -347,15 +353,16 @@ int Engine::step(StageTimer* T) {
     NG_HIP(hipStreamSynchronize(st_));
     return finished;
   }
-  NG_HIP(hipMemcpyAsync(W.seg, hs, nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st_));
   // draws of every segment's current pass
   std::memset(hcrn, 0, (size_t)nseg * NG_CRN_ROW * sizeof(float));
   for (int i = 0; i < nseg; ++i) {
     const Job& j = jobs_[live_[i]];
     crn_host(j.spec.seed, j.round, o_.S, &hcrn[(size_t)i * NG_CRN_ROW]);
   }
-  NG_HIP(hipMemcpyAsync(W.crn, hcrn, (size_t)nseg * NG_CRN_ROW * sizeof(float),
-                        hipMemcpyHostToDevice, st_));
+  // one upload: the segment table, the draws and the budgets (the device
+  // block has the staging layout; the slots past nseg go up unused)
+  NG_HIP(hipMemcpyAsync(W.seg, stage_, (char*)(hP + nseg) - (char*)stage_, hipMemcpyHostToDevice,
+                        st_));
 
   const Work& a = W.w[cur_];
   const Work& b = W.w[cur_ ^ 1];
@@ -366,7 +373,8 @@ int Engine::step(StageTimer* T) {
   launch_precompute(a.shp, (int)N, W.pre, st_);
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_TREE) : -1;
-  fill_i32(W.counters + 2, 0, 1, st_);
+  // counters [1] FP64-fallback edges, [2] the row order flag
+  fill_i32(W.counters + 1, 0, 2, st_);
   knn_build(a.cen, (int)N, sg, W.seg, entries, W.temp, W.counters + 2, st_);
   if (T) T->stop(tk);
   // local neighbourhood refresh (one scene): from the second pass on, only
@@ -389,18 +397,16 @@ int Engine::step(StageTimer* T) {
   NG_LAUNCH_CHECK();
   tk = T ? T->start(NANOGS_T_EDGES) : -1;
   const EdgeSet es{W.src, W.tgt, W.eoff, W.ioff, W.islot, W.aoff};
-  launch_union_edges(W.nbr, a.lg, (int)N, K_, es, W.d_m, W.temp, st_);
+  launch_union_edges(W.nbr, a.lg, (int)N, K_, es, nullptr, W.temp, st_);
   if (T) T->stop(tk);
-  // the edge count stays on the device: the cost launches cover N * k
-  // edges and read it there
+  // the edge count stays on the device (eoff[N], at most N * k): the cost
+  // launches cover N * k edges and read it there
   const int m_cap = (int)(N * K_);
-  int* mcount = W.counters + 3;
-  count_to_i32(W.d_m, m_cap, mcount, st_);
+  const int* mcount = W.eoff + N;
 
   const CrnTab ct{W.crn, o_.S, sg, W.seg, o_.cost_mode};
   const AdjOut adj_out{W.eoff, W.ioff, W.islot, W.akey, W.au};
-  int* fb_count = W.counters + 1;
-  fill_i32(fb_count, 0, 1, st_);
+  int* fb_count = W.counters + 1;  // (zeroed with the order flag)
   if (o_.precision == NANOGS_PREC_FP64) {
     tk = T ? T->start(NANOGS_T_COST_FP64) : -1;
     launch_edge_cost_fp64(a.cen, a.shp, a.sh, o_.app_dims, W.src, W.tgt, (int)N, true, nullptr,
@@ -421,8 +427,8 @@ int Engine::step(StageTimer* T) {
   const Adjacency adj{W.aoff, W.akey, W.au};
   const int* d_mseg = nullptr;
   const int* d_tail = nullptr;
-  const int grid_iters = select_pairs_async(adj, (int)N, a.lg, sg, nseg, hP, W.partner, W.temp,
-                                            st_, &d_mseg, &d_tail);
+  const int grid_iters = select_pairs_async(adj, (int)N, a.lg, sg, nseg, W.budget, W.partner,
+                                            W.temp, st_, &d_mseg, &d_tail);
   if (T) T->stop(tk);
 
   // the pass's counts come back with the merge's synchronisation
@@ -451,7 +457,7 @@ int Engine::step(StageTimer* T) {
       ++j.lod_levels;
     }
   }
-  k_stats_select<<<blocks_for(nseg, 256), 256, 0, st_>>>(W.d_m, fb_count, d_tail, d_mseg, nseg,
+  k_stats_select<<<blocks_for(nseg, 256), 256, 0, st_>>>(mcount, fb_count, d_tail, d_mseg, nseg,
                                                           W.stats);
   NG_LAUNCH_CHECK();
   NG_HIP(hipMemcpyAsync(hb, W.stats, (8 + (size_t)nseg) * sizeof(long long),

@@ -364,12 +364,11 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
                           const long long* hP, int* partner, void* temp, hipStream_t st,
                           long long* d_npairs, long long* hM, const long long* dP = nullptr);
 // As select_pairs with nothing read back and no synchronisation: budgets
-// from page-locked host memory hP_pinned (copied asynchronously), the pairs
-// kept per segment left in device memory (*d_mseg, nseg ints), the
-// finishing workgroup's iteration count in *d_tail_iters (device).  Returns
-// the grid-wide iterations launched.
+// in device memory (dP, nseg), the pairs kept per segment left in device
+// memory (*d_mseg, nseg ints), the finishing workgroup's iteration count in
+// *d_tail_iters (device).  Returns the grid-wide iterations launched.
 int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
-                       const long long* hP_pinned, int* partner, void* temp, hipStream_t st,
+                       const long long* dP, int* partner, void* temp, hipStream_t st,
                        const int** d_mseg, const int** d_tail_iters);
 
 // merge.hip -- MPMM merge + stable compaction in working layout

@@ -285,9 +285,12 @@ k_table_fill(const int* __restrict__ code, int n, int m, int* __restrict__ table
 }
 
 // Rows of segments without a search (inert): empty lists.
+// Also zeroes the query counters (zero[0, nzero)).
 __global__ void k_knn_prefill(int n, const int* __restrict__ sg, const SegInfo* __restrict__ seg,
-                              int k_out, int* __restrict__ nbr) {
+                              int k_out, int* __restrict__ nbr, int* __restrict__ zero,
+                              int nzero) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nzero) zero[p] = 0;
   if (p >= n) return;
   if (seg[sg ? sg[p] : 0].kclass == 0)
     for (int t = 0; t < k_out; ++t) nbr[(long long)p * k_out + t] = -1;
@@ -1508,10 +1511,10 @@ void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo
                int* nbr, StageTimer* T, hipStream_t st) {
   KnnMem m = carve_knn(mem, n, entries, k_out, nullptr);
   const int* inv = use_inv ? m.inv : nullptr;
-  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr);
+  if (n <= 0) return;
+  // (counters: [1] retries, [8, 10) the screens as a 64-bit sum)
+  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr, m.counters + 1, 9);
   NG_LAUNCH_CHECK();
-  fill_i32(m.counters + 1, 0, 1, st);
-  fill_i32(m.counters + 8, 0, 2, st);  // screens (64-bit)
   if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   if (class_mask & 4u) query_k<24>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);

@@ -761,7 +761,7 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
 // (*d_tail_iters).  Returns the grid-wide iterations launched.  Launches
 // that depend on the pair count cover its capacity (n / 2 + 1).
 int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg, int nseg,
-                       const long long* hP_pinned, int* partner, void* temp, hipStream_t st,
+                       const long long* dP, int* partner, void* temp, hipStream_t st,
                        const int** d_mseg, const int** d_tail_iters) {
   Carver c(temp);
   int* pick = c.take<int>(n);
@@ -774,7 +774,6 @@ int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg
   int* pidx = c.take<int>(n / 2 + 1);
   int* pstart = c.take<int>(nseg);
   int* pend = c.take<int>(nseg);
-  long long* Pdev = c.take<long long>(nseg);
   int* mseg = c.take<int>(nseg);
   int* counters = c.take<int>(64);
   PickState ps;
@@ -785,7 +784,6 @@ int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg
 
   fill_i32(partner, -1, n, st);
   fill_i32(counters, 0, 64, st);
-  NG_HIP(hipMemcpyAsync(Pdev, hP_pinned, nseg * sizeof(long long), hipMemcpyHostToDevice, st));
   const int it = ld_iterations(adj, n, lg, partner, pick, pcost, act, pair_a, pair_b, pair_c,
                                counters, ps, st);
   const int* idx = nullptr;
@@ -803,7 +801,7 @@ int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg
     NG_LAUNCH_CHECK();
     idx = pidx;
   }
-  k_topp_seg<<<nseg, 1024, 0, st>>>(pair_a, pair_b, pair_c, idx, pstart, pend, counters + 2, Pdev,
+  k_topp_seg<<<nseg, 1024, 0, st>>>(pair_a, pair_b, pair_c, idx, pstart, pend, counters + 2, dP,
                                      lg, partner, mseg);
   NG_LAUNCH_CHECK();
   *d_mseg = mseg;
