@@ -185,6 +185,104 @@ k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
   }
 }
 
+// The first pick of a matching (every end free): kPickLanes lanes per
+// vertex.  Lane r loads the vertex's entries r, r + kPickLanes, ... (the
+// group's loads are contiguous and issue together) and keeps its kTop
+// smallest; kTop rounds of a minimum over the group then give the vertex's
+// kTop smallest entries in order (the keys of one vertex are distinct: they
+// end in the other end's logical index), the same cache and pick as a full
+// scan by one lane.
+constexpr int kPickLanes = 8;
+
+__global__ void __launch_bounds__(256)
+k_ld_pick_first(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
+                const int* __restrict__ au, int n, int* __restrict__ pick,
+                unsigned* __restrict__ pcost, int* __restrict__ next_count, PickState ps) {
+  constexpr int L = kPickLanes;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  const int lane = lane_id();
+  const int r = lane & (L - 1), gb = lane & ~(L - 1);
+  const long long stride = (long long)gridDim.x * blockDim.x / L;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / L; i < n; i += stride) {
+    const int v = (int)i;
+    const int t0 = aoff[v], t1 = aoff[v + 1];
+    unsigned long long k[kTop];
+    int uu[kTop];
+#pragma unroll
+    for (int q = 0; q < kTop; ++q) {
+      k[q] = KEY_MAX;
+      uu[q] = -1;
+    }
+    auto consider = [&](unsigned long long key, int u) {
+      if (!(key < k[kTop - 1])) return;
+      bool lt_next = true;
+#pragma unroll
+      for (int q = kTop - 1; q > 0; --q) {
+        const bool lt_prev = key < k[q - 1];
+        const unsigned long long nk = lt_prev ? k[q - 1] : (lt_next ? key : k[q]);
+        const int nu = lt_prev ? uu[q - 1] : (lt_next ? u : uu[q]);
+        k[q] = nk;
+        uu[q] = nu;
+        lt_next = lt_prev;
+      }
+      if (lt_next) {
+        k[0] = key;
+        uu[0] = u;
+      }
+    };
+    int t = t0 + r;
+    for (; t + 2 * L < t1; t += 3 * L) {
+      const unsigned long long a0 = akey[t], a1 = akey[t + L], a2 = akey[t + 2 * L];
+      const int u0 = au[t], u1 = au[t + L], u2 = au[t + 2 * L];
+      consider(a0, u0);
+      consider(a1, u1);
+      consider(a2, u2);
+    }
+    for (; t < t1; t += L) consider(akey[t], au[t]);
+    // the group's kTop smallest, one per round (KEY_MAX: none left)
+    int head = 0;
+    unsigned long long gk[kTop];
+    int gu[kTop];
+#pragma unroll
+    for (int q = 0; q < kTop; ++q) {
+      unsigned long long mine = KEY_MAX;
+      int mu = -1;
+#pragma unroll
+      for (int h = 0; h < kTop; ++h)
+        if (h == head) {
+          mine = k[h];
+          mu = uu[h];
+        }
+      unsigned long long m = mine;
+#pragma unroll
+      for (int d = 1; d < L; d <<= 1) {
+        const unsigned lo = __shfl_xor((unsigned)m, d, 64);
+        const unsigned hi = __shfl_xor((unsigned)(m >> 32), d, 64);
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        m = o < m ? o : m;
+      }
+      const unsigned long long own = (__ballot(mine == m && m != KEY_MAX) >> gb) & ((1ull << L) - 1);
+      const int owner = own ? gb + __ffsll((long long)own) - 1 : gb;
+      const int u = __shfl(mu, owner, 64);
+      gk[q] = m;
+      gu[q] = m != KEY_MAX ? u : -1;
+      if (own && lane == owner) ++head;
+    }
+    if (r == 0) {
+      int n_ok = 0;
+#pragma unroll
+      for (int q = 0; q < kTop; ++q) {
+        ps.tkey[(long long)v * kTop + q] = gk[q];
+        ps.tu[(long long)v * kTop + q] = gu[q];
+        n_ok += gu[q] >= 0 ? 1 : 0;
+      }
+      ps.tn[v] = n_ok;
+      pick[v] = gu[0];
+      pcost[v] = (unsigned)(gk[0] >> 32);
+    }
+  }
+}
+
 // Block-wide append: every thread with `flag` gets a distinct slot of
 // `list`, with one atomic on *count per block.  Every thread of the block
 // must call it (it synchronises the block).
@@ -645,8 +743,12 @@ int ld_iterations(const Adjacency& adj, int n, const int* lg, int* partner, int*
     const long long span = std::max(2048ll, (long long)expect);
     expect *= 0.6;
     const unsigned g = grid_for(span);
-    k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n, pick,
-                                 pcost, out_cnt, ps);
+    if (it == 0)
+      k_ld_pick_first<<<grid_for(span * kPickLanes), 256, 0, st>>>(adj.aoff, adj.akey, adj.au, n,
+                                                                   pick, pcost, out_cnt, ps);
+    else
+      k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n, pick,
+                                   pcost, out_cnt, ps);
     NG_LAUNCH_CHECK();
     unsigned gm = (unsigned)((span + kMatchBlock - 1) / kMatchBlock);
     gm = gm < 1 ? 1 : (gm > 1024 ? 1024 : gm);
