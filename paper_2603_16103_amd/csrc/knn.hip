@@ -399,9 +399,9 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
 // its own cell holds at least `block_min` rows (or the segment's rows, if
 // fewer), and selects its k best within that block in three passes over the
 // block's rows, none of which inserts into a sorted list per candidate:
-//   A. a histogram of the float squared distances, 32 bins of a quarter
-//      octave each from (side/8)^2 to (2 side)^2 (side = cell side), giving
-//      tau = the upper edge of the bin holding the keff-th distance;
+//   A. a histogram of the float squared distances, 64 bins of an eighth of
+//      an octave each from (side/8)^2 to (2 side)^2 (side = cell side),
+//      giving tau = the upper edge of the bin holding the keff-th distance;
 //   B. the rows whose float distance is within tau (widened for rounding) go
 //      to a buffer (about keff of them);
 //   C. the buffered rows get the exact key (d2 in double, logical index) and
@@ -445,6 +445,7 @@ NG_DEV Dil3 dil3(unsigned v) {
 NG_DEV unsigned dil_pick(const Dil3& d, int off) { return off < 0 ? d.m : (off > 0 ? d.p : d.c); }
 
 constexpr int kKnnLanes = 4;     // lanes per query of the block search
+constexpr int kHistWords = 32;   // its histogram: 64 eighth-octave bins, two per word
 constexpr int kExtCells = 64;
 constexpr int kExtRows = 128;  // rows of those cells a query scans itself   // cells of the k-th ball's range a lane may screen itself
 // float screen: a point whose exact d2 is <= B has float d2 <= B * kScreen
@@ -585,7 +586,8 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
   const float side = q.sc > 0.f ? (float)(1 << sl) / q.sc : 0.f;
   const float side_g = (float)(1 << sl);
   const float sc2 = q.sc * q.sc;
-  int base = (int)(__float_as_uint(side * side) >> 21) - 24;
+  // eighth-octave bins: the float bits >> 20 (exponent and 3 mantissa bits)
+  int base = (int)(__float_as_uint(side * side) >> 20) - 48;
   if (base < 0) base = 0;
   const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
   auto gaps = [&](int cc, float ta, float* g2) {
@@ -614,15 +616,15 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
   auto kth_edge = [&]() {
     int cum = 0, bstar = -1;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) {
+    for (int w = 0; w < kHistWords; ++w) {
       const unsigned v = hist[w * bs];
       cum += (int)(v & 0xffffu);
       if (bstar < 0 && cum >= keff) bstar = 2 * w;
       cum += (int)(v >> 16);
       if (bstar < 0 && cum >= keff) bstar = 2 * w + 1;
     }
-    if (bstar < 0 || bstar == 31 || base + bstar + 1 >= 1020) return INFINITY;
-    return __uint_as_float((unsigned)(base + bstar + 1) << 21);
+    if (bstar < 0 || bstar == 2 * kHistWords - 1 || base + bstar + 1 >= 2040) return INFINITY;
+    return __uint_as_float((unsigned)(base + bstar + 1) << 20);
   };
   // this lane's cells of a mask (every Q-th set bit from its r-th), the
   // range of the next one loaded before the current one is scanned
@@ -645,14 +647,14 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
 
   // pass A
 #pragma unroll
-  for (int w = 0; w < 16; ++w)
+  for (int w = 0; w < kHistWords; ++w)
     if ((w & (Q - 1)) == r) hist[w * bs] = 0u;
   if (r == 0) *slot = 0;
   auto count = [&](const float4& cj, int j) {
     if (j == p) return;
     const float d2 = d2_screen(qxf, qyf, qzf, cj);
-    int bin = (int)(__float_as_uint(d2) >> 21) - base;
-    bin = bin < 0 ? 0 : (bin > 31 ? 31 : bin);
+    int bin = (int)(__float_as_uint(d2) >> 20) - base;
+    bin = bin < 0 ? 0 : (bin > 2 * kHistWords - 1 ? 2 * kHistWords - 1 : bin);
     atomicAdd(&hist[(bin >> 1) * bs], 1u << ((bin & 1) << 4));
   };
   float tau = INFINITY;
@@ -772,7 +774,8 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
             int lane_rows, int* __restrict__ gbuf, int2* __restrict__ ginfo,
             unsigned long long* __restrict__ screens, const int* __restrict__ list,
             const int* __restrict__ d_count) {
-  // [16][bs / Q]: two 16-bit bin counts per word, then [bs / Q] slot counters
+  // [kHistWords][bs / Q]: two 16-bit bin counts per word, then [bs / Q] slot
+  // counters
   extern __shared__ unsigned s_hist[];
   const int idx = (xcd_block() * blockDim.x + threadIdx.x) / Q;
   const int cnt = list ? *d_count : n;
@@ -784,7 +787,7 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
       int L = 0;
       const int nb = block_gather_q<K, Q>(cen, p, n, S, table, block_min, lane_rows,
                                           s_hist + threadIdx.x / Q, blockDim.x / Q,
-                                          (int*)s_hist + 16 * (blockDim.x / Q) + threadIdx.x / Q,
+                                          (int*)s_hist + kHistWords * (blockDim.x / Q) + threadIdx.x / Q,
                                           gbuf, &L, &ns);
       if ((threadIdx.x & (Q - 1)) == 0) ginfo[p] = make_int2(nb, L);
     }
@@ -1478,7 +1481,7 @@ void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* 
   const int bs = t.knn_block;
   int tk = T ? T->start(NANOGS_T_KNN_QUERY) : -1;
   constexpr int Q = kKnnLanes;
-  k_knn_block<K, Q><<<blocks_for((long long)n * Q, bs), bs, (size_t)17 * (bs / Q) * sizeof(unsigned),
+  k_knn_block<K, Q><<<blocks_for((long long)n * Q, bs), bs, (size_t)(kHistWords + 1) * (bs / Q) * sizeof(unsigned),
                       st>>>(cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf,
                             m.ginfo, (unsigned long long*)(m.counters + 8), list, d_count);
   NG_LAUNCH_CHECK();
