@@ -646,16 +646,15 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
   };
 
   // pass A
-#pragma unroll
-  for (int w = 0; w < kHistWords; ++w)
-    if ((w & (Q - 1)) == r) hist[w * bs] = 0u;
+  for (int w = r; w < kHistWords; w += Q) hist[w * bs] = 0u;
   if (r == 0) *slot = 0;
   auto count = [&](const float4& cj, int j) {
-    if (j == p) return;
     const float d2 = d2_screen(qxf, qyf, qzf, cj);
     int bin = (int)(__float_as_uint(d2) >> 20) - base;
     bin = bin < 0 ? 0 : (bin > 2 * kHistWords - 1 ? 2 * kHistWords - 1 : bin);
-    atomicAdd(&hist[(bin >> 1) * bs], 1u << ((bin & 1) << 4));
+    // (the query itself adds nothing; a select, not a branch, so that the
+    // row loads of a batch issue together)
+    atomicAdd(&hist[(bin >> 1) * bs], j == p ? 0u : 1u << ((bin & 1) << 4));
   };
   float tau = INFINITY;
   for_my_cells(mask, range, [&](int c, int a, int b) {
