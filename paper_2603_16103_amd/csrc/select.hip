@@ -82,7 +82,7 @@ __global__ void k_adj_fill(const int* __restrict__ ea, const int* __restrict__ e
 // are all matched scans its whole range again (and refills the cache with
 // the smallest entries whose other end is free, the only ones that can
 // matter later).
-constexpr int kTop = 4;
+constexpr int kTop = 2;  // (2, 4, 6 and 8 measured: 2 is fastest)
 
 struct PickState {
   unsigned long long* tkey;  // [n][kTop] cached smallest keys, ascending
