@@ -445,6 +445,7 @@ NG_DEV Dil3 dil3(unsigned v) {
 NG_DEV unsigned dil_pick(const Dil3& d, int off) { return off < 0 ? d.m : (off > 0 ? d.p : d.c); }
 
 constexpr int kKnnLanes = 4;     // lanes per query of the block search
+constexpr int kExactLanes = 8;   // lanes per query of the exact pass (4 and 8 measured)
 constexpr int kHistWords = 32;   // its histogram: 64 eighth-octave bins, two per word
 constexpr int kExtCells = 64;
 constexpr int kExtRows = 128;  // rows of those cells a query scans itself   // cells of the k-th ball's range a lane may screen itself
@@ -1486,7 +1487,9 @@ void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* 
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_EXACT) : -1;
-  k_knn_exact<K, Q><<<blocks_for((long long)n * Q, 256), 256, 0, st>>>(
+  constexpr int QE = kExactLanes;
+  static_assert(2 * K % QE == 0, "exact-pass lanes must divide the buffer");
+  k_knn_exact<K, QE><<<blocks_for((long long)n * QE, 256), 256, 0, st>>>(
       cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr, m.gbuf, m.ginfo, m.retry,
       m.counters + 1, list, d_count);
   NG_LAUNCH_CHECK();

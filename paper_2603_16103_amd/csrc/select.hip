@@ -192,7 +192,7 @@ k_ld_pick(const int* __restrict__ aoff, const unsigned long long* __restrict__ a
 // kTop smallest entries in order (the keys of one vertex are distinct: they
 // end in the other end's logical index), the same cache and pick as a full
 // scan by one lane.
-constexpr int kPickLanes = 8;
+constexpr int kPickLanes = 4;  // (4 and 8 measured)
 
 __global__ void __launch_bounds__(256)
 k_ld_pick_first(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
