@@ -42,7 +42,10 @@ __global__ void k_stats_knn(const int* __restrict__ unsorted, const int* __restr
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     out[1] = *unsorted;
     out[2] = kc[1];
-    out[3] = *(const long long*)(kc + 8);
+    long long s = 0;
+    for (int i = 0; i < kScreenSlots; ++i)
+      s += *(const long long*)(kc + kScreenBase + i * kScreenStride);
+    out[3] = s;
     out[4] = dcount ? *dcount : 0;
   }
 }

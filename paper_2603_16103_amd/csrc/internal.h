@@ -234,12 +234,20 @@ long long table_entries(int LT);
 // kNN scratch: concatenated per-segment cell tables, logical -> working
 // inverse, sparse-query list.
 struct StageTimer;
+// The block gather's screen count is summed by each wave into one of
+// kScreenSlots 64-bit counters, each on a 128-byte line of its own, from
+// counters[kScreenBase] (kScreenStride ints apart): atomics from every wave
+// of the chip to one address serialise.
+constexpr int kScreenBase = 64;
+constexpr int kScreenSlots = 64;
+constexpr int kScreenStride = 32;
+constexpr int kKnnCounters = kScreenBase + kScreenSlots * kScreenStride;
 struct KnnMem {
   int* table;
   int* inv;      // logical index -> working row
   int2* retry;   // (row, 0) of the queries the wave search finishes
   int2* ginfo;   // per query: (rows buffered by the block gather or -1, level)
-  int* counters;  // [1]: retry count
+  int* counters;  // [1]: retry count; the screen sums from kScreenBase
   int* gbuf;     // [slot][n] rows buffered by the block gather
 };
 KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* bytes);

@@ -792,10 +792,12 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
       if ((threadIdx.x & (Q - 1)) == 0) ginfo[p] = make_int2(nb, L);
     }
   }
-  // the screens of the wave, one atomic
+  // the screens of the wave, one atomic on the block's slot
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) ns += __shfl_xor(ns, d, 64);
-  if (lane_id() == 0 && ns) atomicAdd(screens, (unsigned long long)ns);
+  if (lane_id() == 0 && ns)
+    atomicAdd(screens + (blockIdx.x % kScreenSlots) * (kScreenStride / 2),
+              (unsigned long long)ns);
 }
 
 // Pass C with Q lanes per query (consecutive lanes): lane r takes the
@@ -804,8 +806,9 @@ k_knn_block(const float4* __restrict__ cen, int n, const int* __restrict__ sg,
 // the other lanes); a row of rank t < keff is entry t of the list (as its
 // working row when inv is given: the buffer holds working rows).  The keys
 // are distinct (logical indices are), so the ranks are the sorted order.
+constexpr int kExactWaves = 4;  // waves per workgroup of the exact pass
 template <int K, int Q>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kExactWaves)
 k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restrict__ sg,
             const SegInfo* __restrict__ seg, const int* __restrict__ table,
             const int* __restrict__ inv, int rows_logical, int* __restrict__ nbr,
@@ -871,17 +874,26 @@ k_knn_exact(const float4* __restrict__ cen, int n, int k_out, const int* __restr
       for (int t = keff + r; t < k_out; t += Q) out[t] = -1;
     }
   }
-  // retries, appended with one atomic per wave
+  // retries, appended with one atomic per workgroup (atomics of every wave
+  // on one address serialise)
+  __shared__ int s_cnt[kExactWaves + 1];
+  const int w = (int)threadIdx.x >> 6;
   const unsigned long long m = __ballot(need);
-  if (m) {
-    const int leader = __ffsll((long long)m) - 1;
-    int at = 0;
-    if (lane == leader) at = atomicAdd(n_retry, __popcll(m));
-    at = __shfl(at, leader, 64);
-    if (need) {
-      const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-      retry[at + __popcll(below)] = make_int2(p, 0);
+  if (lane == 0) s_cnt[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int q = 0; q < kExactWaves; ++q) {
+      const int c = s_cnt[q];
+      s_cnt[q] = tot;
+      tot += c;
     }
+    s_cnt[kExactWaves] = tot ? atomicAdd(n_retry, tot) : 0;
+  }
+  __syncthreads();
+  if (need) {
+    const unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+    retry[s_cnt[kExactWaves] + s_cnt[w] + __popcll(below)] = make_int2(p, 0);
   }
 }
 
@@ -1448,7 +1460,7 @@ KnnMem carve_knn(void* base, long long n, long long entries, int kmax, size_t* b
   m.inv = c.take<int>(n);
   m.retry = c.take<int2>(n);
   m.ginfo = c.take<int2>(n);
-  m.counters = c.take<int>(64);
+  m.counters = c.take<int>(kKnnCounters);
   // last: its size depends on kmax (builds carve with kmax = 0)
   m.gbuf = c.take<int>(n * (2 * (long long)kclass_of(kmax) + 1));
   if (bytes) *bytes = c.bytes();
@@ -1483,13 +1495,14 @@ void query_k(const float4* cen, int n, int k_out, const int* sg, const SegInfo* 
   constexpr int Q = kKnnLanes;
   k_knn_block<K, Q><<<blocks_for((long long)n * Q, bs), bs, (size_t)(kHistWords + 1) * (bs / Q) * sizeof(unsigned),
                       st>>>(cen, n, sg, dseg, m.table, t.knn_block_min, t.knn_lane_rows, m.gbuf,
-                            m.ginfo, (unsigned long long*)(m.counters + 8), list, d_count);
+                            m.ginfo, (unsigned long long*)(m.counters + kScreenBase), list,
+                            d_count);
   NG_LAUNCH_CHECK();
   if (T) T->stop(tk);
   tk = T ? T->start(NANOGS_T_KNN_EXACT) : -1;
   constexpr int QE = kExactLanes;
   static_assert(2 * K % QE == 0, "exact-pass lanes must divide the buffer");
-  k_knn_exact<K, QE><<<blocks_for((long long)n * QE, 256), 256, 0, st>>>(
+  k_knn_exact<K, QE><<<blocks_for((long long)n * QE, 64 * kExactWaves), 64 * kExactWaves, 0, st>>>(
       cen, n, k_out, sg, dseg, m.table, inv, rows_logical, nbr, m.gbuf, m.ginfo, m.retry,
       m.counters + 1, list, d_count);
   NG_LAUNCH_CHECK();
@@ -1517,8 +1530,9 @@ void knn_query(const float4* cen, int n, int k_out, const int* sg, const SegInfo
   KnnMem m = carve_knn(mem, n, entries, k_out, nullptr);
   const int* inv = use_inv ? m.inv : nullptr;
   if (n <= 0) return;
-  // (counters: [1] retries, [8, 10) the screens as a 64-bit sum)
-  k_knn_prefill<<<blocks_for(n, 256), 256, 0, st>>>(n, sg, dseg, k_out, nbr, m.counters + 1, 9);
+  // (counters: [1] retries, the screen slots from kScreenBase)
+  k_knn_prefill<<<blocks_for(std::max(n, kKnnCounters), 256), 256, 0, st>>>(
+      n, sg, dseg, k_out, nbr, m.counters + 1, kKnnCounters - 1);
   NG_LAUNCH_CHECK();
   if (class_mask & 1u) query_k<8>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
   if (class_mask & 2u) query_k<16>(cen, n, k_out, sg, dseg, m, inv, rows_logical, nbr, T, st);
@@ -1539,7 +1553,7 @@ void knn_refresh(const float4* cen, int n_new, int n_old, int k_out, int keff, c
   fill_i32(pcount, 0, n_new, st);
   fill_i32(dcount, 0, 1, st);
   fill_i32(m.counters + 1, 0, 1, st);
-  fill_i32(m.counters + 8, 0, 2, st);
+  fill_i32(m.counters + kScreenBase, 0, kScreenSlots * kScreenStride, st);
   if (n_old > 0) {
     k_refresh_count<<<blocks_for(n_old, 256), 256, 0, st>>>(parent, n_old, pcount);
     NG_LAUNCH_CHECK();
