@@ -127,6 +127,8 @@ def main():
                     help="cold-cache variant: copy this many MiB between steps (outside the "
                          "timed calls) so no step finds its data in the caches; the value is "
                          "then the sum of the per-step times")
+    ap.add_argument("--breakdown-steps", type=int, default=2,
+                    help="untimed steps with every stage timed (stage breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (the "
@@ -163,53 +165,53 @@ def main():
         eprint(f"warmup {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
 
-    stage_ms = {s: 0.0 for s in ng.STAGES}
-    launches = {s: 0 for s in ng.STAGES}
-    work_by_stage = {s: 0.0 for s in KERNEL_OF}
-    edges_total = 0
-    last = None
     flush = None
     if args.flush_mib:
         flush = torch.empty(args.flush_mib << 18, dtype=torch.float32, device="cuda")
         flush_dst = torch.empty_like(flush)
-    cold_s = 0.0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        st = ng.Stats()
-        if flush is not None:
-            flush_dst.copy_(flush)
-            torch.cuda.synchronize()
-            tc = time.perf_counter()
-        n_out = simp(g, target, out, st)
-        if flush is not None:
-            torch.cuda.synchronize()
-            cold_s += time.perf_counter() - tc
-        d = st.as_dict()
-        for s in ng.STAGES:
-            stage_ms[s] += d["stage_ms"][s]
-            launches[s] += d["stage_launches"][s]
-        for n_r, e_r, sc_r in zip(d["n_per_round"], d["edges_per_round"],
-                                  d["knn_screens_per_round"]):
-            edges_total += e_r
-            for s in KERNEL_OF:
-                _, w = stage_work(s, n_r, e_r, k, sc_r)
-                if w is not None:
-                    work_by_stage[s] += w
-        last = d
-        eprint(f"step {i + 1}/{args.steps}: {n_out} splats, {d['rounds']} passes")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert n_out == target, (n_out, target)
 
-    if flush is not None:
-        dt = cold_s
-    ms_step = 1000.0 * dt / args.steps
-    value = args.n * args.steps / dt
-    def roof(stage):
+    def run(steps, label):
+        """steps calls; returns (seconds, per-stage ms and launches, the
+        algorithmic work per roofline entry, edges, the last call's stats)"""
+        acc = {"ms": {s: 0.0 for s in ng.STAGES}, "launches": {s: 0 for s in ng.STAGES},
+               "work": {s: 0.0 for s in KERNEL_OF}, "edges": 0, "last": None}
+        cold_s = 0.0
+        n_out = target
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            st = ng.Stats()
+            if flush is not None:
+                flush_dst.copy_(flush)
+                torch.cuda.synchronize()
+                tc = time.perf_counter()
+            n_out = simp(g, target, out, st)
+            if flush is not None:
+                torch.cuda.synchronize()
+                cold_s += time.perf_counter() - tc
+            d = st.as_dict()
+            for s in ng.STAGES:
+                acc["ms"][s] += d["stage_ms"][s]
+                acc["launches"][s] += d["stage_launches"][s]
+            for n_r, e_r, sc_r in zip(d["n_per_round"], d["edges_per_round"],
+                                      d["knn_screens_per_round"]):
+                acc["edges"] += e_r
+                for s in KERNEL_OF:
+                    _, w = stage_work(s, n_r, e_r, k, sc_r)
+                    if w is not None:
+                        acc["work"][s] += w
+            acc["last"] = d
+            eprint(f"{label} {i + 1}/{steps}: {n_out} splats, {d['rounds']} passes")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert n_out == target, (n_out, target)
+        return (cold_s if flush is not None else dt), acc
+
+    def roof(stage, acc):
         bound, _ = stage_work(stage, 1, 1, k, 1)
         ts = STAGE_OF.get(stage, stage)
-        avg_ms = stage_ms[ts] / launches[ts]
-        per_launch = work_by_stage[stage] / launches[ts]
+        avg_ms = acc["ms"][ts] / acc["launches"][ts]
+        per_launch = acc["work"][stage] / acc["launches"][ts]
         if bound == "hbm":
             achieved, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
             tr = traffic_for(stage)
@@ -222,12 +224,22 @@ def main():
                 ("algo_bytes_per_launch" if bound == "hbm" else "algo_flops_per_launch"):
                     int(per_launch)}
 
-    # the dominant kernel: the single-kernel stage with most time
-    single = [s for s in ("knn_query", "cost", "precompute") if launches[s] > 0]
-    dom = max(single, key=lambda s: stage_ms[s])
-    roof_dom = roof(dom)
-    others = {s: roof(s) for s in KERNEL_OF
-              if s != dom and launches[STAGE_OF.get(s, s)] > 0}
+    # breakdown steps (outside the timed region) with every stage timed: the
+    # per-stage times and the dominant kernel, the single-kernel stage with
+    # most time
+    _, bd = run(args.breakdown_steps, "breakdown step")
+    single = [s for s in ("knn_query", "cost", "precompute") if bd["launches"][s] > 0]
+    dom = max(single, key=lambda s: bd["ms"][s]) if single else "knn_query"
+    # the timed steps record HIP events around the dominant kernel only (an
+    # event record at every stage boundary costs stream time)
+    simp.opts.timing = ng.options(timing=(STAGE_OF.get(dom, dom),)).timing
+    dt, acc = run(args.steps, "step")
+    last = acc["last"]
+    ms_step = 1000.0 * dt / args.steps
+    value = args.n * args.steps / dt
+    roof_dom = roof(dom, acc)
+    others = {s: roof(s, bd) for s in KERNEL_OF
+              if s != dom and bd["launches"][STAGE_OF.get(s, s)] > 0}
     res = {
         "metric": "Gaussians simplified/s (1M→10%)",
         "value": round(value, 1),
@@ -250,9 +262,14 @@ def main():
                    "knn_wave_retries_per_pass": last["knn_retry_per_round"],
                    "knn_screens_per_pass": last["knn_screens_per_round"],
                    "cold_cache_flush_mib": args.flush_mib or None},
-        "edge_costs_per_s": round(edges_total / (stage_ms["cost"] * 1e-3), 1)
-        if stage_ms["cost"] > 0 else None,
-        "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 4) for s in ng.STAGES},
+        "edge_costs_per_s": round(bd["edges"] / (bd["ms"]["cost"] * 1e-3), 1)
+        if bd["ms"]["cost"] > 0 else None,
+        "stage_ms_per_step": {s: round(bd["ms"][s] / args.breakdown_steps, 4)
+                              for s in ng.STAGES} if args.breakdown_steps else None,
+        "stage_timing": f"stage_ms_per_step, edge_costs_per_s and roofline_other_kernels from "
+                        f"{args.breakdown_steps} breakdown steps with every stage timed, outside "
+                        f"the timed region; the timed steps time the dominant kernel's stage "
+                        f"({STAGE_OF.get(dom, dom)}) only",
         "roofline": roof_dom,
         "roofline_other_kernels": others,
     }

@@ -116,7 +116,10 @@ typedef struct {
   int32_t* d_origin;  /* nullable device [n]: provenance of each output
                          splat (smallest input index it absorbed) */
   int32_t timing;     /* 1: time each stage with HIP events on the call's
-                         stream into nanogs_stats.stage_ms (0) */
+                         stream into nanogs_stats.stage_ms;
+                         NANOGS_TIME_SOME | (1 << stage) | ...: only the
+                         stages whose bit is set (each event record costs a
+                         few microseconds of stream time); 0: off (0) */
   float tau;          /* opacity pre-filter of nanogs_simplify (Algorithm
                          1, before the loop): keep the splats with alpha >=
                          min(tau, median alpha); < 0 turns it off (-1) */
@@ -144,6 +147,8 @@ typedef struct {
 #define NANOGS_T_KNN_EXACT 10 /* kNN exact keys of the buffered rows */
 #define NANOGS_T_KNN_WAVE 11  /* kNN queries finished one wave each */
 #define NANOGS_NTIMED 12
+#define NANOGS_TIME_SOME 0x40000000 /* options.timing: the low NANOGS_NTIMED
+                                       bits select the stages timed */
 
 typedef struct {
   int32_t rounds;                          /* passes that merged >= 1 pair */
@@ -158,7 +163,7 @@ typedef struct {
                                                      the wave search */
   int64_t knn_screens_per_round[NANOGS_MAX_ROUNDS]; /* float distance screens
                                                        of the block gather */
-  double stage_ms[NANOGS_NTIMED];      /* summed over passes (timing = 1) */
+  double stage_ms[NANOGS_NTIMED];      /* summed over passes (stages timed) */
   int32_t stage_launches[NANOGS_NTIMED];
   int64_t n_kept;  /* splats the opacity pre-filter kept (n when it is off) */
   int64_t requery_per_round[NANOGS_MAX_ROUNDS]; /* rows whose kNN list was

@@ -58,6 +58,12 @@ nanogs_status read_opts(const nanogs_options* o, Opts* out) {
     set_error("options.max_rounds must be >= 0");
     return NANOGS_EINVAL;
   }
+  if (r.timing != 0 && r.timing != 1 &&
+      ((r.timing & ~(NANOGS_TIME_SOME | ((1 << NANOGS_NTIMED) - 1))) != 0 ||
+       (r.timing & NANOGS_TIME_SOME) == 0)) {
+    set_error("options.timing must be 0, 1 or NANOGS_TIME_SOME with stage bits");
+    return NANOGS_EINVAL;
+  }
   if (std::isnan(r.tau) || std::isinf(r.tau)) {
     set_error("options.tau must be finite (< 0 turns the opacity pre-filter off)");
     return NANOGS_EINVAL;
@@ -232,7 +238,7 @@ nanogs_status run_simplify(const nanogs_gaussians* in, long long n, long long ta
                            nanogs_stats* stats, void* ws, hipStream_t st,
                            const LodOut& lod = LodOut()) {
   thread_local StageTimer T;
-  T.begin_call(o.timing != 0, st);
+  T.begin_call(o.timing, st);
   // opacity pre-filter (Algorithm 1, before the loop): the loop runs on the
   // survivors; provenance is mapped back to input indices at the end
   nanogs_gaussians src = *in;

@@ -423,24 +423,41 @@ void remap_indices(int* v, long long count, const int* map, hipStream_t st);
 void crn_host(uint64_t seed, int round, int S, float* out);
 
 // Stage timing with HIP events recorded on the working stream.
+// Per-stage HIP event timing of one call.  The events come from a pool that
+// the timer keeps (per thread, for the device it was last used on; they are
+// not released before the thread ends), created without the system-scope
+// fence a default event record makes: a timing event needs no cache
+// writeback, and one at every stage boundary would stall the stream.
 struct StageTimer {
   static constexpr int kMax = 4096;
   bool on = false;
+  unsigned mask = 0;  // bit s: stage s is timed
   hipStream_t st = nullptr;
   int used = 0;
+  int created = 0;  // events in the pool
+  int dev = -1;     // device of the pool
   int stage[kMax / 2];
   hipEvent_t ev[kMax];
-  void begin_call(bool enable, hipStream_t s) {
-    on = enable;
+  // timing: options.timing (0 off, 1 every stage, NANOGS_TIME_SOME | bits)
+  void begin_call(int timing, hipStream_t s) {
+    on = timing != 0;
+    mask = timing == 1 ? ~0u : (unsigned)timing & 0x3fffffffu;  // (bits below the flag)
     st = s;
     used = 0;
+    if (!on) return;
+    int d = 0;
+    NG_HIP(hipGetDevice(&d));
+    if (d != dev) {  // a pool of another device's events: start a new one
+      created = 0;
+      dev = d;
+    }
   }
   int start(int which) {
-    if (!on || used + 2 > kMax) return -1;
+    if (!on || !((mask >> which) & 1u) || used + 2 > kMax) return -1;
     const int i = used;
     used += 2;
-    NG_HIP(hipEventCreate(&ev[i]));
-    NG_HIP(hipEventCreate(&ev[i + 1]));
+    for (; created < used; ++created)
+      NG_HIP(hipEventCreateWithFlags(&ev[created], hipEventDisableSystemFence));
     stage[i / 2] = which;
     NG_HIP(hipEventRecord(ev[i], st));
     return i;
@@ -448,15 +465,13 @@ struct StageTimer {
   void stop(int i) {
     if (i >= 0) NG_HIP(hipEventRecord(ev[i + 1], st));
   }
-  // after the stream is synchronised: accumulate and release the events
+  // after the stream is synchronised: accumulate (the events stay pooled)
   void collect(double* ms, int* launches) {
     for (int i = 0; i < used; i += 2) {
       float t = 0.f;
       NG_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
       ms[stage[i / 2]] += t;
       launches[stage[i / 2]] += 1;
-      NG_HIP(hipEventDestroy(ev[i]));
-      NG_HIP(hipEventDestroy(ev[i + 1]));
     }
     used = 0;
   }

@@ -30,6 +30,7 @@ REFRESH_LOCAL = 1
 STAGES = ("precompute", "knn_tree", "knn_query", "edges", "cost", "cost_fp64", "select",
           "merge", "setup", "output", "knn_exact", "knn_wave")
 NTIMED = len(STAGES)
+TIME_SOME = 0x40000000  # options.timing: the low NTIMED bits select stages
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EWORKSPACE", 3: "ENONFINITE", 4: "EHIP", 5: "ENOTREADY",
           6: "ENOMEM", 7: "ECANCELLED"}
@@ -233,13 +234,18 @@ def _workspace(nbytes: int):
 def options(S=1, app_dims=SH, precision=PREC_FP32, fb_ratio=1.0 / 256, seed=0, max_rounds=0,
             d_trace=None, d_origin=None, timing=False, tau=-1.0, cost_mode=COST_MC,
             refresh=REFRESH_FULL, pass_frac=0.0) -> Options:
+    """nanogs_options.  timing: False, True (every stage) or stage names
+    (STAGES) to time only those stages."""
     o = Options()
     load().nanogs_default_options(ctypes.byref(o))
     o.S, o.app_dims, o.precision, o.fb_ratio = S, app_dims, precision, fb_ratio
     o.seed, o.max_rounds = seed, max_rounds
     o.d_trace = _ptr(d_trace).value if d_trace is not None else None
     o.d_origin = _ptr(d_origin).value if d_origin is not None else None
-    o.timing = 1 if timing else 0
+    if timing is True or timing is False or isinstance(timing, int):
+        o.timing = 1 if timing else 0
+    else:  # stage names: only those stages are timed
+        o.timing = TIME_SOME | sum(1 << STAGES.index(s) for s in set(timing))
     o.tau = tau
     o.cost_mode = cost_mode
     o.refresh = refresh

@@ -100,6 +100,16 @@ def test_bad_arguments_fail_before_any_launch(lib):
     st = lib.nanogs_simplify(ctypes.byref(ok), 10, 5, 16, ctypes.byref(o), ctypes.byref(out),
                              ctypes.byref(n_out), None, None, 0, None)
     assert st == 1 and b"options.S" in lib.nanogs_last_error()
+    for bad in (2, 1 << 20, nanogs.TIME_SOME | (1 << nanogs.NTIMED)):
+        lib.nanogs_default_options(ctypes.byref(o))
+        o.timing = bad
+        st = lib.nanogs_simplify(ctypes.byref(ok), 10, 5, 16, ctypes.byref(o), ctypes.byref(out),
+                                 ctypes.byref(n_out), None, None, 0, None)
+        assert st == 1 and b"options.timing" in lib.nanogs_last_error()
+    # the binding's stage selection
+    o = nanogs.options(timing=("knn_query", "cost"))
+    assert o.timing == nanogs.TIME_SOME | (1 << 2) | (1 << 4)
+    assert nanogs.options(timing=True).timing == 1 and nanogs.options().timing == 0
     # workspace too small
     lib.nanogs_default_options(ctypes.byref(o))
     st = lib.nanogs_simplify(ctypes.byref(ok), 10, 5, 16, ctypes.byref(o), ctypes.byref(out),
