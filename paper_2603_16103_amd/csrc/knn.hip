@@ -614,15 +614,23 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
     a = cstart[f];
     b = cstart[f + (1u << sub)];
   };
+  // (the histogram words in chunks of 8 whose loads issue together, no
+  // further chunk once the bin is found)
   auto kth_edge = [&]() {
     int cum = 0, bstar = -1;
 #pragma unroll
-    for (int w = 0; w < kHistWords; ++w) {
-      const unsigned v = hist[w * bs];
-      cum += (int)(v & 0xffffu);
-      if (bstar < 0 && cum >= keff) bstar = 2 * w;
-      cum += (int)(v >> 16);
-      if (bstar < 0 && cum >= keff) bstar = 2 * w + 1;
+    for (int w0 = 0; w0 < kHistWords; w0 += 8) {
+      unsigned v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = hist[(w0 + u) * bs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        cum += (int)(v[u] & 0xffffu);
+        if (bstar < 0 && cum >= keff) bstar = 2 * (w0 + u);
+        cum += (int)(v[u] >> 16);
+        if (bstar < 0 && cum >= keff) bstar = 2 * (w0 + u) + 1;
+      }
+      if (bstar >= 0) break;
     }
     if (bstar < 0 || bstar == 2 * kHistWords - 1 || base + bstar + 1 >= 2040) return INFINITY;
     return __uint_as_float((unsigned)(base + bstar + 1) << 20);
