@@ -406,9 +406,9 @@ NG_DEV unsigned quant(float v, float lo, float sc) {
 //      to a buffer (about keff of them);
 //   C. the buffered rows get the exact key (d2 in double, logical index) and
 //      their rank among the buffered keys.
-// Cells whose box is beyond the current tau are skipped in A and B (their
-// rows fall in bins above tau, so neither tau nor the buffer changes).  The
-// own cell and the six faces come first, so tau is usually known early.
+// Pass A scans every cell of the block; pass B skips the cells whose box is
+// beyond tau (their rows fall in bins above tau, so the buffer does not
+// change).
 // Rows outside the block that may still enter the list lie in the cells of
 // the k-th ball's range [q - r, q + r] outside the block; those are screened
 // in pass B too.  A block over the scan cap, a range too wide or too full,
@@ -665,23 +665,21 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
     // row loads of a batch issue together)
     atomicAdd(&hist[(bin >> 1) * bs], j == p ? 0u : 1u << ((bin & 1) << 4));
   };
-  float tau = INFINITY;
-  for_my_cells(mask, range, [&](int c, int a, int b) {
-    if (c == 0 || tau == INFINITY || !(box_d2(c) > tau * sc2 * kPrune)) {
-      nscreen += b - a;
-      int j = a;
-      for (; j + 4 <= b; j += 4) {
-        const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
-        count(c0, j);
-        count(c1, j + 1);
-        count(c2, j + 2);
-        count(c3, j + 3);
-      }
-      for (; j < b; ++j) count(cen[j], j);
+  // (every cell of the block: a bound read from the histogram after the own
+  // and face cells, to skip the cells beyond it, costs more than it saves)
+  for_my_cells(mask, range, [&](int, int a, int b) {
+    nscreen += b - a;
+    int j = a;
+    for (; j + 4 <= b; j += 4) {
+      const float4 c0 = cen[j], c1 = cen[j + 1], c2 = cen[j + 2], c3 = cen[j + 3];
+      count(c0, j);
+      count(c1, j + 1);
+      count(c2, j + 2);
+      count(c3, j + 3);
     }
-    if (c <= 6) tau = kth_edge();  // after the own cell and each face
+    for (; j < b; ++j) count(cen[j], j);
   });
-  tau = kth_edge();  // (every lane of the query is through pass A here)
+  const float tau = kth_edge();  // (every lane of the query is through pass A here)
 
   // pass B: rows within tau into the buffer, slots from the counter
   const float adm = tau * kScreen;
