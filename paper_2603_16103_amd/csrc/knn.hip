@@ -554,14 +554,15 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
   int L = LT;
   int rows = 0;
   unsigned mask = 0u;
-  for (;; --L) {
-    const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
+  // two levels per step (L and L - 1): their table loads issue together
+  auto level_counts = [&](int Lv, int& rw, unsigned& mk) {
+    const int sl = 10 - Lv, G = 1 << Lv, sub = 3 * (LT - Lv);
     const int cx = (int)(q.qi[0] >> sl), cy = (int)(q.qi[1] >> sl), cz = (int)(q.qi[2] >> sl);
     const Dil3 dx = dil3((unsigned)cx), dy = dil3((unsigned)cy), dz = dil3((unsigned)cz);
-    rows = 0;
-    mask = 0u;
+    int a[(27 + Q - 1) / Q], bb[(27 + Q - 1) / Q];
 #pragma unroll
     for (int i = 0; i < (27 + Q - 1) / Q; ++i) {
+      a[i] = bb[i] = 0;
       const int c = i * Q + r;
       if (c >= 27) continue;
       const int ox = blk(kBlkX, c), oy = blk(kBlkY, c), oz = blk(kBlkZ, c);
@@ -569,13 +570,38 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
       if (x < 0 || x >= G || y < 0 || y >= G || z < 0 || z >= G) continue;
       const unsigned f = ((dil_pick(dx, ox) << 2) | (dil_pick(dy, oy) << 1) | dil_pick(dz, oz))
                          << sub;
-      const int cnt = cstart[f + (1u << sub)] - cstart[f];
-      rows += cnt;
-      if (cnt > 0) mask |= 1u << c;
+      a[i] = cstart[f];
+      bb[i] = cstart[f + (1u << sub)];
     }
-    rows = qsum<Q>(rows);
-    mask = (unsigned)qor64<Q>(mask);
-    if (rows >= bmin || L <= 1) break;
+    rw = 0;
+    mk = 0u;
+#pragma unroll
+    for (int i = 0; i < (27 + Q - 1) / Q; ++i) {
+      const int cnt = bb[i] - a[i];
+      rw += cnt;
+      if (cnt > 0) mk |= 1u << (i * Q + r);
+    }
+  };
+  for (;; L -= 2) {
+    int r0, r1 = 0;
+    unsigned m0, m1 = 0u;
+    level_counts(L, r0, m0);
+    if (L > 1) level_counts(L - 1, r1, m1);
+    r0 = qsum<Q>(r0);
+    m0 = (unsigned)qor64<Q>(m0);
+    if (r0 >= bmin || L <= 1) {
+      rows = r0;
+      mask = m0;
+      break;
+    }
+    r1 = qsum<Q>(r1);
+    m1 = (unsigned)qor64<Q>(m1);
+    if (r1 >= bmin || L - 1 <= 1) {
+      rows = r1;
+      mask = m1;
+      L = L - 1;
+      break;
+    }
   }
   *level = L;
   *screens = 0;
