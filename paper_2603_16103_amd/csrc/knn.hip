@@ -1241,13 +1241,17 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
       // block search: the finest level whose 3x3x3 block holds bmin rows
       int bmin = block_min > keff + 1 ? block_min : keff + 1;
       if (bmin > S.nrows) bmin = S.nrows;
+      // two levels per step: lanes 0..26 look up level L, lanes 32..58
+      // level L - 1 (their loads issue together)
       int L, a = 0, b = 0;
-      for (L = LT;; --L) {
-        const int sl = 10 - L, G = 1 << L, sub = 3 * (LT - L);
-        const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+      const int half = lane >> 5, li = lane & 31;
+      for (L = LT;; L -= 2) {
+        const int Lh = L - half;
         a = b = 0;
-        if (lane < 27) {
-          const int x = cx + blk(kBlkX, lane), y = cy + blk(kBlkY, lane), z = cz + blk(kBlkZ, lane);
+        if (li < 27 && Lh >= 1) {
+          const int sl = 10 - Lh, G = 1 << Lh, sub = 3 * (LT - Lh);
+          const int cx = (int)(qi[0] >> sl), cy = (int)(qi[1] >> sl), cz = (int)(qi[2] >> sl);
+          const int x = cx + blk(kBlkX, li), y = cy + blk(kBlkY, li), z = cz + blk(kBlkZ, li);
           if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
             const unsigned f = ((spread10((unsigned)x) << 2) | (spread10((unsigned)y) << 1) |
                                 spread10((unsigned)z)) << sub;
@@ -1257,8 +1261,17 @@ k_knn_wave(const float4* __restrict__ cen, int n, int k_out, const int* __restri
         }
         int rows = b - a;
 #pragma unroll
-        for (int d = 32; d > 0; d >>= 1) rows += __shfl_xor(rows, d, 64);
-        if (rows >= bmin || L <= 1) break;
+        for (int d = 16; d > 0; d >>= 1) rows += __shfl_xor(rows, d, 64);
+        const int rows0 = __shfl(rows, 0, 64), rows1 = __shfl(rows, 32, 64);
+        if (rows0 >= bmin || L <= 1) {
+          if (half) a = b = 0;  // (the ranges of level L)
+          break;
+        }
+        if (rows1 >= bmin || L - 1 <= 1) {
+          if (!half) a = b = 0;
+          L = L - 1;
+          break;
+        }
       }
       if (lane == 0) s_pref[0] = 0;
       __syncthreads();
