@@ -691,9 +691,28 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
     // row loads of a batch issue together)
     atomicAdd(&hist[(bin >> 1) * bs], j == p ? 0u : 1u << ((bin & 1) << 4));
   };
+  // this lane's cells of the block (every Q-th set bit from its r-th, at
+  // most kMyCells) and their ranges, loaded together and kept for pass B
+  constexpr int kMyCells = (27 + Q - 1) / Q;
+  int my_c[kMyCells], my_a[kMyCells], my_b[kMyCells];
+  {
+    unsigned long long rem = drop_bits(mask, r);
+#pragma unroll
+    for (int i = 0; i < kMyCells; ++i) {
+      my_c[i] = rem ? __ffsll((long long)rem) - 1 : -1;
+      my_a[i] = my_b[i] = 0;
+      if (my_c[i] >= 0) range(my_c[i], my_a[i], my_b[i]);
+      rem = drop_bits(rem, Q);
+    }
+  }
+  auto for_block_cells = [&](auto&& f) {
+#pragma unroll
+    for (int i = 0; i < kMyCells; ++i)
+      if (my_c[i] >= 0) f(my_c[i], my_a[i], my_b[i]);
+  };
   // (every cell of the block: a bound read from the histogram after the own
   // and face cells, to skip the cells beyond it, costs more than it saves)
-  for_my_cells(mask, range, [&](int, int a, int b) {
+  for_block_cells([&](int, int a, int b) {
     nscreen += b - a;
     int j = a;
     for (; j + 4 <= b; j += 4) {
@@ -727,7 +746,7 @@ NG_DEV int block_gather_q(const float4* __restrict__ cen, int p, int n, const Se
     }
     for (; j < b; ++j) keep(cen[j], j);
   };
-  for_my_cells(mask, range, [&](int c, int a, int b) {
+  for_block_cells([&](int c, int a, int b) {
     if (c > 0 && box_d2(c) > tau * sc2 * kPrune) return;
     scan_rows(a, b);
   });
