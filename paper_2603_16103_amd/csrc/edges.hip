@@ -19,11 +19,19 @@ namespace {
 
 NG_DEV int logical(const int* lg, int p) { return lg ? lg[p] : p; }
 
-// thread per directed slot (p, t): 1 if the slot emits an edge
+// thread per directed slot (p, t): 1 if the slot emits an edge.  When k
+// divides 64 a row's slots are k consecutive lanes of one wave (the grid is a
+// multiple of 64), and with cnt given the row's first lane also writes its
+// emitted count and zeroes its incoming counter (what k_edge_count does
+// otherwise).
 __global__ void __launch_bounds__(256)
 k_edge_flags(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int k, int vec4,
-             unsigned char* __restrict__ flag) {
+             unsigned char* __restrict__ flag, int* __restrict__ cnt, int* __restrict__ ideg) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cnt && s == 0) {
+    cnt[n] = 0;  // so the scan's entry n is the total
+    if (ideg) ideg[n] = 0;
+  }
   if (s >= (long long)n * k) return;
   const int p = (int)(s / k);
   const int j = nbr[s];
@@ -47,6 +55,16 @@ k_edge_flags(const int* __restrict__ nbr, const int* __restrict__ lg, int n, int
     }
   }
   flag[s] = emit ? 1 : 0;
+  if (cnt) {  // (64 % k == 0 here)
+    const unsigned long long m = __ballot(emit);
+    const int t = (int)(s - (long long)p * k);
+    if (t == 0) {
+      const int first = lane_id();
+      const unsigned long long row = k == 64 ? ~0ull : (((1ull << k) - 1ull) << first);
+      cnt[p] = __popcll(m & row);
+      if (ideg) ideg[p] = 0;
+    }
+  }
 }
 
 // thread per row: emitted count (the row's flags are contiguous bytes)
@@ -186,11 +204,16 @@ void launch_union_edges(const int* nbr, const int* lg, int n, int k, EdgeSet es,
   const long long slots = (long long)n * k;
   // rows read as int4 when every row start is 16-byte aligned
   const int vec4 = (k % 4 == 0) && ((uintptr_t)nbr % 16 == 0);
-  k_edge_flags<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, lg, n, k, vec4, flag);
-  NG_LAUNCH_CHECK();
-  k_edge_count<<<blocks_for(n + 1, 256), 256, 0, st>>>(flag, n, k, cnt,
+  const bool fused = k > 0 && 64 % k == 0;  // the flags kernel counts the rows
+  k_edge_flags<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, lg, n, k, vec4, flag,
+                                                       fused ? cnt : nullptr,
                                                        es.ioff ? ideg : nullptr);
   NG_LAUNCH_CHECK();
+  if (!fused) {
+    k_edge_count<<<blocks_for(n + 1, 256), 256, 0, st>>>(flag, n, k, cnt,
+                                                         es.ioff ? ideg : nullptr);
+    NG_LAUNCH_CHECK();
+  }
   scan_exclusive_i32(cnt, es.eoff, n + 1, tot, stemp, st);
   k_edge_emit<<<blocks_for(slots, 256), 256, 0, st>>>(nbr, n, k, flag, es.eoff, es.src, es.tgt,
                                                   ideg, es.ioff ? es.islot : nullptr);
