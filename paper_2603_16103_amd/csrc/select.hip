@@ -197,14 +197,17 @@ constexpr int kPickLanes = 4;  // (4 and 8 measured)
 __global__ void __launch_bounds__(256)
 k_ld_pick_first(const int* __restrict__ aoff, const unsigned long long* __restrict__ akey,
                 const int* __restrict__ au, int n, int* __restrict__ pick,
-                unsigned* __restrict__ pcost, int* __restrict__ next_count, PickState ps) {
+                unsigned* __restrict__ pcost, int* __restrict__ counters, int* __restrict__ partner,
+                PickState ps) {
   constexpr int L = kPickLanes;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  // (the matching's counters and partner entries start here: no fills)
+  if (blockIdx.x == 0 && threadIdx.x < 64) counters[threadIdx.x] = 0;
   const int lane = lane_id();
   const int r = lane & (L - 1), gb = lane & ~(L - 1);
   const long long stride = (long long)gridDim.x * blockDim.x / L;
   for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / L; i < n; i += stride) {
     const int v = (int)i;
+    if (r == 0) partner[v] = -1;
     const int t0 = aoff[v], t1 = aoff[v + 1];
     unsigned long long k[kTop];
     int uu[kTop];
@@ -725,14 +728,15 @@ void build_adjacency(const int* ea, const int* eb, const float* cost, long long 
 // halving), at least select_check of them, then one workgroup finishes the
 // remaining ones on the device.  No host round trip happens; the grids of
 // later launches are sized for the expected active count (the kernels stride
-// over the actual one).  counters[2] receives the pairs, counters[3] the
+// over the actual one).  The first pick sets every partner entry to -1 and
+// zeroes counters[0, 64); counters[2] receives the pairs, counters[3] the
 // iterations of the finish.  Returns the grid-wide iterations launched.
 int ld_iterations(const Adjacency& adj, int n, const int* lg, int* partner, int* pick,
                   unsigned* pcost, int* const act[2], int* pair_a, int* pair_b,
                   unsigned* pair_c, int* counters, const PickState& ps, hipStream_t st) {
   int grid_iters = (int)std::ceil(1.2 * std::log2(std::max((double)n, 2.0) / 2048.0));
   grid_iters = std::max(grid_iters, tuning_for(n).select_check);
-  grid_iters = std::min(grid_iters, 24);
+  grid_iters = std::max(std::min(grid_iters, 24), 1);  // (the first one initialises)
   int it = 0;
   double expect = n;
   for (; it < grid_iters; ++it) {
@@ -745,7 +749,8 @@ int ld_iterations(const Adjacency& adj, int n, const int* lg, int* partner, int*
     const unsigned g = grid_for(span);
     if (it == 0)
       k_ld_pick_first<<<grid_for(span * kPickLanes), 256, 0, st>>>(adj.aoff, adj.akey, adj.au, n,
-                                                                   pick, pcost, out_cnt, ps);
+                                                                   pick, pcost, counters, partner,
+                                                                   ps);
     else
       k_ld_pick<<<g, 256, 0, st>>>(adj.aoff, adj.akey, adj.au, partner, in_list, in_cnt, n, pick,
                                    pcost, out_cnt, ps);
@@ -788,8 +793,6 @@ SelectResult select_pairs(const Adjacency& adj, int n, const int* lg, const int*
   void* stemp = (char*)temp + c.bytes();
   long long* host = pinned_host();
 
-  fill_i32(partner, -1, n, st);
-  fill_i32(counters, 0, 64, st);
   SelectResult r{0, 0};
   const int it = ld_iterations(adj, n, lg, partner, pick, pcost, act, pair_a, pair_b, pair_c,
                                counters, ps, st);
@@ -884,8 +887,6 @@ int select_pairs_async(const Adjacency& adj, int n, const int* lg, const int* sg
   ps.tn = c.take<int>(n);
   void* stemp = (char*)temp + c.bytes();
 
-  fill_i32(partner, -1, n, st);
-  fill_i32(counters, 0, 64, st);
   const int it = ld_iterations(adj, n, lg, partner, pick, pcost, act, pair_a, pair_b, pair_c,
                                counters, ps, st);
   const int* idx = nullptr;
