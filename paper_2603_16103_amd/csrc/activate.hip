@@ -88,6 +88,41 @@ __global__ void k_activate_stored(const float* __restrict__ pos, const float* __
   org[p] = i;
 }
 
+// Two-step form: first the rows in input order (coalesced reads), then a
+// gather of the activated rows in the working order (two 16-byte-aligned
+// reads per row instead of four scattered input fields).
+__global__ void k_activate_in(const float* __restrict__ pos, const float* __restrict__ ls,
+                              const float* __restrict__ rot, const float* __restrict__ op, int n,
+                              int lbase, float4* __restrict__ cen_t, float4* __restrict__ shp_t,
+                              int* __restrict__ nonfinite) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long i3 = 3 * (long long)i;
+  const float x = pos[i3], y = pos[i3 + 1], z = pos[i3 + 2];
+  Act a = activate_one(ls + i3, rot + 4 * (long long)i, op[i]);
+  if (!(a.finite && isfinite(x) && isfinite(y) && isfinite(z))) *nonfinite = 1;
+  cen_t[i] = make_float4(x, y, z, __int_as_float(lbase + i));
+  shp_t[2 * (long long)i] = make_float4(a.s0, a.s1, a.s2, a.alpha);
+  shp_t[2 * (long long)i + 1] = make_float4(a.qw, a.qx, a.qy, a.qz);
+}
+
+__global__ void k_gather_act(const int* __restrict__ perm, int n, int lbase,
+                             const float4* __restrict__ cen_t, const float4* __restrict__ shp_t,
+                             float4* __restrict__ cen, int* __restrict__ lg,
+                             float4* __restrict__ shp, int* __restrict__ org,
+                             int* __restrict__ sg, int sgid) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int i = perm[p];
+  const float4 c = cen_t[i], s0 = shp_t[2 * (long long)i], s1 = shp_t[2 * (long long)i + 1];
+  cen[p] = c;
+  shp[2 * (long long)p] = s0;
+  shp[2 * (long long)p + 1] = s1;
+  lg[p] = lbase + i;
+  org[p] = i;
+  if (sg) sg[p] = sgid;
+}
+
 __global__ void k_activate_plain(const float* __restrict__ pos, const float* __restrict__ ls,
                                  const float* __restrict__ rot, const float* __restrict__ op,
                                  int n, float* __restrict__ mu, float* __restrict__ scale,
@@ -230,8 +265,17 @@ __global__ void k_unpack(const float4* __restrict__ cen, const float4* __restric
 void launch_activate_stored(const float* pos, const float* log_scale, const float* rot,
                             const float* opacity, const int* perm, int n, int lbase, float4* cen,
                             int* lg, float4* shp, int* org, int* sg, int sgid, int* nonfinite,
-                            hipStream_t st) {
+                            hipStream_t st, float4* cen_t, float4* shp_t) {
   if (n <= 0) return;
+  if (perm && cen_t && shp_t) {
+    k_activate_in<<<blocks_for(n, 256), 256, 0, st>>>(pos, log_scale, rot, opacity, n, lbase,
+                                                      cen_t, shp_t, nonfinite);
+    NG_LAUNCH_CHECK();
+    k_gather_act<<<blocks_for(n, 256), 256, 0, st>>>(perm, n, lbase, cen_t, shp_t, cen, lg, shp,
+                                                     org, sg, sgid);
+    NG_LAUNCH_CHECK();
+    return;
+  }
   k_activate_stored<<<blocks_for(n, 256), 256, 0, st>>>(pos, log_scale, rot, opacity, perm, n,
                                                         lbase, cen, lg, shp, org, sg, sgid,
                                                         nonfinite);

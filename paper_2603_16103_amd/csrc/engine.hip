@@ -238,7 +238,10 @@ bool Engine::setup_job(Job& j, int pos) {
   const long long r0 = Ntot_;
   launch_activate_stored(j.spec.in.pos, j.spec.in.log_scale, j.spec.in.rot, j.spec.in.opacity,
                          W.perm, (int)n, (int)r0, a.cen + r0, a.lg + r0, a.shp + 2 * r0, a.org + r0,
-                         a.sg + r0, pos, W.counters, st_);
+                         a.sg + r0, pos, W.counters, st_,
+                         // (the other working set is free between passes: its
+                         // first n rows hold the rows in input order)
+                         W.w[cur_ ^ 1].cen, W.w[cur_ ^ 1].shp);
   // the SH rows are checked for non-finite values while they are copied
   launch_copy_sh_rows(j.spec.in.sh, W.perm, a.sh + r0 * NG_SH, nullptr, 0, (int)n, st_,
                       W.counters);

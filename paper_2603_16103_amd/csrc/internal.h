@@ -192,11 +192,13 @@ void sort_pairs_u32(unsigned* keys, int* vals, long long n, int key_bits, void* 
 // activate.hip -- boundary conversions and packing
 // Stored form -> working layout; row p takes input row i = perm[p] (perm
 // nullable: identity), gets logical index lbase + i, provenance i and (sg
-// nullable) segment sgid.
+// nullable) segment sgid.  cen_t / shp_t (nullable, n and 2n rows of
+// scratch): with perm, the rows are activated in input order there first,
+// then gathered.
 void launch_activate_stored(const float* pos, const float* log_scale, const float* rot,
                             const float* opacity, const int* perm, int n, int lbase, float4* cen,
                             int* lg, float4* shp, int* org, int* sg, int sgid, int* nonfinite,
-                            hipStream_t st);
+                            hipStream_t st, float4* cen_t = nullptr, float4* shp_t = nullptr);
 // Checks the SH rows for non-finite values.
 void launch_check_finite(const float* x, long long count, int* nonfinite, hipStream_t st);
 // Row copy of [rows][48] float arrays: dst[dst_row(r)] = src[src_row(r)],
