@@ -169,6 +169,10 @@ size_t scan_temp_bytes(long long n);
 // out[i] = sum_{j<i} in[j]; *total (device, nullable) = sum of all.
 void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* temp,
                         hipStream_t st);
+// Two exclusive scans of n ints each in one pair of launches (out_a of in_a,
+// out_b of in_b; totals nullable); temp of scan_temp_bytes(n).
+void scan_exclusive2_i32(const int* in_a, int* out_a, int* total_a, const int* in_b, int* out_b,
+                         int* total_b, long long n, void* temp, hipStream_t st);
 void fill_i32(int* p, int v, long long n, hipStream_t st);
 // *out = min(max(*d, 0), cap) as int32 (device to device, one thread).
 void count_to_i32(const long long* d, long long cap, int* out, hipStream_t st);

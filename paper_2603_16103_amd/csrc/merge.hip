@@ -339,8 +339,7 @@ long long merge_compact(const float4* cen, const int* lg, const float4* shp, con
   k_keep_flags<<<blocks_for(n, 256), 256, 0, st>>>(partner, lg, n, seg ? sg : nullptr, seg, keep,
                                                    remL);
   NG_LAUNCH_CHECK();
-  scan_exclusive_i32(keep, newpos, n, counters, stemp, st);
-  scan_exclusive_i32(remL, rsum, n, counters + 1, stemp, st);
+  scan_exclusive2_i32(keep, newpos, counters, remL, rsum, counters + 1, n, stemp, st);
   if (trace) fill_i32(counters + 2, 0, 1, st);
   k_out_keys<<<blocks_for(n, 256), 256, 0, st>>>(cen, shp, n, partner, keep, newpos,
                                                  seg ? sg : nullptr, seg, keys, order);

@@ -78,8 +78,14 @@ __device__ int block_sum(int v) {
   return t;
 }
 
+// (blockIdx.y = 1: the second array of a two-array scan, in_b / sums_b)
 __global__ void __launch_bounds__(SCAN_BS)
-k_scan_reduce(const int* __restrict__ in, long long n, int* __restrict__ sums) {
+k_scan_reduce(const int* __restrict__ in, long long n, int* __restrict__ sums,
+              const int* __restrict__ in_b, int* __restrict__ sums_b) {
+  if (blockIdx.y) {
+    in = in_b;
+    sums = sums_b;
+  }
   const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
   int s = 0;
 #pragma unroll
@@ -93,7 +99,14 @@ k_scan_reduce(const int* __restrict__ in, long long n, int* __restrict__ sums) {
 
 __global__ void __launch_bounds__(SCAN_BS)
 k_scan_apply(const int* __restrict__ in, int* __restrict__ out, long long n,
-             const int* __restrict__ sums, int* __restrict__ total) {
+             const int* __restrict__ sums, int* __restrict__ total, const int* __restrict__ in_b,
+             int* __restrict__ out_b, const int* __restrict__ sums_b, int* __restrict__ total_b) {
+  if (blockIdx.y) {
+    in = in_b;
+    out = out_b;
+    sums = sums_b;
+    total = total_b;
+  }
   int pre = 0;
   for (int t = threadIdx.x; t < (int)blockIdx.x; t += SCAN_BS) pre += sums[t];
   pre = block_sum(pre);
@@ -198,9 +211,10 @@ void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* 
   int* offs = c.take<int>(nt);
   void* rest = (char*)temp + c.bytes();
   if (nt <= kScanDirect) {
-    k_scan_reduce<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, n, sums);
+    k_scan_reduce<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, n, sums, nullptr, nullptr);
     NG_LAUNCH_CHECK();
-    k_scan_apply<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, out, n, sums, total);
+    k_scan_apply<<<(unsigned)nt, SCAN_BS, 0, st>>>(in, out, n, sums, total, nullptr, nullptr,
+                                                   nullptr, nullptr);
     NG_LAUNCH_CHECK();
     return;
   }
@@ -208,6 +222,26 @@ void scan_exclusive_i32(const int* in, int* out, long long n, int* total, void* 
   NG_LAUNCH_CHECK();
   scan_exclusive_i32(sums, offs, nt, total, rest, st);
   k_scan_add<<<(unsigned)nt, SCAN_BS, 0, st>>>(out, n, offs);
+  NG_LAUNCH_CHECK();
+}
+
+void scan_exclusive2_i32(const int* in_a, int* out_a, int* total_a, const int* in_b, int* out_b,
+                         int* total_b, long long n, void* temp, hipStream_t st) {
+  const long long nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (n <= SCAN_TILE || nt > kScanDirect) {
+    scan_exclusive_i32(in_a, out_a, n, total_a, temp, st);
+    scan_exclusive_i32(in_b, out_b, n, total_b, temp, st);
+    return;
+  }
+  // the two arrays' tile sums where one scan keeps its sums and offsets
+  Carver c(temp);
+  int* sums_a = c.take<int>(nt);
+  int* sums_b = c.take<int>(nt);
+  const dim3 grid((unsigned)nt, 2);
+  k_scan_reduce<<<grid, SCAN_BS, 0, st>>>(in_a, n, sums_a, in_b, sums_b);
+  NG_LAUNCH_CHECK();
+  k_scan_apply<<<grid, SCAN_BS, 0, st>>>(in_a, out_a, n, sums_a, total_a, in_b, out_b, sums_b,
+                                         total_b);
   NG_LAUNCH_CHECK();
 }
 
